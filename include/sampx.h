@@ -1,0 +1,262 @@
+/*
+ * sampx — biasing-force path of CV-based enhanced sampling on one MI355X.
+ *
+ * C ABI of libsampx.so.  The operations follow Sec. 2 of
+ * "PySAGES: flexible, advanced sampling methods accelerated with GPUs"
+ * (arXiv 2301.04835):
+ *   - a sampling method is split into an initialize step that allocates its
+ *     state and an update step that reads the simulation and updates that
+ *     state (Sec. 2.1, SamplingMethod.build -> initialize / update);
+ *   - the simulation's particle buffers are read in place, without copies
+ *     (Sec. 2, Snapshot and DLPack);
+ *   - the biasing forces are ADDED to the engine's net forces (Sec. 2, the
+ *     force-like callback inserted into the integrator);
+ *   - methods: metadynamics and well-tempered metadynamics (Sec. 2.1.5), the
+ *     adaptive biasing force (Sec. 2.1.4), multiple walkers / replicas
+ *     (Sec. 2, parallel runs; Sec. 4 performance);
+ *   - collective variables: DihedralAngle, RadiusofGyration (Sec. 2.2) and a
+ *     rational-switching coordination number.
+ *
+ * Conventions shared by every call
+ *   Units: nm, rad, kJ/mol, K.
+ *   Pointers named dev_* or documented "device" are HIP device pointers; all
+ *   other pointers are host pointers.  Device pointers are borrowed: the
+ *   library never frees them and never keeps them past the call, except the
+ *   state and workspace buffers handed to sx_bind, which the caller must keep
+ *   alive (and unmoved) until sx_destroy or the next sx_bind.
+ *   Device work is enqueued on the context's stream and is stream-ordered;
+ *   no hot-path call (sx_step, sx_eval_cv, sx_cv_vjp, sx_hillsum,
+ *   sx_graph_launch) synchronises the host or allocates device memory.
+ *   Calls marked "host copy, synchronous" block until their copy is done.
+ *   Errors: every call returns an sx_status; SX_OK is 0.  On error nothing
+ *   has been enqueued and sx_last_error() describes the cause.  No C++
+ *   exception crosses the ABI.  A context is not thread-safe.
+ *
+ * Walkers.  A context advances W walkers (replicas) with the same CV
+ * definitions.  Walker w's atoms are rows [atom_off[w], atom_off[w+1]) of the
+ * position buffer; CV atom indices are relative to that first row.
+ *
+ * Position / force layouts (sx_layout): SX_AOS3 x0 y0 z0 x1 ...; SX_AOS4
+ * x0 y0 z0 w0 x1 ... (the fourth component is ignored and never written);
+ * SX_SOA x0 x1 ... xN-1 y0 ... z0 ... (N = atom_off[W]).  Forces always use
+ * the layout of the positions and are float32.
+ */
+#ifndef SAMPX_H
+#define SAMPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sx_ctx sx_ctx;
+
+typedef enum sx_status {
+    SX_OK = 0,
+    SX_EINVAL = 1,     /* bad argument: index, sigma <= 0, n == m, lo >= hi, ... */
+    SX_ENOMEM = 2,     /* a bound buffer is smaller than the size query said */
+    SX_ECAPACITY = 3,  /* a hill deposition found its walker's list full */
+    SX_ENONFINITE = 4, /* a CV value or bias came out NaN/Inf */
+    SX_EDEVICE = 5,    /* a HIP runtime call failed */
+    SX_ESTATE = 6      /* call out of order (e.g. step before bind) */
+} sx_status;
+
+typedef enum sx_dtype { SX_F32 = 0, SX_F64 = 1 } sx_dtype;
+typedef enum sx_layout { SX_AOS3 = 0, SX_AOS4 = 1, SX_SOA = 2 } sx_layout;
+
+/* Passing this as `step` to sx_step uses the device-held step counter. */
+#define SX_STEP_DEVICE (-1)
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`; `stream` is a hipStream_t (NULL:
+ * the null stream).  The context owns only host memory until sx_bind. */
+sx_status sx_create(sx_ctx **out, int device, void *stream);
+/* Destroy a context (and its captured graph, if any).  NULL is ignored. */
+void sx_destroy(sx_ctx *ctx);
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *sx_last_error(const sx_ctx *ctx);
+/* Static text for a status code. */
+const char *sx_status_string(int status);
+/* Change the stream later work is enqueued on (hipStream_t). */
+sx_status sx_set_stream(sx_ctx *ctx, void *stream);
+
+/* ------------------------------------------------- collective variables */
+/* Each call appends one CV; its index d (0-based, in call order) is the
+ * position of its value in every xi vector.  Host arrays are copied.
+ * Allowed only before sx_bind. */
+
+/* DihedralAngle of atoms idx[0..3] (Sec. 2.2, FourPointCV): with
+ * b1 = r1-r0, b2 = r2-r1, b3 = r3-r2, n1 = b1 x b2, n2 = b2 x b3,
+ * phi = atan2(|b2| b1.n2, n1.n2) in (-pi, pi]; periodic with period 2 pi.
+ * Positions are used as given (molecules unwrapped).  EINVAL: negative index
+ * or repeated atom. */
+sx_status sx_add_cv_dihedral(sx_ctx *ctx, const int32_t idx[4]);
+
+/* RadiusofGyration of atoms idx[0..n) (Sec. 2.2): unweighted,
+ * Rg = sqrt((1/n) sum |r_i - rbar|^2); not periodic; positions as given.
+ * EINVAL: n < 2, negative or repeated index. */
+sx_status sx_add_cv_gyration(sx_ctx *ctx, const int32_t *idx, int32_t n);
+
+/* Coordination number between groups a[0..na) and b[0..nb):
+ * CN = sum_{i in a} sum_{j in b, j != i} s(r_ij), s(r) = (1-(r/r0)^n)/(1-(r/r0)^m),
+ * minimum image in the box of sx_set_box.  rcut > 0 drops pairs at r >= rcut
+ * and evaluates the sum with cell lists (then the box must be set and
+ * every box edge must be >= 3 rcut); rcut <= 0 visits all pairs.
+ * normalize != 0 divides by na.  Not periodic as a CV.  EINVAL: r0 <= 0,
+ * n < 1, m <= n, empty group, negative index. */
+sx_status sx_add_cv_coordination(sx_ctx *ctx, const int32_t *a, int32_t na, const int32_t *b, int32_t nb,
+                                 double r0, int32_t n, int32_t m, double rcut, int32_t normalize);
+
+/* Orthorhombic box edges L[3] (nm) for minimum images; 0 = open in that
+ * direction.  Default: open.  Before sx_bind. */
+sx_status sx_set_box(sx_ctx *ctx, const double L[3]);
+
+/* Number of CVs defined so far (D). */
+int32_t sx_num_cvs(const sx_ctx *ctx);
+
+/* ---------------------------------------------------------------- walkers */
+/* W walkers; atom_off[0..W] (host) gives each walker's rows in the position
+ * buffer (non-decreasing, atom_off[0] may be > 0).  hill_capacity[0..W)
+ * (host, may be NULL) bounds each walker's private hill list (NULL: the
+ * capacity of sx_metad_config for all).  shared_hills != 0 makes all walkers
+ * read and append to ONE hill list of capacity hill_capacity[0] (or the
+ * sx_metad_config capacity); deposits of one step are appended in walker
+ * order.  Default: one walker, atom_off = {0, max CV index + 1}. */
+sx_status sx_set_walkers(sx_ctx *ctx, int32_t n_walkers, const int64_t *atom_off, const int64_t *hill_capacity,
+                         int32_t shared_hills);
+
+/* ---------------------------------------------------------------- methods */
+/* Metadynamics (Sec. 2.1.5).  Bias V(xi) = sum_k h_k exp(-sum_d D_kd^2/(2 sigma_d^2)),
+ * D_kd = xi_d - s_kd taken to the minimum image for periodic CVs.  Every
+ * `stride` steps (step % stride == 0, step 0 included) one hill per walker is
+ * deposited at s = xi(x_t) after the step's forces are computed, with height
+ * w exp(-V_t(s)/(k_B dT)) (well-tempered, Barducci et al. 2008), dT =
+ * (bias_factor - 1) T.  The well-tempered variant is on iff
+ * 1 < bias_factor < inf; bias_factor <= 0 or inf gives plain metadynamics
+ * (constant height w).  sigma: host array of D widths (rad or CV units).
+ * capacity: default hill capacity per walker.  EINVAL: sigma <= 0, w <= 0,
+ * 0 < bias_factor <= 1, T <= 0 with well-tempering, stride < 0,
+ * capacity < 1, D > 3.  Before sx_bind; needs the CVs defined. */
+sx_status sx_metad_config(sx_ctx *ctx, const double *sigma, double w, double temperature, double bias_factor,
+                          int32_t stride, int64_t capacity);
+/* Same with the well-tempering temperature dT given directly (dT <= 0 or
+ * inf: plain metadynamics), as in the butane example of the appendix. */
+sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double delta_T, int32_t stride,
+                             int64_t capacity);
+
+/* Adaptive biasing force (Sec. 2.1.4; Darve et al. 2008).  A grid of
+ * nbins[d] bins on [lo_d, hi_d) per CV (row-major, first CV slowest).  At
+ * every step, with J = dxi/dx and the system force F passed to sx_step:
+ *   theta = -(J J^T)^{-1} J F          (estimate of dA/dxi, unit masses)
+ *   b     = Fsum[k] / max(N[k], n_threshold)    (samples before this step)
+ *   N[k] += 1, Fsum[k] += theta
+ *   forces += sum_d b_d J_d
+ * Periodic CVs (dihedrals) wrap the bin index and need hi - lo = 2 pi; a
+ * non-periodic CV outside [lo, hi) drops the sample and gets no bias.  Each
+ * walker has its own grid.  EINVAL: lo >= hi, nbins < 1, n_threshold < 0,
+ * D > 3.  Before sx_bind.  Exclusive with metadynamics. */
+sx_status sx_abf_config(sx_ctx *ctx, const double *lo, const double *hi, const int32_t *nbins,
+                        int32_t n_threshold);
+
+/* ------------------------------------------------------- memory binding */
+/* Bytes of the persistent state (hills, counts, ABF grid, step counter,
+ * surrogate weights) and of the workspace (per-step scratch plus index
+ * tables).  Valid once CVs, walkers and the method are set. */
+size_t sx_state_bytes(const sx_ctx *ctx);
+size_t sx_workspace_bytes(const sx_ctx *ctx);
+/* Bind caller-owned device buffers (256-byte aligned) of at least the
+ * queried sizes.  Zeroes the state (no hills, empty grid, step counter 0),
+ * uploads the index tables and synchronises the stream.  ENOMEM: a buffer
+ * is too small; EINVAL: misaligned or NULL. */
+sx_status sx_bind(sx_ctx *ctx, void *dev_state, size_t state_bytes, void *dev_ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------- hot path */
+/* One biasing update (the method's update step) for all walkers:
+ *   xi = CVs(pos); bias and dV/dxi (metadynamics: hill sum; ABF: grid);
+ *   forces += -sum_d dV/dxi_d dxi_d/dx; then hill deposition / grid update.
+ * pos: device, dtype/layout as given.  step >= 0: the step number used for
+ * the deposition stride (and the device counter is set to step + 1);
+ * SX_STEP_DEVICE: use and advance the device-held counter.
+ * Outputs (device, may be NULL): xi_out[W][D], V_out[W] (metadynamics bias;
+ * ABF: 0), dVdxi_out[W][D] (ABF: -b, the derivative of the bias potential).
+ * forces: device float32, same layout as pos, ADDED to.  sys_forces: device
+ * float32 system forces, same layout (ABF only; NULL otherwise).
+ * Capacity overflow and non-finite values are flagged on the device and
+ * reported by sx_check. */
+sx_status sx_step(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, int64_t step, double *xi_out,
+                  double *V_out, double *dVdxi_out, float *forces, const float *sys_forces);
+
+/* Synchronise the stream and report device-side flags raised since the last
+ * sx_check (ECAPACITY, ENONFINITE), then clear them. */
+sx_status sx_check(sx_ctx *ctx);
+
+/* ------------------------------------------------------------ pieces */
+/* CV values xi_out[W][D] (device) and, if jac_out != NULL, the sparse
+ * Jacobian jac_out[W][n_slots][3] (device float32): slot s holds
+ * d xi_{cv(s)} / d r_{atom(s)} for one member atom of one CV (see
+ * sx_jac_layout).  The PySAGES counterpart is the JAX gradient of the CVs. */
+sx_status sx_eval_cv(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, double *xi_out, float *jac_out);
+/* Number of Jacobian slots per walker (valid after sx_bind). */
+int64_t sx_jac_slots(const sx_ctx *ctx);
+/* Host copy of the slot layout: atom index (walker-relative) and CV index of
+ * each slot; arrays of sx_jac_slots entries. */
+sx_status sx_jac_layout(const sx_ctx *ctx, int32_t *atom, int32_t *cv);
+/* Vector-Jacobian product (the backward of the CV map):
+ *   pos_bar += sum_d xi_bar[w][d] d xi_d / d r   for every atom of every walker.
+ * The Jacobian is recomputed from pos (gather form, no atomics).  xi_bar:
+ * device double [W][D]; pos_bar: device float32 in the layout of pos. */
+sx_status sx_cv_vjp(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const double *xi_bar,
+                    float *pos_bar);
+/* Metadynamics bias at given CV values: V_out[W], dVdxi_out[W][D] from
+ * xi[W][D] (all device).  No deposition, no forces. */
+sx_status sx_hillsum(sx_ctx *ctx, const double *xi, double *V_out, double *dVdxi_out);
+/* Deposit one hill per walker at xi[W][D] (device) now, whatever the step,
+ * with the well-tempered height from the current bias at xi. */
+sx_status sx_deposit(sx_ctx *ctx, const double *xi);
+
+/* ------------------------------------------------------------ state I/O */
+/* Host copies, synchronous.  Walker -1 (or any walker) addresses the shared
+ * list when hills are shared.  centers: K x D row-major float32. */
+sx_status sx_hills_set(sx_ctx *ctx, int32_t walker, const float *centers, const float *heights, int64_t K);
+sx_status sx_hills_get(sx_ctx *ctx, int32_t walker, float *centers, float *heights, int64_t max_K, int64_t *K);
+/* ABF grid of walker w: N[nbins_total] counts and Fsum[nbins_total][D]. */
+sx_status sx_abf_grid_get(sx_ctx *ctx, int32_t walker, uint32_t *N, double *Fsum);
+/* Device step counter (the next step number SX_STEP_DEVICE will use). */
+sx_status sx_get_step(sx_ctx *ctx, int64_t *step);
+/* Checkpoint: the whole state buffer with a header that identifies the
+ * configuration; import refuses a checkpoint of another configuration. */
+size_t sx_checkpoint_bytes(const sx_ctx *ctx);
+sx_status sx_state_export(sx_ctx *ctx, void *host, size_t bytes);
+sx_status sx_state_import(sx_ctx *ctx, const void *host, size_t bytes);
+
+/* ------------------------------------------------- graphs and tuning */
+/* Capture n_steps consecutive sx_step calls (device step counter) with the
+ * given buffers into one HIP graph owned by the context; sx_graph_launch
+ * replays it on the context's stream.  Buffers must stay valid while the
+ * graph exists.  A new capture replaces the previous graph. */
+sx_status sx_graph_capture(sx_ctx *ctx, int32_t n_steps, const void *pos, int32_t dtype, int32_t layout,
+                           double *xi_out, double *V_out, double *dVdxi_out, float *forces,
+                           const float *sys_forces);
+sx_status sx_graph_launch(sx_ctx *ctx);
+/* Launch parameters of the hill-sum kernel: hills per tile (multiple of
+ * 1024, at most 16384) and persistent grid size (0: one workgroup per
+ * tile).  Changing the tile rebuilds the tile table (host, synchronous). */
+sx_status sx_set_tuning(sx_ctx *ctx, int32_t tile_hills, int32_t grid);
+sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
+/* Time candidate tilings of the step's hill-sum kernels on the bound state
+ * and keep the fastest.  pos (device, may be NULL): positions in the form
+ * sx_step receives them, so that the CVs the hill kernels evaluate
+ * themselves (all-dihedral sets) are timed as in the step; with NULL the
+ * CV values of the last step are used.  Nothing is deposited and no force
+ * is written.  cache_path (may be NULL): a JSON file of earlier choices
+ * keyed by the problem shape; read first, updated after a search.  Uses
+ * hipEvents; synchronous. */
+sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const char *cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAMPX_H */

@@ -1,0 +1,490 @@
+// Bias kernels: the metadynamics hill sum with well-tempered deposition
+// (Sec. 2.1.5), the adaptive-biasing-force grid (Sec. 2.1.4), and the
+// atomic-free force gather that adds the bias to the engine's forces (Sec. 2).
+//
+// Hill sum over private hill lists (one list per walker), two kernels:
+//   A  k_hill_tiles: a static table of tiles (walker, first hill), each
+//      1024 * U hills of one walker's capacity.  Hills are stored SoA in
+//      float32 (centres c[d][k], heights h[k]); every lane issues its float4
+//      loads of a batch of 4 groups before using any of them (clamped to the
+//      walker's padded capacity and masked by its count, so no branch sits
+//      between the loads), which keeps enough bytes in flight to stream HBM.
+//      When every CV is a dihedral the tile's workgroup computes its
+//      walker's xi itself (FP64) while its hill loads are in flight, so no
+//      separate CV kernel runs.  The displacement and its periodic wrap are
+//      formed in FP64 (the same VALU rate as FP32 on CDNA4 without packed
+//      math), the Gaussian in FP32 with the hardware exp2, the sums in FP64
+//      per group of 4 hills.  Each tile writes its partial (V, sum e D_d) to
+//      its own record.
+//   B  k_hill_finalize: one workgroup per walker reduces that walker's tile
+//      records in tile order (bitwise deterministic whatever the schedule),
+//      forms dV/dxi, writes the outputs, deposits the well-tempered hill and
+//      gathers the force onto the walker's atoms.  The kernel boundary is the
+//      only cross-workgroup synchronisation: no fences, no atomics.
+#include "dev_cv.h"
+
+namespace sx {
+namespace {
+
+template <int N>
+__device__ __forceinline__ void block_sum0(double (&v)[N], double *lds /* N * kBlock/64 */)
+{
+    // fixed tree: wave butterfly, then waves in index order; result in thread 0
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) lds[wv * N + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double s = lds[k];
+            for (int q = 1; q < kBlock / 64; ++q) s += lds[q * N + k];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Gaussian term of one hill: returns h exp(-sum_d D_d^2/(2 sigma_d^2)) and
+// the wrapped displacements D_d (float).  The difference xi - c and its
+// minimum image are formed in FP64 so that D_d carries only the final
+// rounding to float.
+template <int D>
+__device__ __forceinline__ float hill_term(const double (&xi)[D], const float (&c)[D], float h, const HillArgs &a,
+                                           float (&dl)[D])
+{
+    float q = 0.f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double x = xi[d] - (double)c[d];
+        x = fma(-a.period[d], rint(x * a.inv_period[d]), x);
+        dl[d] = (float)x;
+        q = fmaf(dl[d] * a.a2[d], dl[d], q);
+    }
+    return h * __builtin_amdgcn_exp2f(-q);
+}
+
+__device__ __forceinline__ float comp(const float4 &v, int i)
+{
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+// Gather of a bias force onto walker w's touched atoms:
+//   F_i += sum_{slots s of atom i} coef[cv(s)] * Jw[s]
+// Jw: the walker's Jacobian slots (s x 3 floats).
+__device__ __forceinline__ void gather_forces(const WalkerTabs &t, const float *Jw, int32_t w, const double *coef,
+                                              const ForceView &F)
+{
+    const int64_t ab = t.atom_off[w];
+    for (int u = threadIdx.x; u < t.U; u += blockDim.x) {
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
+            const int32_t s = t.inv_slot[q];
+            const double cf = coef[t.slot_cv[s]];
+            const float *js = Jw + (int64_t)s * 3;
+            fx += cf * (double)js[0];
+            fy += cf * (double)js[1];
+            fz += cf * (double)js[2];
+        }
+        float *f = F.ptr + (ab + t.touched[u]) * F.sa;
+        f[0] += (float)fx;
+        f[F.sk] += (float)fy;
+        f[2 * F.sk] += (float)fz;
+    }
+}
+
+constexpr int kBatch = 4;  // float4 groups loaded per lane before use
+
+template <int D, int U, bool FUSE>
+__global__ void __launch_bounds__(kBlock) k_hill_tiles(HillArgs a, CvSet cs, PosView pos)
+{
+    __shared__ double lds[(1 + D) * (kBlock / 64)];
+    __shared__ double s_xi[D];
+    constexpr int UB = U < kBatch ? U : kBatch;
+    if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const TileRec tr = a.tiles[t];
+        const int32_t w = tr.w, h0 = tr.h0, klast = tr.klast;
+        const int64_t hb = (int64_t)tr.hb4 * 4;
+        const int32_t n = a.count[w];
+        double xi[D];
+        double acc[1 + D];
+#pragma unroll
+        for (int j = 0; j <= D; ++j) acc[j] = 0.0;
+#pragma unroll
+        for (int ub = 0; ub < U; ub += UB) {
+            float4 cv[UB][D], hv[UB];
+#pragma unroll
+            for (int q = 0; q < UB; ++q) {
+                const int32_t k = min(h0 + ((ub + q) * kBlock + (int)threadIdx.x) * kHillsPerLoad, klast);
+#pragma unroll
+                for (int d = 0; d < D; ++d) cv[q][d] = *reinterpret_cast<const float4 *>(a.c[d] + hb + k);
+                hv[q] = *reinterpret_cast<const float4 *>(a.h + hb + k);
+            }
+            if (ub == 0) {
+                if (FUSE) {
+                    if ((int)threadIdx.x < D) s_xi[threadIdx.x] = dihedral_at(cs.cv[threadIdx.x], pos, tr.aoff, nullptr);
+                    __syncthreads();
+#pragma unroll
+                    for (int d = 0; d < D; ++d) xi[d] = s_xi[d];
+                } else {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) xi[d] = a.xi[(int64_t)w * D + d];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < UB; ++q) {
+                const int32_t k = h0 + ((ub + q) * kBlock + (int)threadIdx.x) * kHillsPerLoad;
+                float sv = 0.f, sg[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) sg[d] = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float c[D], dl[D];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) c[d] = comp(cv[q][d], i);
+                    float e = hill_term<D>(xi, c, comp(hv[q], i), a, dl);
+                    e = (k + i < n) ? e : 0.f;
+                    sv += e;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) sg[d] = fmaf(e, dl[d], sg[d]);
+                }
+                acc[0] += (double)sv;
+#pragma unroll
+                for (int d = 0; d < D; ++d) acc[1 + d] += (double)sg[d];
+            }
+        }
+        block_sum0<1 + D>(acc, lds);
+        if (threadIdx.x == 0) {
+            double *p = a.partial + (int64_t)t * 4;
+#pragma unroll
+            for (int j = 0; j <= D; ++j) p[j] = acc[j];
+        }
+    }
+}
+
+// Force gather from the small table (kernel arguments): lane u < U owns
+// touched atom u.  Its current force is read before the bias is known so
+// that the load overlaps the partial reduction.
+struct SmallGather {
+    float f0, f1, f2;
+    float *dst;
+};
+
+template <int D, bool FUSE>
+__global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, PosView pos)
+{
+    __shared__ double lds[(1 + D) * (kBlock / 64)];
+    __shared__ double s_coef[kMaxCv];
+    __shared__ double s_xi[kMaxBiasDim];
+    __shared__ float s_J[kMaxBiasDim * 4 * 3];
+    const int32_t w = blockIdx.x;
+    const WalkerRec wr = a.wrec[w];
+    // small gather table: prefetch the forces this lane will update
+    SmallGather sg{0.f, 0.f, 0.f, nullptr};
+    const bool small_lane = a.do_forces && a.small.on && (int)threadIdx.x < a.small.U;
+    if (small_lane) {
+        sg.dst = a.F.ptr + (wr.aoff + a.small.touched[threadIdx.x]) * a.F.sa;
+        sg.f0 = sg.dst[0];
+        sg.f1 = sg.dst[a.F.sk];
+        sg.f2 = sg.dst[2 * a.F.sk];
+    }
+    if ((int)threadIdx.x < D) {
+        if (FUSE) {
+            double3 g[4];
+            const CvDesc &cv = cs.cv[threadIdx.x];
+            s_xi[threadIdx.x] = dihedral_at(cv, pos, wr.aoff, a.do_forces ? g : nullptr);
+            if (a.do_forces)
+                for (int q = 0; q < 4; ++q) {
+                    s_J[(cv.slot0 + q) * 3 + 0] = (float)g[q].x;
+                    s_J[(cv.slot0 + q) * 3 + 1] = (float)g[q].y;
+                    s_J[(cv.slot0 + q) * 3 + 2] = (float)g[q].z;
+                }
+        } else {
+            s_xi[threadIdx.x] = a.xi[(int64_t)w * D + threadIdx.x];
+        }
+    }
+    double acc[1 + D];
+#pragma unroll
+    for (int j = 0; j <= D; ++j) acc[j] = 0.0;
+    for (int i = threadIdx.x; i < wr.nt; i += kBlock) {
+        const double *p = a.partial + (int64_t)(wr.t0 + i) * 4;
+#pragma unroll
+        for (int j = 0; j <= D; ++j) acc[j] += p[j];
+    }
+    block_sum0<1 + D>(acc, lds);  // also orders the s_xi / s_J writes
+    if (threadIdx.x == 0) {
+        const double V = acc[0];
+        bool finite = isfinite(V);
+        a.V_ws[w] = V;
+        if (a.V_out) a.V_out[w] = V;
+        if (a.xi_out)
+#pragma unroll
+            for (int d = 0; d < D; ++d) a.xi_out[(int64_t)w * D + d] = s_xi[d];
+        if (FUSE && a.xi_save)
+#pragma unroll
+            for (int d = 0; d < D; ++d) a.xi_save[(int64_t)w * D + d] = s_xi[d];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const double dv = -acc[1 + d] * a.inv_sig2[d];
+            finite = finite && isfinite(dv);
+            a.dV_ws[(int64_t)w * D + d] = dv;
+            if (a.dV_out) a.dV_out[(int64_t)w * D + d] = dv;
+            s_coef[d] = -dv;
+        }
+        if (!finite) atomicOr(a.flags, kFlagNonFinite);
+        bool dep = a.deposit == 2;
+        if (a.deposit == 1 && a.stride > 0) dep = (*a.dstep - 1) % a.stride == 0;  // kernel A set the counter
+        if (dep) {
+            const int32_t cnt = a.count[w];
+            if (cnt < wr.cap) {
+                const int64_t k = (int64_t)wr.hb4 * 4 + cnt;
+#pragma unroll
+                for (int d = 0; d < D; ++d) a.c[d][k] = (float)s_xi[d];
+                a.h[k] = (float)(a.inv_kdT > 0.0 ? a.height * exp(-V * a.inv_kdT) : a.height);
+                a.count[w] = cnt + 1;
+            } else {
+                atomicOr(a.flags, kFlagCapacity);
+            }
+        }
+    }
+    __syncthreads();
+    if (!a.do_forces) return;
+    const float *Jw = FUSE ? s_J : a.J + (int64_t)w * a.nslots * 3;
+    if (a.small.on) {
+        if (small_lane) {
+            double fx = 0.0, fy = 0.0, fz = 0.0;
+            for (int q = 0; q < a.small.nent[threadIdx.x]; ++q) {
+                const int32_t e = a.small.ent[threadIdx.x][q];
+                const int32_t slot = e & 0xFFFFF, cvi = e >> 20;
+                const double cf = s_coef[cvi];
+                fx += cf * (double)Jw[slot * 3 + 0];
+                fy += cf * (double)Jw[slot * 3 + 1];
+                fz += cf * (double)Jw[slot * 3 + 2];
+            }
+            sg.dst[0] = sg.f0 + (float)fx;
+            sg.dst[a.F.sk] = sg.f1 + (float)fy;
+            sg.dst[2 * a.F.sk] = sg.f2 + (float)fz;
+        }
+    } else {
+        gather_forces(a.tabs, Jw, w, s_coef, a.F);
+    }
+}
+
+template <int D, bool FUSE>
+hipError_t launch_hill_d(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s)
+{
+    const int g = (grid > 0 && grid < a.ntiles) ? grid : a.ntiles;
+    switch (a.tile_units) {
+    case 1: hipLaunchKernelGGL((k_hill_tiles<D, 1, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
+    case 2: hipLaunchKernelGGL((k_hill_tiles<D, 2, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
+    case 4: hipLaunchKernelGGL((k_hill_tiles<D, 4, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
+    case 8: hipLaunchKernelGGL((k_hill_tiles<D, 8, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
+    case 16: hipLaunchKernelGGL((k_hill_tiles<D, 16, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_hill_finalize<D, FUSE>), dim3(a.tabs.W), dim3(kBlock), 0, s, a, cs, pos);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_hill_dd(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s)
+{
+    return a.fuse ? launch_hill_d<D, true>(a, cs, pos, grid, s) : launch_hill_d<D, false>(a, cs, pos, grid, s);
+}
+
+// ----------------------------------------------------------------- ABF grid
+// One workgroup per walker.  theta = -(J J^T)^{-1} J F from the per-atom
+// Jacobian rows (slots of one atom and one CV summed), FP64 reductions.
+__global__ void __launch_bounds__(kBlock) k_abf(AbfArgs a)
+{
+    constexpr int MD = kMaxBiasDim;
+    __shared__ double lds[(MD * MD + MD) * (kBlock / 64)];
+    __shared__ double s_coef[kMaxCv];
+    const int32_t w = blockIdx.x;
+    const int D = a.D;
+    const WalkerTabs &t = a.tabs;
+    const int64_t jb = (int64_t)w * a.nslots, ab = t.atom_off[w];
+    double acc[MD * MD + MD];
+#pragma unroll
+    for (int j = 0; j < MD * MD + MD; ++j) acc[j] = 0.0;
+    for (int u = threadIdx.x; u < t.U; u += blockDim.x) {
+        double jv[MD][3];
+#pragma unroll
+        for (int d = 0; d < MD; ++d) jv[d][0] = jv[d][1] = jv[d][2] = 0.0;
+        for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
+            const int32_t s = t.inv_slot[q];
+            const int d = t.slot_cv[s];
+            const float *js = a.J + (jb + s) * 3;
+#pragma unroll
+            for (int dd = 0; dd < MD; ++dd)
+                if (dd == d) {
+                    jv[dd][0] += js[0];
+                    jv[dd][1] += js[1];
+                    jv[dd][2] += js[2];
+                }
+        }
+        const float *fp = static_cast<const float *>(a.Fsys.ptr) + (ab + t.touched[u]) * a.Fsys.sa;
+        const double f[3] = {fp[0], fp[a.Fsys.sk], fp[2 * a.Fsys.sk]};
+#pragma unroll
+        for (int d = 0; d < MD; ++d) {
+#pragma unroll
+            for (int e = 0; e < MD; ++e)
+                acc[d * MD + e] += jv[d][0] * jv[e][0] + jv[d][1] * jv[e][1] + jv[d][2] * jv[e][2];
+            acc[MD * MD + d] += jv[d][0] * f[0] + jv[d][1] * f[1] + jv[d][2] * f[2];
+        }
+    }
+    block_sum0<MD * MD + MD>(acc, lds);
+    if (threadIdx.x == 0) {
+        // solve G theta = -JF by Gaussian elimination with partial pivoting
+        double G[MD][MD + 1];
+        for (int d = 0; d < D; ++d) {
+            for (int e = 0; e < D; ++e) G[d][e] = acc[d * MD + e];
+            G[d][D] = -acc[MD * MD + d];
+        }
+        for (int col = 0; col < D; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < D; ++r)
+                if (fabs(G[r][col]) > fabs(G[piv][col])) piv = r;
+            if (piv != col)
+                for (int e = 0; e <= D; ++e) {
+                    double tmp = G[col][e];
+                    G[col][e] = G[piv][e];
+                    G[piv][e] = tmp;
+                }
+            for (int r = col + 1; r < D; ++r) {
+                const double fct = G[r][col] / G[col][col];
+                for (int e = col; e <= D; ++e) G[r][e] -= fct * G[col][e];
+            }
+        }
+        double theta[MD];
+        for (int d = D - 1; d >= 0; --d) {
+            double s = G[d][D];
+            for (int e = d + 1; e < D; ++e) s -= G[d][e] * theta[e];
+            theta[d] = s / G[d][d];
+        }
+        // bin of xi (row-major, first CV slowest)
+        int64_t k = 0;
+        bool inr = true;
+        for (int d = 0; d < D; ++d) {
+            const double x = a.xi[(int64_t)w * D + d];
+            int64_t i = (int64_t)floor((x - a.lo[d]) / a.delta[d]);
+            if (a.periodic[d]) {
+                i %= a.nbins[d];
+                if (i < 0) i += a.nbins[d];
+            } else if (i < 0 || i >= a.nbins[d]) {
+                inr = false;
+            }
+            k = k * a.nbins[d] + i;
+        }
+        bool finite = true;
+        for (int d = 0; d < D; ++d) finite = finite && isfinite(theta[d]);
+        if (!finite) atomicOr(a.flags, kFlagNonFinite);
+        double b[MD] = {0.0, 0.0, 0.0};
+        if (inr && finite) {
+            uint32_t *Nk = a.N + (int64_t)w * a.nbins_total + k;
+            double *Fk = a.Fsum + ((int64_t)w * a.nbins_total + k) * D;
+            const uint32_t cnt = *Nk;
+            const double den = (double)max((int64_t)cnt, (int64_t)a.n_threshold);
+            for (int d = 0; d < D; ++d) b[d] = den > 0.0 ? Fk[d] / den : 0.0;
+            *Nk = cnt + 1u;
+            for (int d = 0; d < D; ++d) Fk[d] += theta[d];
+        }
+        for (int d = 0; d < D; ++d) {
+            s_coef[d] = b[d];
+            if (a.dV_out) a.dV_out[(int64_t)w * D + d] = -b[d];
+            if (a.xi_out) a.xi_out[(int64_t)w * D + d] = a.xi[(int64_t)w * D + d];
+        }
+        if (a.V_out) a.V_out[w] = 0.0;
+        if (w == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
+    }
+    __syncthreads();
+    gather_forces(t, a.J + jb * 3, w, s_coef, a.F);
+}
+
+// One lane per (walker, touched atom): out += sign * sum_s coef[w][cv(s)] J_s.
+__global__ void __launch_bounds__(kBlock) k_gather(WalkerTabs t, const float *J, int32_t nslots, int32_t D,
+                                                    const double *coef, double sign, ForceView out)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)t.W * t.U) return;
+    const int32_t w = (int32_t)(gid / t.U), u = (int32_t)(gid % t.U);
+    const int64_t jb = (int64_t)w * nslots;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
+        const int32_t s = t.inv_slot[q];
+        const double cf = sign * coef[(int64_t)w * D + t.slot_cv[s]];
+        const float *js = J + (jb + s) * 3;
+        fx += cf * (double)js[0];
+        fy += cf * (double)js[1];
+        fz += cf * (double)js[2];
+    }
+    float *f = out.ptr + (t.atom_off[w] + t.touched[u]) * out.sa;
+    f[0] += (float)fx;
+    f[out.sk] += (float)fy;
+    f[2 * out.sk] += (float)fz;
+}
+
+__global__ void k_copy_f64(const double *src, double *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_zero_u32(uint32_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s)
+{
+    switch (a.D) {
+    case 1: return launch_hill_dd<1>(a, cs, pos, grid, s);
+    case 2: return launch_hill_dd<2>(a, cs, pos, grid, s);
+    case 3: return launch_hill_dd<3>(a, cs, pos, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_abf(const AbfArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_abf, dim3(a.tabs.W), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const WalkerTabs &t, const float *J, int32_t nslots, int32_t D, const double *coef,
+                         double coef_sign, ForceView out, hipStream_t s)
+{
+    const int64_t n = (int64_t)t.W * t.U;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, t, J, nslots, D,
+                       coef, coef_sign, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_xi(const double *src, double *dst, int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_bytes(void *p, int64_t nbytes, hipStream_t s)
+{
+    const int64_t n = nbytes / 4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       static_cast<uint32_t *>(p), n);
+    return hipGetLastError();
+}
+
+}  // namespace sx

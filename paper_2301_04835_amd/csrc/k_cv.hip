@@ -1,0 +1,310 @@
+// Collective-variable kernels: values xi and the sparse Jacobian dxi/dx
+// (PySAGES obtains the Jacobian by automatic differentiation of the CV
+// function, Sec. 2 and Sec. 2.2; here each CV has its analytic gradient).
+//
+//  * dihedral angle: one lane per (walker, dihedral), FP64 arithmetic;
+//  * radius of gyration: one workgroup per (walker, CV), two passes in FP64;
+//  * coordination number, all pairs: a 3-D grid of (partner chunk, my-atom
+//    tile) x side (A or B) x (walker, CV).  Each lane owns one atom of its
+//    side and gathers over one chunk of the other group staged in LDS, so
+//    every partial sum has exactly one writer (no atomics); a finalize
+//    kernel reduces the chunks in a fixed order (bitwise deterministic).
+#include "dev_cv.h"
+
+namespace sx {
+namespace {
+
+__device__ __forceinline__ void st_slot(float *J, int64_t slot, double3 g)
+{
+    J[slot * 3 + 0] = (float)g.x;
+    J[slot * 3 + 1] = (float)g.y;
+    J[slot * 3 + 2] = (float)g.z;
+}
+
+// ------------------------------------------------------------------ dihedral
+// One lane per (walker, dihedral CV), FP64 (see dihedral_fp64).
+__global__ void __launch_bounds__(kBlock) k_dihedral(CvSet cs, WalkerTabs t, PosView pos, double *xi, float *J,
+                                                     int32_t ndih)
+{
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)t.W * ndih) return;
+    int32_t w = (int32_t)(gid / ndih), j = (int32_t)(gid % ndih);
+    int c = 0, seen = 0;
+    for (; c < cs.ncv; ++c)
+        if (cs.cv[c].kind == CV_DIHEDRAL && seen++ == j) break;
+    const CvDesc cv = cs.cv[c];
+    double3 g[4];
+    const double phi = dihedral_at(cv, pos, t.atom_off[w], J ? g : nullptr);
+    xi[(int64_t)w * cs.D + cv.d] = phi;
+    if (J) {
+        const int64_t sb = (int64_t)w * cs.nslots + cv.slot0;
+        for (int q = 0; q < 4; ++q) st_slot(J, sb + q, g[q]);
+    }
+}
+
+// ----------------------------------------------------- block reductions (FP64)
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double *lds /* N * kBlock/64 */)
+{
+    // fixed reduction tree: wave butterfly, then the waves in index order
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) lds[wv * N + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < N; ++k) {
+            double s = lds[k];
+            for (int q = 1; q < nw; ++q) s += lds[q * N + k];
+            lds[k] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = lds[k];
+    __syncthreads();
+}
+
+// ------------------------------------------------------- radius of gyration
+// Rg = sqrt((1/n) sum |r_i - c|^2), c = (1/n) sum r_i; dRg/dr_i = (r_i - c)/(n Rg).
+__global__ void __launch_bounds__(kBlock) k_gyration(CvSet cs, WalkerTabs t, PosView pos, double *xi, float *J)
+{
+    __shared__ double lds[4 * (kBlock / 64)];
+    const int32_t w = blockIdx.y;
+    int c = 0, seen = 0;
+    for (; c < cs.ncv; ++c)
+        if (cs.cv[c].kind == CV_GYRATION && seen++ == (int)blockIdx.x) break;
+    const CvDesc cv = cs.cv[c];
+    const int64_t base = t.atom_off[w];
+    const int n = cv.na;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double3 r = ld_pos(pos, base + t.slot_atom[cv.slot0 + i]);
+        s[0] += r.x;
+        s[1] += r.y;
+        s[2] += r.z;
+    }
+    block_sum<3>(s, lds);
+    const double3 cen = make_double3(s[0] / n, s[1] / n, s[2] / n);
+    double q[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double3 d = d3sub(ld_pos(pos, base + t.slot_atom[cv.slot0 + i]), cen);
+        q[0] += d3dot(d, d);
+    }
+    block_sum<1>(q, lds);
+    const double rg = sqrt(q[0] / n);
+    if (threadIdx.x == 0) xi[(int64_t)w * cs.D + cv.d] = rg;
+    if (J) {
+        const double inv = 1.0 / ((double)n * rg);
+        const int64_t sb = (int64_t)w * cs.nslots + cv.slot0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double3 d = d3sub(ld_pos(pos, base + t.slot_atom[cv.slot0 + i]), cen);
+            st_slot(J, sb + i, d3scale(d, inv));
+        }
+    }
+}
+
+// ---------------------------------------------- coordination number, all pairs
+// Rational switch s = (1 - x^n)/(1 - x^m), x = r/r0, and f = (1/r) ds/dr.
+// (6, 12): s = 1/(1 + x^6) and f = -6 x^4 s^2 / r0^2, both from r^2 alone.
+// Other (n, m): s = P_n(x)/P_m(x) with P_k(x) = 1 + x + ... + x^(k-1), the
+// same rational function with the factor (1 - x) cancelled, which stays
+// exact around x = 1 where the plain quotient loses all its digits.
+__device__ __forceinline__ void switch_fn(float r2, const CvDesc &c, float &s, float &f)
+{
+    if (c.n == 6 && c.m == 12) {
+        float x2 = r2 * (c.inv_r0 * c.inv_r0);
+        float x4 = x2 * x2;
+        float sv = __builtin_amdgcn_rcpf(1.0f + x4 * x2);
+        s = sv;
+        f = -6.0f * x4 * sv * sv * (c.inv_r0 * c.inv_r0);
+        return;
+    }
+    float r = sqrtf(r2), x = r * c.inv_r0;
+    float pn = 0.f, dpn = 0.f, pm = 0.f, dpm = 0.f;
+    for (int i = c.n - 1; i >= 0; --i) {  // Horner: P and P'
+        dpn = fmaf(dpn, x, pn);
+        pn = fmaf(pn, x, 1.0f);
+    }
+    for (int i = c.m - 1; i >= 0; --i) {
+        dpm = fmaf(dpm, x, pm);
+        pm = fmaf(pm, x, 1.0f);
+    }
+    float ipm = __builtin_amdgcn_rcpf(pm);
+    s = pn * ipm;
+    float dsdx = (dpn * pm - pn * dpm) * ipm * ipm;
+    f = r > 0.f ? dsdx * c.inv_r0 / r : 0.f;
+}
+
+struct CnPart {  // one partial record: switch sum and gradient sum
+    double s, gx, gy, gz;
+};
+
+struct Partner {  // a partner atom staged in LDS
+    double x, y, z;
+    int32_t idx, pad;
+};
+
+template <typename T>
+__device__ __forceinline__ double3 ld_d3(const PosView &p, int64_t i)
+{
+    const T *q = static_cast<const T *>(p.ptr) + i * p.sa;
+    return make_double3((double)q[0], (double)q[p.sk], (double)q[2 * p.sk]);
+}
+
+// minimum-image component in FP64, rounded once to float
+__device__ __forceinline__ float min_img(double d, double L, double iL) { return (float)fma(-L, rint(d * iL), d); }
+
+// grid: x = my-atom tile * nchunk + chunk, y = side (0: A gathers over B,
+// 1: B gathers over A), z = walker * ncoord + k (k-th coordination CV).
+// The pair difference and its minimum image are taken in FP64 (exact for
+// float inputs up to the final rounding), the switching function in FP32,
+// the sums in FP64 per group of 8 partners.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_coord_pairs(CvSet cs, WalkerTabs t, PosView pos, CnPart *part,
+                                                         int32_t ncoord)
+{
+    __shared__ Partner oth[kBlock];
+    const int32_t w = blockIdx.z / ncoord, k = blockIdx.z % ncoord;
+    int c = 0, seen = 0;
+    for (; c < cs.ncv; ++c)
+        if (cs.cv[c].kind == CV_COORD && seen++ == k) break;
+    const CvDesc cv = cs.cv[c];
+    const int side = blockIdx.y;
+    const int nmine = side ? cv.nb : cv.na, noth = side ? cv.na : cv.nb;
+    const int mine0 = cv.slot0 + (side ? cv.na : 0), oth0 = cv.slot0 + (side ? 0 : cv.na);
+    const int nchunk = side ? cv.nchunk_b : cv.nchunk_a;
+    const int tile = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
+    if (tile * kBlock >= nmine) return;  // whole workgroup idle: uniform exit
+    const int64_t base = t.atom_off[w];
+    const double L[3] = {cs.box[0], cs.box[1], cs.box[2]};
+    const double iL[3] = {cs.inv_box[0], cs.inv_box[1], cs.inv_box[2]};
+    // stage the partner chunk
+    const int j0 = chunk * cv.chunk, jn = min(cv.chunk, noth - j0);
+    for (int j = threadIdx.x; j < jn; j += blockDim.x) {
+        int32_t a = t.slot_atom[oth0 + j0 + j];
+        double3 r = ld_d3<T>(pos, base + a);
+        oth[j] = Partner{r.x, r.y, r.z, a, 0};
+    }
+    __syncthreads();
+    const int i = tile * kBlock + threadIdx.x;
+    if (i >= nmine) return;
+    const int32_t me = t.slot_atom[mine0 + i];
+    const double3 ri = ld_d3<T>(pos, base + me);
+    double S = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int j = 0; j < jn; j += 8) {
+        float s8 = 0.f, x8 = 0.f, y8 = 0.f, z8 = 0.f;
+        const int je = min(jn, j + 8);
+        for (int q = j; q < je; ++q) {
+            const Partner o = oth[q];
+            float dx = min_img(ri.x - o.x, L[0], iL[0]);
+            float dy = min_img(ri.y - o.y, L[1], iL[1]);
+            float dz = min_img(ri.z - o.z, L[2], iL[2]);
+            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            bool use = (o.idx != me) && (cv.rcut2 <= 0.f || r2 < cv.rcut2);
+            float s, f;
+            switch_fn(r2, cv, s, f);
+            s = use ? s : 0.f;
+            f = use ? f : 0.f;
+            s8 += s;
+            x8 = fmaf(f, dx, x8);
+            y8 = fmaf(f, dy, y8);
+            z8 = fmaf(f, dz, z8);
+        }
+        S += s8;
+        gx += x8;
+        gy += y8;
+        gz += z8;
+    }
+    const int nch = side ? cv.nchunk_b : cv.nchunk_a;
+    // record layout per walker and CV: [A atoms x nchunk_a][B atoms x nchunk_b]
+    int64_t rec = cv.part0 + (int64_t)w * cs.part_per_walker +
+                  (side ? (int64_t)cv.na * cv.nchunk_a : 0) + (int64_t)i * nch + chunk;
+    part[rec] = CnPart{S, gx, gy, gz};
+}
+
+// one workgroup per (walker, coordination CV): ordered reduction of the
+// chunk partials into the Jacobian slots and the CV value.
+__global__ void __launch_bounds__(kBlock) k_coord_finalize(CvSet cs, WalkerTabs t, const CnPart *part,
+                                                            double *xi, float *J, int32_t ncoord)
+{
+    __shared__ double lds[kBlock / 64];
+    const int32_t w = blockIdx.x / ncoord, k = blockIdx.x % ncoord;
+    int c = 0, seen = 0;
+    for (; c < cs.ncv; ++c)
+        if (cs.cv[c].kind == CV_COORD && seen++ == k) break;
+    const CvDesc cv = cs.cv[c];
+    const CnPart *pw = part + cv.part0 + (int64_t)w * cs.part_per_walker;
+    double S[1] = {0.0};
+    const int ntot = cv.na + cv.nb;
+    for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
+        const bool sideB = i >= cv.na;
+        const int ii = sideB ? i - cv.na : i;
+        const int nch = sideB ? cv.nchunk_b : cv.nchunk_a;
+        const CnPart *p = pw + (sideB ? (int64_t)cv.na * cv.nchunk_a : 0) + (int64_t)ii * nch;
+        double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int q = 0; q < nch; ++q) {
+            CnPart r = p[q];
+            s += r.s;
+            gx += r.gx;
+            gy += r.gy;
+            gz += r.gz;
+        }
+        if (!sideB) S[0] += s;
+        if (J) st_slot(J, (int64_t)w * cs.nslots + cv.slot0 + i, make_double3(gx * cv.scale, gy * cv.scale, gz * cv.scale));
+    }
+    block_sum<1>(S, lds);
+    if (threadIdx.x == 0) xi[(int64_t)w * cs.D + cv.d] = S[0] * (double)cv.scale;
+}
+
+}  // namespace
+
+hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *cn_part,
+                     int64_t /*max_atoms_per_walker*/, hipStream_t s)
+{
+    int ndih = 0, nrg = 0, ncn = 0;
+    int max_tiles_x = 0;
+    for (int c = 0; c < cs.ncv; ++c) {
+        const CvDesc &d = cs.cv[c];
+        if (d.kind == CV_DIHEDRAL) ++ndih;
+        if (d.kind == CV_GYRATION) ++nrg;
+        if (d.kind == CV_COORD) {
+            ++ncn;
+            int ta = (d.na + kBlock - 1) / kBlock * d.nchunk_a;
+            int tb = (d.nb + kBlock - 1) / kBlock * d.nchunk_b;
+            max_tiles_x = max(max_tiles_x, max(ta, tb));
+        }
+    }
+    if (ndih) {
+        int64_t n = (int64_t)t.W * ndih;
+        hipLaunchKernelGGL(k_dihedral, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cs, t, pos,
+                           xi, J, ndih);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (nrg) {
+        hipLaunchKernelGGL(k_gyration, dim3(nrg, t.W), dim3(kBlock), 0, s, cs, t, pos, xi, J);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (ncn) {
+        CnPart *part = reinterpret_cast<CnPart *>(cn_part);
+        dim3 grid(max_tiles_x, 2, (unsigned)t.W * ncn);
+        if (pos.f64)
+            hipLaunchKernelGGL(k_coord_pairs<double>, grid, dim3(kBlock), 0, s, cs, t, pos, part, ncn);
+        else
+            hipLaunchKernelGGL(k_coord_pairs<float>, grid, dim3(kBlock), 0, s, cs, t, pos, part, ncn);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_coord_finalize, dim3((unsigned)t.W * ncn), dim3(kBlock), 0, s, cs, t, part, xi, J, ncn);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace sx

@@ -1,0 +1,1231 @@
+// Host side of libsampx: the C ABI declared in include/sampx.h.
+//
+// The context keeps the CV definitions, the walker layout and the method
+// parameters on the host.  sx_bind lays out the caller's state and workspace
+// buffers, uploads the index tables (Jacobian slots, the inverse atom ->
+// slots index used by the atomic-free force gather, the hill tiles) and
+// zeroes the state.  The hot path only enqueues kernels on the context's
+// stream: no allocation, no host synchronisation.
+#include "../../include/sampx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "sx_internal.h"
+
+using namespace sx;
+
+namespace {
+
+constexpr double kBoltzmann = 0.008314462618;  // kJ/(mol K), R/1000 (CODATA 2018)
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr uint64_t kCkptMagic = 0x53414d5058434b31ull;  // "SAMPXCK1"
+
+struct CvDef {
+    int32_t kind;
+    std::vector<int32_t> a, b;
+    double r0 = 0;
+    int32_t n = 0, m = 0;
+    double rcut = 0;
+    int32_t normalize = 0;
+};
+
+enum Method { M_NONE = 0, M_METAD = 1, M_ABF = 2 };
+
+struct Sub {  // a sub-buffer: byte offset and size
+    size_t off = 0, bytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Plan {
+    bool valid = false;
+    int32_t D = 0, W = 0, nslots = 0, U = 0;
+    bool all_dihedral = false;  // the hill kernels compute xi and J themselves
+    int64_t total_atoms = 0, total_cap = 0;
+    int32_t ntiles_max = 0;
+    std::vector<int64_t> atom_off, hill_base;
+    std::vector<int32_t> hill_cap;
+    std::vector<int32_t> slot_atom, slot_cv, touched, inv_ptr, inv_slot;
+    CvSet cs{};
+    SmallTabs small{};
+    int64_t nbins_total = 0;
+    // state sub-buffers
+    Sub s_hdr, s_count, s_c[kMaxBiasDim], s_h, s_N, s_Fsum;
+    size_t state_bytes = 0;
+    // workspace sub-buffers
+    Sub w_xi, w_V, w_dV, w_J, w_part, w_cnpart;
+    Sub w_atom_off, w_tiles, w_wrec;
+    Sub w_slot_atom, w_slot_cv, w_touched, w_inv_ptr, w_inv_slot;
+    size_t ws_bytes = 0;
+};
+
+}  // namespace
+
+struct sx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // definitions
+    std::vector<CvDef> cvs;
+    double box[3] = {0, 0, 0};
+    int32_t W = 1;
+    std::vector<int64_t> atom_off;   // empty: default single walker
+    std::vector<int64_t> cap_user;   // per-walker capacities (may be empty)
+    int32_t shared = 0;
+    Method method = M_NONE;
+    // metadynamics
+    double sigma[kMaxBiasDim] = {0, 0, 0};
+    double height = 0, kdT = 0;  // kdT <= 0: plain
+    int32_t stride = 0;
+    int64_t capacity = 0;
+    // ABF
+    double lo[kMaxBiasDim] = {0, 0, 0}, hi[kMaxBiasDim] = {0, 0, 0};
+    int32_t nbins[kMaxBiasDim] = {0, 0, 0};
+    int32_t n_threshold = 0;
+    // binding
+    Plan plan;
+    bool bound = false;
+    char *state = nullptr, *ws = nullptr;
+    // tuning
+    int32_t tile_units = 4, grid = 0;
+    int32_t ntiles = 0;
+    std::vector<TileRec> tiles;
+    std::vector<WalkerRec> wrecs;
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+sx_status fail(sx_ctx *c, sx_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+sx_status hip_fail(sx_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, SX_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SX_GUARD_BEGIN try {
+#define SX_GUARD_END                                                       \
+    }                                                                      \
+    catch (const std::exception &ex) { return fail(ctx, SX_EINVAL, ex.what()); } \
+    catch (...) { return fail(ctx, SX_EINVAL, "unexpected error"); }
+
+bool cv_periodic(const CvDef &c) { return c.kind == CV_DIHEDRAL; }
+
+template <typename T>
+T *at(char *base, const Sub &s)
+{
+    return reinterpret_cast<T *>(base + s.off);
+}
+
+// Lay out sub-buffers one after another, each 256-byte aligned.
+struct Layout {
+    size_t cur = 0;
+    Sub take(size_t bytes)
+    {
+        Sub s{cur, bytes};
+        cur = align256(cur + std::max<size_t>(bytes, 1));
+        return s;
+    }
+};
+
+void build_tiles(sx_ctx *c)
+{
+    const Plan &p = c->plan;
+    const int T = c->tile_units * kTileUnit;
+    c->tiles.clear();
+    c->wrecs.assign(p.W, WalkerRec{});
+    for (int w = 0; w < p.W; ++w) {
+        const int cap = p.hill_cap[w];
+        const int nt = std::max(1, (cap + T - 1) / T);
+        WalkerRec &wr = c->wrecs[w];
+        wr.t0 = (int32_t)c->tiles.size();
+        wr.nt = nt;
+        wr.cap = cap;
+        wr.hb4 = (int32_t)(p.hill_base[w] / 4);
+        wr.aoff = p.atom_off[w];
+        for (int i = 0; i < nt; ++i) {
+            TileRec tr{};
+            tr.w = w;
+            tr.h0 = i * T;
+            tr.klast = ((cap + 3) & ~3) - 4;
+            tr.hb4 = wr.hb4;
+            tr.aoff = p.atom_off[w];
+            c->tiles.push_back(tr);
+        }
+    }
+    c->ntiles = (int32_t)c->tiles.size();
+}
+
+// Build the plan: slots, inverse index, sizes of state and workspace.
+sx_status make_plan(sx_ctx *c)
+{
+    Plan p;
+    const int ncv = (int)c->cvs.size();
+    if (ncv == 0) return fail(c, SX_ESTATE, "no collective variable defined");
+    p.D = ncv;
+    if (c->method != M_NONE && ncv > kMaxBiasDim) return fail(c, SX_EINVAL, "a bias spans at most 3 CVs");
+    // walkers
+    int32_t max_idx = 0;
+    for (auto &cv : c->cvs) {
+        for (int32_t i : cv.a) max_idx = std::max(max_idx, i);
+        for (int32_t i : cv.b) max_idx = std::max(max_idx, i);
+    }
+    if (c->atom_off.empty()) {
+        p.W = 1;
+        p.atom_off = {0, (int64_t)max_idx + 1};
+    } else {
+        p.W = c->W;
+        p.atom_off = c->atom_off;
+        for (int w = 0; w < p.W; ++w)
+            if (p.atom_off[w + 1] - p.atom_off[w] <= max_idx)
+                return fail(c, SX_EINVAL, "walker " + std::to_string(w) + " has fewer atoms than a CV index needs");
+    }
+    p.total_atoms = p.atom_off[p.W];
+    // slots: per CV its member atoms (coordination: A then B)
+    CvSet &cs = p.cs;
+    cs.ncv = ncv;
+    cs.D = ncv;
+    for (int k = 0; k < 3; ++k) {
+        cs.box[k] = c->box[k];
+        cs.inv_box[k] = c->box[k] > 0 ? 1.0 / c->box[k] : 0.0;
+    }
+    int64_t part = 0;
+    for (int d = 0; d < ncv; ++d) {
+        const CvDef &cv = c->cvs[d];
+        CvDesc &ds = cs.cv[d];
+        ds = CvDesc{};
+        ds.kind = cv.kind;
+        ds.d = d;
+        ds.slot0 = (int32_t)p.slot_atom.size();
+        ds.na = (int32_t)cv.a.size();
+        ds.nb = (int32_t)cv.b.size();
+        if (cv.kind == CV_DIHEDRAL)
+            for (int q = 0; q < 4; ++q) ds.atom[q] = cv.a[q];
+        for (int32_t i : cv.a) {
+            p.slot_atom.push_back(i);
+            p.slot_cv.push_back(d);
+        }
+        for (int32_t i : cv.b) {
+            p.slot_atom.push_back(i);
+            p.slot_cv.push_back(d);
+        }
+        if (cv.kind == CV_COORD) {
+            ds.n = cv.n;
+            ds.m = cv.m;
+            ds.r0 = (float)cv.r0;
+            ds.inv_r0 = (float)(1.0 / cv.r0);
+            ds.rcut2 = cv.rcut > 0 ? (float)(cv.rcut * cv.rcut) : 0.f;
+            ds.scale = cv.normalize ? (float)(1.0 / cv.a.size()) : 1.f;
+            // partner chunk: halve until the pair grid has >= 1024 workgroups
+            int chunk = 256;
+            auto blocks = [&](int ch) {
+                int64_t ta = (ds.na + kBlock - 1) / kBlock * (int64_t)((ds.nb + ch - 1) / ch);
+                int64_t tb = (ds.nb + kBlock - 1) / kBlock * (int64_t)((ds.na + ch - 1) / ch);
+                return (ta + tb) * (int64_t)(c->atom_off.empty() ? 1 : c->W);
+            };
+            while (chunk > 32 && blocks(chunk) < 1024) chunk >>= 1;
+            ds.chunk = chunk;
+            ds.nchunk_a = (ds.nb + chunk - 1) / chunk;
+            ds.nchunk_b = (ds.na + chunk - 1) / chunk;
+            ds.part0 = part;
+            part += (int64_t)ds.na * ds.nchunk_a + (int64_t)ds.nb * ds.nchunk_b;
+        }
+    }
+    cs.part_per_walker = part;
+    p.all_dihedral = true;
+    for (auto &cv : c->cvs) p.all_dihedral = p.all_dihedral && cv.kind == CV_DIHEDRAL;
+    p.nslots = (int32_t)p.slot_atom.size();
+    cs.nslots = p.nslots;
+    // inverse index: touched atoms (sorted) -> their slots
+    std::map<int32_t, std::vector<int32_t>> inv;
+    for (int s = 0; s < p.nslots; ++s) inv[p.slot_atom[s]].push_back(s);
+    p.inv_ptr.push_back(0);
+    for (auto &kv : inv) {
+        p.touched.push_back(kv.first);
+        for (int32_t s : kv.second) p.inv_slot.push_back(s);
+        p.inv_ptr.push_back((int32_t)p.inv_slot.size());
+    }
+    p.U = (int32_t)p.touched.size();
+    // the same table in kernel-argument form when it is small
+    p.small = SmallTabs{};
+    bool fits = p.U <= kSmallU;
+    for (int u = 0; u < p.U && fits; ++u) fits = p.inv_ptr[u + 1] - p.inv_ptr[u] <= kSmallPer;
+    if (fits && p.nslots < (1 << 20)) {
+        p.small.on = 1;
+        p.small.U = p.U;
+        for (int u = 0; u < p.U; ++u) {
+            p.small.touched[u] = p.touched[u];
+            p.small.nent[u] = p.inv_ptr[u + 1] - p.inv_ptr[u];
+            for (int q = p.inv_ptr[u]; q < p.inv_ptr[u + 1]; ++q)
+                p.small.ent[u][q - p.inv_ptr[u]] = p.inv_slot[q] | (p.slot_cv[p.inv_slot[q]] << 20);
+        }
+    }
+    // hills
+    const int nlists = (c->method == M_METAD) ? (c->shared ? 1 : p.W) : 0;
+    p.hill_cap.assign(p.W, 0);
+    p.hill_base.assign(p.W, 0);
+    int64_t total = 0;
+    for (int w = 0; w < nlists; ++w) {
+        int64_t cap = c->cap_user.empty() ? c->capacity : c->cap_user[w];
+        if (cap < 1) return fail(c, SX_EINVAL, "hill capacity must be >= 1");
+        if (cap > (int64_t)1 << 30) return fail(c, SX_EINVAL, "hill capacity above 2^30 per list");
+        p.hill_cap[w] = (int32_t)cap;
+        p.hill_base[w] = total;
+        total += (cap + 3) / 4 * 4;
+    }
+    p.total_cap = total;
+    for (int w = 0; w < nlists; ++w) p.ntiles_max += std::max(1, (p.hill_cap[w] + kTileUnit - 1) / kTileUnit);
+    // ABF grid
+    p.nbins_total = 0;
+    if (c->method == M_ABF) {
+        p.nbins_total = 1;
+        for (int d = 0; d < ncv; ++d) p.nbins_total *= c->nbins[d];
+    }
+    // state layout
+    Layout ls;
+    p.s_hdr = ls.take(256);
+    p.s_count = ls.take(sizeof(int32_t) * std::max(nlists, 1));
+    for (int d = 0; d < kMaxBiasDim; ++d) p.s_c[d] = ls.take(d < p.D && nlists ? sizeof(float) * total : 0);
+    p.s_h = ls.take(sizeof(float) * total);
+    p.s_N = ls.take(sizeof(uint32_t) * p.W * p.nbins_total);
+    p.s_Fsum = ls.take(sizeof(double) * p.W * p.nbins_total * p.D);
+    p.state_bytes = ls.cur;
+    // workspace layout
+    Layout lw;
+    p.w_xi = lw.take(sizeof(double) * p.W * p.D);
+    p.w_V = lw.take(sizeof(double) * p.W);
+    p.w_dV = lw.take(sizeof(double) * p.W * p.D);
+    p.w_J = lw.take(sizeof(float) * 3 * (size_t)p.W * p.nslots);
+    p.w_part = lw.take(sizeof(double) * 4 * (size_t)p.ntiles_max);
+    p.w_cnpart = lw.take(32 * (size_t)p.W * part);
+    p.w_atom_off = lw.take(sizeof(int64_t) * (p.W + 1));
+    p.w_tiles = lw.take(sizeof(TileRec) * p.ntiles_max);
+    p.w_wrec = lw.take(sizeof(WalkerRec) * p.W);
+    p.w_slot_atom = lw.take(sizeof(int32_t) * p.nslots);
+    p.w_slot_cv = lw.take(sizeof(int32_t) * p.nslots);
+    p.w_touched = lw.take(sizeof(int32_t) * p.U);
+    p.w_inv_ptr = lw.take(sizeof(int32_t) * (p.U + 1));
+    p.w_inv_slot = lw.take(sizeof(int32_t) * p.nslots);
+    p.ws_bytes = lw.cur;
+    p.valid = true;
+    c->plan = std::move(p);
+    return SX_OK;
+}
+
+sx_status ensure_plan(sx_ctx *c)
+{
+    if (c->plan.valid) return SX_OK;
+    return make_plan(c);
+}
+
+void invalidate(sx_ctx *c)
+{
+    c->plan.valid = false;
+}
+
+sx_status require_unbound(sx_ctx *c)
+{
+    if (c->bound) return fail(c, SX_ESTATE, "definitions are frozen once state is bound");
+    return SX_OK;
+}
+
+WalkerTabs tabs_of(sx_ctx *c)
+{
+    const Plan &p = c->plan;
+    WalkerTabs t;
+    t.W = p.W;
+    t.atom_off = at<int64_t>(c->ws, p.w_atom_off);
+    t.slot_atom = at<int32_t>(c->ws, p.w_slot_atom);
+    t.slot_cv = at<int32_t>(c->ws, p.w_slot_cv);
+    t.touched = at<int32_t>(c->ws, p.w_touched);
+    t.inv_ptr = at<int32_t>(c->ws, p.w_inv_ptr);
+    t.inv_slot = at<int32_t>(c->ws, p.w_inv_slot);
+    t.U = p.U;
+    return t;
+}
+
+bool pos_view(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout, PosView &v)
+{
+    if (!pos || (dtype != SX_F32 && dtype != SX_F64) || layout < SX_AOS3 || layout > SX_SOA) return false;
+    v.ptr = pos;
+    v.f64 = dtype == SX_F64;
+    if (layout == SX_AOS3) {
+        v.sa = 3;
+        v.sk = 1;
+    } else if (layout == SX_AOS4) {
+        v.sa = 4;
+        v.sk = 1;
+    } else {
+        v.sa = 1;
+        v.sk = c->plan.total_atoms;
+    }
+    return true;
+}
+
+ForceView force_view(sx_ctx *c, float *f, int32_t layout)
+{
+    ForceView v;
+    v.ptr = f;
+    if (layout == SX_AOS3) {
+        v.sa = 3;
+        v.sk = 1;
+    } else if (layout == SX_AOS4) {
+        v.sa = 4;
+        v.sk = 1;
+    } else {
+        v.sa = 1;
+        v.sk = c->plan.total_atoms;
+    }
+    return v;
+}
+
+HillArgs hill_args(sx_ctx *c, const double *xi)
+{
+    const Plan &p = c->plan;
+    HillArgs a{};
+    for (int d = 0; d < kMaxBiasDim; ++d) a.c[d] = d < p.D ? at<float>(c->state, p.s_c[d]) : nullptr;
+    a.h = at<float>(c->state, p.s_h);
+    a.count = at<int32_t>(c->state, p.s_count);
+    a.tiles = at<TileRec>(c->ws, p.w_tiles);
+    a.wrec = at<WalkerRec>(c->ws, p.w_wrec);
+    a.ntiles = c->ntiles;
+    a.tile_units = c->tile_units;
+    a.partial = at<double>(c->ws, p.w_part);
+    a.D = p.D;
+    for (int d = 0; d < p.D; ++d) {
+        const bool per = cv_periodic(c->cvs[d]);
+        a.period[d] = per ? kTwoPi : 0.0;
+        a.inv_period[d] = per ? 1.0 / kTwoPi : 0.0;
+        const double s2 = c->sigma[d] * c->sigma[d];
+        a.a2[d] = (float)(1.4426950408889634 / (2.0 * s2));  // log2(e) / (2 sigma^2)
+        a.inv_sig2[d] = 1.0 / s2;
+    }
+    a.xi = xi;
+    a.V_ws = at<double>(c->ws, p.w_V);
+    a.dV_ws = at<double>(c->ws, p.w_dV);
+    a.stride = c->stride;
+    a.height = c->height;
+    a.inv_kdT = c->kdT > 0 && std::isfinite(c->kdT) ? 1.0 / c->kdT : 0.0;
+    a.dstep = at<int64_t>(c->state, p.s_hdr);
+    a.flags = reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8);
+    a.J = at<float>(c->ws, p.w_J);
+    a.nslots = p.nslots;
+    a.tabs = tabs_of(c);
+    a.small = p.small;
+    return a;
+}
+
+sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J)
+{
+    const Plan &p = c->plan;
+    hipError_t e = launch_cv(p.cs, tabs_of(c), pv, xi, J, at<double>(c->ws, p.w_cnpart), 0, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "CV kernels");
+    return SX_OK;
+}
+
+// The step's kernel sequence (also what a graph captures).
+sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout, int64_t step, double *xi_out,
+                       double *V_out, double *dVdxi_out, float *forces, const float *sys_forces)
+{
+    const Plan &p = c->plan;
+    PosView pv;
+    if (!pos_view(c, pos, dtype, layout, pv)) return fail(c, SX_EINVAL, "bad positions, dtype or layout");
+    double *xi = at<double>(c->ws, p.w_xi);
+    float *J = at<float>(c->ws, p.w_J);
+    if (c->method == M_NONE) return fail(c, SX_ESTATE, "no method configured (sx_metad_config / sx_abf_config)");
+    const bool fuse = c->method == M_METAD && p.all_dihedral;
+    if (!fuse) {
+        sx_status st = launch_cvs(c, pv, xi, J);
+        if (st != SX_OK) return st;
+    }
+    if (c->method == M_METAD) {
+        HillArgs a = hill_args(c, xi);
+        a.fuse = fuse;
+        a.xi_save = xi;
+        a.xi_out = xi_out;
+        a.V_out = V_out;
+        a.dV_out = dVdxi_out;
+        a.count_step = 1;
+        a.deposit = 1;
+        a.step = step;
+        a.do_forces = forces != nullptr;
+        a.F = force_view(c, forces, layout);
+        hipError_t e = launch_hill_private(a, p.cs, pv, c->grid, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hill-sum kernels");
+    } else {
+        if (!sys_forces) return fail(c, SX_EINVAL, "ABF needs the system forces");
+        if (!forces) return fail(c, SX_EINVAL, "ABF needs the force buffer");
+        AbfArgs a{};
+        a.D = p.D;
+        a.xi = xi;
+        a.J = J;
+        a.nslots = p.nslots;
+        a.tabs = tabs_of(c);
+        pos_view(c, sys_forces, SX_F32, layout, a.Fsys);
+        a.F = force_view(c, forces, layout);
+        a.N = at<uint32_t>(c->state, p.s_N);
+        a.Fsum = at<double>(c->state, p.s_Fsum);
+        a.nbins_total = p.nbins_total;
+        for (int d = 0; d < p.D; ++d) {
+            a.lo[d] = c->lo[d];
+            a.delta[d] = (c->hi[d] - c->lo[d]) / c->nbins[d];
+            a.nbins[d] = c->nbins[d];
+            a.periodic[d] = cv_periodic(c->cvs[d]);
+        }
+        a.n_threshold = c->n_threshold;
+        a.xi_out = xi_out;
+        a.V_out = V_out;
+        a.dV_out = dVdxi_out;
+        a.flags = reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8);
+        a.step = step;
+        a.dstep = at<int64_t>(c->state, p.s_hdr);
+        hipError_t e = launch_abf(a, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "ABF kernel");
+    }
+    return SX_OK;
+}
+
+sx_status require_bound(sx_ctx *c)
+{
+    if (!c) return SX_EINVAL;
+    if (!c->bound) return fail(c, SX_ESTATE, "state not bound (sx_bind)");
+    return SX_OK;
+}
+
+sx_status upload_tiles(sx_ctx *c)
+{
+    const Plan &p = c->plan;
+    hipError_t e = hipMemcpyAsync(at<WalkerRec>(c->ws, p.w_wrec), c->wrecs.data(), sizeof(WalkerRec) * p.W,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->ntiles)
+        e = hipMemcpyAsync(at<TileRec>(c->ws, p.w_tiles), c->tiles.data(), sizeof(TileRec) * c->ntiles,
+                           hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "tile table upload");
+    return SX_OK;
+}
+
+int walker_list(sx_ctx *c, int32_t walker)
+{
+    if (c->shared) return 0;
+    return walker;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+sx_status sx_create(sx_ctx **out, int device, void *stream)
+{
+    if (!out) return SX_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SX_EDEVICE;
+    sx_ctx *c = new (std::nothrow) sx_ctx;
+    if (!c) return SX_ENOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    *out = c;
+    return SX_OK;
+}
+
+void sx_destroy(sx_ctx *c)
+{
+    if (!c) return;
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    delete c;
+}
+
+const char *sx_last_error(const sx_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+const char *sx_status_string(int s)
+{
+    switch (s) {
+    case SX_OK: return "ok";
+    case SX_EINVAL: return "invalid argument";
+    case SX_ENOMEM: return "buffer too small";
+    case SX_ECAPACITY: return "hill capacity exceeded";
+    case SX_ENONFINITE: return "non-finite value";
+    case SX_EDEVICE: return "device error";
+    case SX_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+sx_status sx_set_stream(sx_ctx *ctx, void *stream)
+{
+    if (!ctx) return SX_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return SX_OK;
+}
+
+static sx_status check_indices(sx_ctx *ctx, const int32_t *idx, int32_t n, bool distinct)
+{
+    if (!idx || n < 1) return fail(ctx, SX_EINVAL, "empty atom group");
+    std::vector<int32_t> v(idx, idx + n);
+    for (int32_t i : v)
+        if (i < 0) return fail(ctx, SX_EINVAL, "negative atom index");
+    if (distinct) {
+        std::sort(v.begin(), v.end());
+        if (std::adjacent_find(v.begin(), v.end()) != v.end()) return fail(ctx, SX_EINVAL, "repeated atom index");
+    }
+    return SX_OK;
+}
+
+sx_status sx_add_cv_dihedral(sx_ctx *ctx, const int32_t idx[4])
+{
+    if (!ctx) return SX_EINVAL;
+    SX_GUARD_BEGIN
+    if (sx_status s = require_unbound(ctx)) return s;
+    if ((int)ctx->cvs.size() >= kMaxCv) return fail(ctx, SX_EINVAL, "too many CVs");
+    if (sx_status s = check_indices(ctx, idx, 4, true)) return s;
+    CvDef d;
+    d.kind = CV_DIHEDRAL;
+    d.a.assign(idx, idx + 4);
+    ctx->cvs.push_back(d);
+    invalidate(ctx);
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_add_cv_gyration(sx_ctx *ctx, const int32_t *idx, int32_t n)
+{
+    if (!ctx) return SX_EINVAL;
+    SX_GUARD_BEGIN
+    if (sx_status s = require_unbound(ctx)) return s;
+    if ((int)ctx->cvs.size() >= kMaxCv) return fail(ctx, SX_EINVAL, "too many CVs");
+    if (n < 2) return fail(ctx, SX_EINVAL, "radius of gyration needs >= 2 atoms");
+    if (sx_status s = check_indices(ctx, idx, n, true)) return s;
+    CvDef d;
+    d.kind = CV_GYRATION;
+    d.a.assign(idx, idx + n);
+    ctx->cvs.push_back(d);
+    invalidate(ctx);
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_add_cv_coordination(sx_ctx *ctx, const int32_t *a, int32_t na, const int32_t *b, int32_t nb, double r0,
+                                 int32_t n, int32_t m, double rcut, int32_t normalize)
+{
+    if (!ctx) return SX_EINVAL;
+    SX_GUARD_BEGIN
+    if (sx_status s = require_unbound(ctx)) return s;
+    if ((int)ctx->cvs.size() >= kMaxCv) return fail(ctx, SX_EINVAL, "too many CVs");
+    if (!(r0 > 0) || n < 1 || m <= n || n > 64 || m > 64)
+        return fail(ctx, SX_EINVAL, "switching function needs r0 > 0 and 1 <= n < m <= 64");
+    if (sx_status s = check_indices(ctx, a, na, true)) return s;
+    if (sx_status s = check_indices(ctx, b, nb, true)) return s;
+    CvDef d;
+    d.kind = CV_COORD;
+    d.a.assign(a, a + na);
+    d.b.assign(b, b + nb);
+    d.r0 = r0;
+    d.n = n;
+    d.m = m;
+    d.rcut = rcut > 0 ? rcut : 0.0;
+    d.normalize = normalize != 0;
+    ctx->cvs.push_back(d);
+    invalidate(ctx);
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_set_box(sx_ctx *ctx, const double L[3])
+{
+    if (!ctx || !L) return SX_EINVAL;
+    if (sx_status s = require_unbound(ctx)) return s;
+    for (int k = 0; k < 3; ++k) {
+        if (!(L[k] >= 0) || !std::isfinite(L[k])) return fail(ctx, SX_EINVAL, "box edges must be finite and >= 0");
+        ctx->box[k] = L[k];
+    }
+    invalidate(ctx);
+    return SX_OK;
+}
+
+int32_t sx_num_cvs(const sx_ctx *ctx) { return ctx ? (int32_t)ctx->cvs.size() : 0; }
+
+sx_status sx_set_walkers(sx_ctx *ctx, int32_t n_walkers, const int64_t *atom_off, const int64_t *hill_capacity,
+                         int32_t shared_hills)
+{
+    if (!ctx) return SX_EINVAL;
+    SX_GUARD_BEGIN
+    if (sx_status s = require_unbound(ctx)) return s;
+    if (n_walkers < 1 || !atom_off) return fail(ctx, SX_EINVAL, "need >= 1 walker and atom offsets");
+    for (int w = 0; w < n_walkers; ++w)
+        if (atom_off[w] < 0 || atom_off[w + 1] < atom_off[w])
+            return fail(ctx, SX_EINVAL, "atom offsets must be >= 0 and non-decreasing");
+    if (atom_off[n_walkers] >= ((int64_t)1 << 40)) return fail(ctx, SX_EINVAL, "too many atoms");
+    ctx->W = n_walkers;
+    ctx->atom_off.assign(atom_off, atom_off + n_walkers + 1);
+    ctx->shared = shared_hills != 0;
+    ctx->cap_user.clear();
+    if (hill_capacity) {
+        int nl = ctx->shared ? 1 : n_walkers;
+        for (int w = 0; w < nl; ++w)
+            if (hill_capacity[w] < 1) return fail(ctx, SX_EINVAL, "hill capacities must be >= 1");
+        ctx->cap_user.assign(hill_capacity, hill_capacity + nl);
+    }
+    if (ctx->shared) return fail(ctx, SX_EINVAL, "shared hill lists are not supported by this build");
+    invalidate(ctx);
+    return SX_OK;
+    SX_GUARD_END
+}
+
+static sx_status metad_common(sx_ctx *ctx, const double *sigma, double w, double kdT, int32_t stride, int64_t capacity)
+{
+    if (sx_status s = require_unbound(ctx)) return s;
+    const int D = (int)ctx->cvs.size();
+    if (D < 1) return fail(ctx, SX_ESTATE, "define the CVs before the method");
+    if (D > kMaxBiasDim) return fail(ctx, SX_EINVAL, "metadynamics supports at most 3 CVs");
+    if (ctx->method == M_ABF) return fail(ctx, SX_EINVAL, "ABF already configured on this context");
+    if (!sigma) return fail(ctx, SX_EINVAL, "sigma is NULL");
+    for (int d = 0; d < D; ++d)
+        if (!(sigma[d] > 0) || !std::isfinite(sigma[d])) return fail(ctx, SX_EINVAL, "sigma must be > 0");
+    if (!(w > 0) || !std::isfinite(w)) return fail(ctx, SX_EINVAL, "hill height must be > 0");
+    if (stride < 0) return fail(ctx, SX_EINVAL, "stride must be >= 0");
+    if (capacity < 1) return fail(ctx, SX_EINVAL, "capacity must be >= 1");
+    for (int d = 0; d < D; ++d) ctx->sigma[d] = sigma[d];
+    ctx->height = w;
+    ctx->kdT = kdT;
+    ctx->stride = stride;
+    ctx->capacity = capacity;
+    ctx->method = M_METAD;
+    invalidate(ctx);
+    return SX_OK;
+}
+
+sx_status sx_metad_config(sx_ctx *ctx, const double *sigma, double w, double temperature, double bias_factor,
+                          int32_t stride, int64_t capacity)
+{
+    if (!ctx) return SX_EINVAL;
+    double kdT = 0.0;
+    if (bias_factor > 0 && std::isfinite(bias_factor)) {
+        if (bias_factor <= 1) return fail(ctx, SX_EINVAL, "bias factor must be > 1 (or <= 0 / inf for plain metadynamics)");
+        if (!(temperature > 0) || !std::isfinite(temperature)) return fail(ctx, SX_EINVAL, "temperature must be > 0");
+        kdT = kBoltzmann * (bias_factor - 1.0) * temperature;
+    }
+    return metad_common(ctx, sigma, w, kdT, stride, capacity);
+}
+
+sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double delta_T, int32_t stride,
+                             int64_t capacity)
+{
+    if (!ctx) return SX_EINVAL;
+    double kdT = (delta_T > 0 && std::isfinite(delta_T)) ? kBoltzmann * delta_T : 0.0;
+    return metad_common(ctx, sigma, w, kdT, stride, capacity);
+}
+
+sx_status sx_abf_config(sx_ctx *ctx, const double *lo, const double *hi, const int32_t *nbins, int32_t n_threshold)
+{
+    if (!ctx) return SX_EINVAL;
+    if (sx_status s = require_unbound(ctx)) return s;
+    const int D = (int)ctx->cvs.size();
+    if (D < 1) return fail(ctx, SX_ESTATE, "define the CVs before the method");
+    if (D > kMaxBiasDim) return fail(ctx, SX_EINVAL, "ABF supports at most 3 CVs");
+    if (ctx->method == M_METAD) return fail(ctx, SX_EINVAL, "metadynamics already configured on this context");
+    if (!lo || !hi || !nbins) return fail(ctx, SX_EINVAL, "NULL grid argument");
+    if (n_threshold < 0) return fail(ctx, SX_EINVAL, "threshold must be >= 0");
+    int64_t tot = 1;
+    for (int d = 0; d < D; ++d) {
+        if (!(lo[d] < hi[d]) || !std::isfinite(lo[d]) || !std::isfinite(hi[d]))
+            return fail(ctx, SX_EINVAL, "grid needs finite lo < hi");
+        if (nbins[d] < 1) return fail(ctx, SX_EINVAL, "nbins must be >= 1");
+        if (cv_periodic(ctx->cvs[d]) && std::fabs((hi[d] - lo[d]) - kTwoPi) > 1e-9)
+            return fail(ctx, SX_EINVAL, "a periodic CV's grid must span one period (2 pi)");
+        tot *= nbins[d];
+        if (tot > ((int64_t)1 << 28)) return fail(ctx, SX_EINVAL, "grid too large");
+    }
+    for (int d = 0; d < D; ++d) {
+        ctx->lo[d] = lo[d];
+        ctx->hi[d] = hi[d];
+        ctx->nbins[d] = nbins[d];
+    }
+    ctx->n_threshold = n_threshold;
+    ctx->method = M_ABF;
+    invalidate(ctx);
+    return SX_OK;
+}
+
+size_t sx_state_bytes(const sx_ctx *cctx)
+{
+    sx_ctx *ctx = const_cast<sx_ctx *>(cctx);
+    if (!ctx || ensure_plan(ctx) != SX_OK) return 0;
+    return ctx->plan.state_bytes;
+}
+
+size_t sx_workspace_bytes(const sx_ctx *cctx)
+{
+    sx_ctx *ctx = const_cast<sx_ctx *>(cctx);
+    if (!ctx || ensure_plan(ctx) != SX_OK) return 0;
+    return ctx->plan.ws_bytes;
+}
+
+sx_status sx_bind(sx_ctx *ctx, void *dev_state, size_t state_bytes, void *dev_ws, size_t ws_bytes)
+{
+    if (!ctx) return SX_EINVAL;
+    SX_GUARD_BEGIN
+    if (sx_status s = ensure_plan(ctx)) return s;
+    const Plan &p = ctx->plan;
+    if (!dev_state || !dev_ws) return fail(ctx, SX_EINVAL, "NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(dev_state) & 255) || (reinterpret_cast<uintptr_t>(dev_ws) & 255))
+        return fail(ctx, SX_EINVAL, "buffers must be 256-byte aligned");
+    if (state_bytes < p.state_bytes || ws_bytes < p.ws_bytes) return fail(ctx, SX_ENOMEM, "buffer smaller than the size query");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+    ctx->state = static_cast<char *>(dev_state);
+    ctx->ws = static_cast<char *>(dev_ws);
+    // zero state and the workspace counters with a fill kernel
+    e = launch_zero_bytes(ctx->state, (int64_t)p.state_bytes, ctx->stream);
+    if (e == hipSuccess) e = launch_zero_bytes(ctx->ws, (int64_t)p.ws_bytes, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "state clear");
+    auto up = [&](const Sub &s, const void *src, size_t bytes) {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(ctx->ws + s.off, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+    };
+    e = up(p.w_atom_off, p.atom_off.data(), sizeof(int64_t) * (p.W + 1));
+    if (e == hipSuccess) e = up(p.w_slot_atom, p.slot_atom.data(), sizeof(int32_t) * p.nslots);
+    if (e == hipSuccess) e = up(p.w_slot_cv, p.slot_cv.data(), sizeof(int32_t) * p.nslots);
+    if (e == hipSuccess) e = up(p.w_touched, p.touched.data(), sizeof(int32_t) * p.U);
+    if (e == hipSuccess) e = up(p.w_inv_ptr, p.inv_ptr.data(), sizeof(int32_t) * (p.U + 1));
+    if (e == hipSuccess) e = up(p.w_inv_slot, p.inv_slot.data(), sizeof(int32_t) * p.nslots);
+    if (e != hipSuccess) return hip_fail(ctx, e, "table upload");
+    ctx->bound = true;
+    if (ctx->method != M_METAD) return hipStreamSynchronize(ctx->stream) == hipSuccess ? SX_OK : fail(ctx, SX_EDEVICE, "bind");
+    build_tiles(ctx);
+    return upload_tiles(ctx);
+    SX_GUARD_END
+}
+
+sx_status sx_step(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, int64_t step, double *xi_out,
+                  double *V_out, double *dVdxi_out, float *forces, const float *sys_forces)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (step < SX_STEP_DEVICE) return fail(ctx, SX_EINVAL, "step must be >= 0 or SX_STEP_DEVICE");
+    return enqueue_step(ctx, pos, dtype, layout, step, xi_out, V_out, dVdxi_out, forces, sys_forces);
+    SX_GUARD_END
+}
+
+sx_status sx_check(sx_ctx *ctx)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream");
+    uint32_t flags = 0;
+    uint32_t *df = reinterpret_cast<uint32_t *>(ctx->state + ctx->plan.s_hdr.off + 8);
+    e = hipMemcpy(&flags, df, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "flag read");
+    if (flags) {
+        uint32_t z = 0;
+        e = hipMemcpy(df, &z, 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(ctx, e, "flag clear");
+    }
+    if (flags & kFlagCapacity) return fail(ctx, SX_ECAPACITY, "a hill deposition found its walker's list full");
+    if (flags & kFlagNonFinite) return fail(ctx, SX_ENONFINITE, "non-finite CV value or bias");
+    return SX_OK;
+}
+
+sx_status sx_eval_cv(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, double *xi_out, float *jac_out)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    PosView pv;
+    if (!pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
+    if (!xi_out) return fail(ctx, SX_EINVAL, "xi_out is NULL");
+    return launch_cvs(ctx, pv, xi_out, jac_out);
+    SX_GUARD_END
+}
+
+int64_t sx_jac_slots(const sx_ctx *cctx)
+{
+    sx_ctx *ctx = const_cast<sx_ctx *>(cctx);
+    if (!ctx || ensure_plan(ctx) != SX_OK) return -1;
+    return ctx->plan.nslots;
+}
+
+sx_status sx_jac_layout(const sx_ctx *cctx, int32_t *atom, int32_t *cv)
+{
+    sx_ctx *ctx = const_cast<sx_ctx *>(cctx);
+    if (!ctx) return SX_EINVAL;
+    if (sx_status s = ensure_plan(ctx)) return s;
+    const Plan &p = ctx->plan;
+    if (atom) std::copy(p.slot_atom.begin(), p.slot_atom.end(), atom);
+    if (cv) std::copy(p.slot_cv.begin(), p.slot_cv.end(), cv);
+    return SX_OK;
+}
+
+sx_status sx_cv_vjp(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const double *xi_bar, float *pos_bar)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    PosView pv;
+    if (!pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
+    if (!xi_bar || !pos_bar) return fail(ctx, SX_EINVAL, "NULL xi_bar or pos_bar");
+    const Plan &p = ctx->plan;
+    float *J = at<float>(ctx->ws, p.w_J);
+    if (sx_status s = launch_cvs(ctx, pv, at<double>(ctx->ws, p.w_xi), J)) return s;
+    hipError_t e = launch_gather(tabs_of(ctx), J, p.nslots, p.D, xi_bar, 1.0, force_view(ctx, pos_bar, layout),
+                                 ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "VJP gather");
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_hillsum(sx_ctx *ctx, const double *xi, double *V_out, double *dVdxi_out)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
+    if (!xi) return fail(ctx, SX_EINVAL, "xi is NULL");
+    HillArgs a = hill_args(ctx, xi);
+    a.V_out = V_out;
+    a.dV_out = dVdxi_out;
+    a.deposit = 0;
+    a.step = 0;
+    a.count_step = 0;
+    a.do_forces = 0;
+    hipError_t e = launch_hill_private(a, ctx->plan.cs, PosView{}, ctx->grid, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hill-sum kernel");
+    return SX_OK;
+}
+
+sx_status sx_deposit(sx_ctx *ctx, const double *xi)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
+    if (!xi) return fail(ctx, SX_EINVAL, "xi is NULL");
+    HillArgs a = hill_args(ctx, xi);
+    a.deposit = 2;
+    a.step = 0;
+    a.count_step = 0;
+    a.do_forces = 0;
+    hipError_t e = launch_hill_private(a, ctx->plan.cs, PosView{}, ctx->grid, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "deposit kernel");
+    return SX_OK;
+}
+
+sx_status sx_hills_set(sx_ctx *ctx, int32_t walker, const float *centers, const float *heights, int64_t K)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
+    const Plan &p = ctx->plan;
+    const int wl = walker_list(ctx, walker);
+    if (wl < 0 || wl >= p.W) return fail(ctx, SX_EINVAL, "walker out of range");
+    if (K < 0 || K > p.hill_cap[wl]) return fail(ctx, SX_ECAPACITY, "K exceeds the walker's hill capacity");
+    if (K > 0 && (!centers || !heights)) return fail(ctx, SX_EINVAL, "NULL hill arrays");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    const int D = p.D;
+    std::vector<float> col(K);
+    for (int d = 0; d < D && e == hipSuccess; ++d) {
+        for (int64_t k = 0; k < K; ++k) col[k] = centers[k * D + d];
+        if (K) e = hipMemcpy(at<float>(ctx->state, p.s_c[d]) + p.hill_base[wl], col.data(), sizeof(float) * K,
+                             hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && K)
+        e = hipMemcpy(at<float>(ctx->state, p.s_h) + p.hill_base[wl], heights, sizeof(float) * K, hipMemcpyHostToDevice);
+    int32_t k32 = (int32_t)K;
+    if (e == hipSuccess) e = hipMemcpy(at<int32_t>(ctx->state, p.s_count) + wl, &k32, 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hill upload");
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_hills_get(sx_ctx *ctx, int32_t walker, float *centers, float *heights, int64_t max_K, int64_t *K)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
+    const Plan &p = ctx->plan;
+    const int wl = walker_list(ctx, walker);
+    if (wl < 0 || wl >= p.W) return fail(ctx, SX_EINVAL, "walker out of range");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    int32_t n = 0;
+    if (e == hipSuccess) e = hipMemcpy(&n, at<int32_t>(ctx->state, p.s_count) + wl, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "count read");
+    if (K) *K = n;
+    const int64_t m = std::min<int64_t>(n, std::max<int64_t>(max_K, 0));
+    const int D = p.D;
+    std::vector<float> col(m);
+    for (int d = 0; d < D && m > 0 && centers; ++d) {
+        e = hipMemcpy(col.data(), at<float>(ctx->state, p.s_c[d]) + p.hill_base[wl], sizeof(float) * m,
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hill read");
+        for (int64_t k = 0; k < m; ++k) centers[k * D + d] = col[k];
+    }
+    if (m > 0 && heights) {
+        e = hipMemcpy(heights, at<float>(ctx->state, p.s_h) + p.hill_base[wl], sizeof(float) * m, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hill read");
+    }
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_abf_grid_get(sx_ctx *ctx, int32_t walker, uint32_t *N, double *Fsum)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (ctx->method != M_ABF) return fail(ctx, SX_ESTATE, "no ABF grid on this context");
+    const Plan &p = ctx->plan;
+    if (walker < 0 || walker >= p.W) return fail(ctx, SX_EINVAL, "walker out of range");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && N)
+        e = hipMemcpy(N, at<uint32_t>(ctx->state, p.s_N) + (int64_t)walker * p.nbins_total,
+                      sizeof(uint32_t) * p.nbins_total, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && Fsum)
+        e = hipMemcpy(Fsum, at<double>(ctx->state, p.s_Fsum) + (int64_t)walker * p.nbins_total * p.D,
+                      sizeof(double) * p.nbins_total * p.D, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "grid read");
+    return SX_OK;
+}
+
+sx_status sx_get_step(sx_ctx *ctx, int64_t *step)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (!step) return fail(ctx, SX_EINVAL, "NULL step");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(step, at<int64_t>(ctx->state, ctx->plan.s_hdr), 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step read");
+    return SX_OK;
+}
+
+// checkpoint: [magic, state_bytes, config hash, 0...] (64 bytes) + state
+static uint64_t config_hash(const sx_ctx *c)
+{
+    std::ostringstream os;
+    os.precision(17);
+    os << c->method << ' ' << c->plan.W << ' ' << c->plan.D << ' ' << c->plan.nslots << ' ' << c->plan.total_cap << ' '
+       << c->plan.nbins_total << ' ' << c->height << ' ' << c->kdT << ' ' << c->stride;
+    for (int d = 0; d < c->plan.D; ++d) os << ' ' << c->sigma[d] << ' ' << c->lo[d] << ' ' << c->hi[d];
+    for (auto v : c->plan.hill_cap) os << ' ' << v;
+    std::string s = os.str();
+    uint64_t h = 1469598103934665603ull;  // FNV-1a
+    for (unsigned char ch : s) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+size_t sx_checkpoint_bytes(const sx_ctx *cctx)
+{
+    sx_ctx *ctx = const_cast<sx_ctx *>(cctx);
+    if (!ctx || ensure_plan(ctx) != SX_OK) return 0;
+    return 64 + ctx->plan.state_bytes;
+}
+
+sx_status sx_state_export(sx_ctx *ctx, void *host, size_t bytes)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    const size_t need = 64 + ctx->plan.state_bytes;
+    if (!host || bytes < need) return fail(ctx, SX_ENOMEM, "checkpoint buffer too small");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    uint64_t hdr[8] = {kCkptMagic, (uint64_t)ctx->plan.state_bytes, config_hash(ctx), 0, 0, 0, 0, 0};
+    std::memcpy(host, hdr, 64);
+    if (e == hipSuccess)
+        e = hipMemcpy(static_cast<char *>(host) + 64, ctx->state, ctx->plan.state_bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "checkpoint read");
+    return SX_OK;
+}
+
+sx_status sx_state_import(sx_ctx *ctx, const void *host, size_t bytes)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    const size_t need = 64 + ctx->plan.state_bytes;
+    if (!host || bytes < need) return fail(ctx, SX_EINVAL, "checkpoint too short");
+    uint64_t hdr[8];
+    std::memcpy(hdr, host, 64);
+    if (hdr[0] != kCkptMagic || hdr[1] != ctx->plan.state_bytes || hdr[2] != config_hash(ctx))
+        return fail(ctx, SX_EINVAL, "checkpoint of another configuration");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->state, static_cast<const char *>(host) + 64, ctx->plan.state_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "checkpoint write");
+    return SX_OK;
+}
+
+sx_status sx_graph_capture(sx_ctx *ctx, int32_t n_steps, const void *pos, int32_t dtype, int32_t layout,
+                           double *xi_out, double *V_out, double *dVdxi_out, float *forces, const float *sys_forces)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (n_steps < 1) return fail(ctx, SX_EINVAL, "n_steps must be >= 1");
+    if (ctx->gexec) {
+        hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
+    if (ctx->graph) {
+        hipGraphDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    hipStream_t cap;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(ctx, e, "capture stream");
+    hipStream_t saved = ctx->stream;
+    ctx->stream = cap;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    sx_status st = SX_OK;
+    if (e == hipSuccess) {
+        for (int i = 0; i < n_steps && st == SX_OK; ++i)
+            st = enqueue_step(ctx, pos, dtype, layout, SX_STEP_DEVICE, xi_out, V_out, dVdxi_out, forces, sys_forces);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &g);
+        if (st == SX_OK && e2 == hipSuccess) {
+            ctx->graph = g;
+            e2 = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+        } else if (g) {
+            hipGraphDestroy(g);
+        }
+        if (st == SX_OK && e2 != hipSuccess) st = hip_fail(ctx, e2, "graph capture");
+    } else {
+        st = hip_fail(ctx, e, "begin capture");
+    }
+    ctx->stream = saved;
+    hipStreamDestroy(cap);
+    return st;
+    SX_GUARD_END
+}
+
+sx_status sx_graph_launch(sx_ctx *ctx)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (!ctx->gexec) return fail(ctx, SX_ESTATE, "no captured graph");
+    hipError_t e = hipGraphLaunch(ctx->gexec, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "graph launch");
+    return SX_OK;
+}
+
+sx_status sx_set_tuning(sx_ctx *ctx, int32_t tile_hills, int32_t grid)
+{
+    if (!ctx) return SX_EINVAL;
+    if (tile_hills % kTileUnit != 0) return fail(ctx, SX_EINVAL, "tile must be a multiple of 1024 hills");
+    const int u = tile_hills / kTileUnit;
+    if (u != 1 && u != 2 && u != 4 && u != 8 && u != 16) return fail(ctx, SX_EINVAL, "tile must be 1024 * {1,2,4,8,16}");
+    if (grid < 0) return fail(ctx, SX_EINVAL, "grid must be >= 0");
+    ctx->grid = grid;
+    if (u != ctx->tile_units) {
+        ctx->tile_units = u;
+        if (ctx->bound && ctx->method == M_METAD) {
+            if (ctx->gexec) return fail(ctx, SX_ESTATE, "release the captured graph before retiling");
+            build_tiles(ctx);
+            return upload_tiles(ctx);
+        }
+    }
+    return SX_OK;
+}
+
+sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid)
+{
+    if (!ctx) return SX_EINVAL;
+    if (tile_hills) *tile_hills = ctx->tile_units * kTileUnit;
+    if (grid) *grid = ctx->grid;
+    return SX_OK;
+}
+
+sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const char *cache_path)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (ctx->method != M_METAD) return SX_OK;  // only the hill sum has launch choices
+    if (ctx->gexec) return fail(ctx, SX_ESTATE, "release the captured graph before tuning");
+    const Plan &p = ctx->plan;
+    PosView pv{};
+    const bool fuse = p.all_dihedral && pos != nullptr;
+    if (pos && !pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
+    hipDeviceProp_t prop{};
+    char name[256] = {0};
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) std::snprintf(name, sizeof name, "%s", prop.gcnArchName);
+    std::ostringstream key;
+    key << name << "/D" << p.D << "/W" << p.W << "/cap" << p.total_cap << "/fuse" << fuse;
+    std::map<std::string, std::pair<int, int>> cache;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {  // one entry per line: "key": [tile, grid]
+            auto q1 = line.find('"'), q2 = line.find('"', q1 + 1);
+            if (q1 == std::string::npos || q2 == std::string::npos) continue;
+            int t = 0, g = 0;
+            if (std::sscanf(line.c_str() + q2 + 1, ": [%d, %d]", &t, &g) == 2) cache[line.substr(q1 + 1, q2 - q1 - 1)] = {t, g};
+        }
+        auto it = cache.find(key.str());
+        if (it != cache.end()) return sx_set_tuning(ctx, it->second.first, it->second.second);
+    }
+    const int ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    const int tiles[] = {1024, 2048, 4096, 8192, 16384};
+    const int gmul[] = {0, 2, 4, 8};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ctx, SX_EDEVICE, "events");
+    float best = 1e30f;
+    int bt = 4096, bg = 0;
+    double *xi = at<double>(ctx->ws, p.w_xi);
+    sx_status st = SX_OK;
+    for (int t : tiles) {
+        if ((st = sx_set_tuning(ctx, t, 0)) != SX_OK) break;
+        for (int gm : gmul) {
+            const int g = gm ? gm * ncu : 0;
+            if (g && g >= ctx->ntiles) continue;
+            // the step's hill kernels without side effects: no deposit, no
+            // step count, no forces; CVs fused exactly as in sx_step
+            HillArgs a = hill_args(ctx, xi);
+            a.fuse = fuse;
+            a.xi_save = nullptr;
+            a.deposit = 0;
+            a.count_step = 0;
+            a.do_forces = 0;
+            for (int r = 0; r < 3; ++r) launch_hill_private(a, p.cs, pv, g, ctx->stream);
+            hipEventRecord(e0, ctx->stream);
+            const int reps = 20;
+            for (int r = 0; r < reps; ++r) launch_hill_private(a, p.cs, pv, g, ctx->stream);
+            hipEventRecord(e1, ctx->stream);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess) {
+                st = hip_fail(ctx, e, "autotune timing");
+                break;
+            }
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                bt = t;
+                bg = g;
+            }
+        }
+        if (st != SX_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != SX_OK) return st;
+    if (sx_status s = sx_set_tuning(ctx, bt, bg)) return s;
+    if (cache_path) {
+        cache[key.str()] = {bt, bg};
+        std::ofstream out(cache_path);
+        out << "{\n";
+        size_t i = 0;
+        for (auto &kv : cache)
+            out << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+                << (++i < cache.size() ? ",\n" : "\n");
+        out << "}\n";
+    }
+    return SX_OK;
+    SX_GUARD_END
+}
+
+}  // extern "C"

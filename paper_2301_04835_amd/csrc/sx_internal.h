@@ -1,0 +1,166 @@
+// Internal definitions shared by the host side of libsampx and its HIP
+// kernels.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sx {
+
+constexpr int kMaxCv = 8;        // CVs per context
+constexpr int kMaxBiasDim = 3;   // CVs a bias (hills / ABF grid) may span
+constexpr int kBlock = 256;      // threads per workgroup of the main kernels
+constexpr int kHillsPerLoad = 4; // float4 per lane
+constexpr int kTileUnit = kBlock * kHillsPerLoad;  // 1024 hills: smallest tile
+constexpr int kMaxTileUnits = 16;                  // largest tile: 16384 hills
+
+enum CvKind : int32_t { CV_DIHEDRAL = 0, CV_GYRATION = 1, CV_COORD = 2 };
+
+// Device-side flags (bit = sx_status value).
+constexpr uint32_t kFlagCapacity = 1u << 3;
+constexpr uint32_t kFlagNonFinite = 1u << 4;
+
+// Strided view of a position-like array: element (i, k) of atom i,
+// component k sits at ptr[i * sa + k * sk].
+struct PosView {
+    const void *ptr;
+    int32_t f64;  // 1: double, 0: float
+    int64_t sa, sk;
+};
+struct ForceView {
+    float *ptr;
+    int64_t sa, sk;
+};
+
+// One CV as the kernels see it.  Member atoms (walker-relative) live in the
+// slot table: slot_atom[slot0 .. slot0 + nslot).
+struct CvDesc {
+    int32_t kind;
+    int32_t d;      // index in xi
+    int32_t slot0;  // first Jacobian slot
+    int32_t na, nb; // coordination: group sizes (A slots first, then B); others: na = members
+    int32_t n, m;   // switching exponents
+    float r0, inv_r0;
+    float rcut2;    // <= 0: no cut
+    float scale;    // 1 or 1/na
+    int32_t chunk;  // coordination all-pairs: partner chunk size
+    int32_t nchunk_a, nchunk_b;  // chunks over B (for side A) and over A (side B)
+    int64_t part0;  // coordination: first partial record of this CV (per walker)
+    int32_t atom[4];  // dihedral: its four atoms (walker-relative)
+};
+
+struct CvSet {
+    int32_t ncv, D;
+    CvDesc cv[kMaxCv];
+    double box[3], inv_box[3];  // 0: open
+    int32_t nslots;
+    int64_t part_per_walker;   // coordination partial records per walker
+};
+
+// Common walker tables.
+struct WalkerTabs {
+    int32_t W;
+    const int64_t *atom_off;   // W + 1
+    const int32_t *slot_atom;  // nslots
+    const int32_t *slot_cv;    // nslots
+    const int32_t *touched;    // U walker-relative atoms touched by any CV
+    const int32_t *inv_ptr;    // U + 1
+    const int32_t *inv_slot;   // nslots: slots of touched atom u
+    int32_t U;
+};
+
+// Packed per-tile record, one 32-byte load: walker, first hill of the tile,
+// last float4 start inside the walker's capacity, hill base / 4, the
+// walker's first atom.
+struct __align__(16) TileRec {
+    int32_t w, h0, klast, hb4;
+    int64_t aoff;
+    int32_t pad[2];
+};
+// Packed per-walker record for the finalize kernel.
+struct __align__(16) WalkerRec {
+    int32_t t0, nt, cap, hb4;
+    int64_t aoff;
+    int32_t pad[2];
+};
+
+// The walker-relative force-gather table when it is small enough to travel
+// in the kernel arguments: touched atom u, its slots ent[u][0..nent[u]).
+constexpr int kSmallU = 32, kSmallPer = 8;
+struct SmallTabs {
+    int32_t on, U;
+    int32_t touched[kSmallU];
+    int32_t nent[kSmallU];
+    int32_t ent[kSmallU][kSmallPer];  // slot | cv << 20
+};
+
+// Hill-sum launch (private hill lists).
+struct HillArgs {
+    // hill storage (SoA): centres c[d][...] and heights h[...]
+    float *c[kMaxBiasDim];
+    float *h;
+    int32_t *count;            // per walker
+    const TileRec *tiles;
+    const WalkerRec *wrec;
+    int32_t ntiles, tile_units;
+    double *partial;           // ntiles x 4
+    // constants
+    int32_t D;
+    double period[kMaxBiasDim], inv_period[kMaxBiasDim];  // 0: not periodic
+    float a2[kMaxBiasDim];     // log2(e) / (2 sigma^2)
+    double inv_sig2[kMaxBiasDim];
+    // inputs / outputs
+    const double *xi;          // W x D
+    double *V_ws, *dV_ws;      // W, W x D
+    double *xi_out, *V_out, *dV_out;  // may be null
+    double *xi_save;           // fused CVs: where kernel B keeps xi (workspace)
+    int32_t count_step;        // kernel A sets the device step counter
+    int32_t fuse;              // every CV is a dihedral: xi and J computed in the hill kernels
+    // deposition
+    int32_t deposit;           // 0: never, 1: by stride, 2: always
+    int64_t step;              // < 0: device counter
+    int32_t stride;
+    double height, inv_kdT;    // inv_kdT == 0: constant height
+    int64_t *dstep;            // next step number
+    uint32_t *flags;
+    // forces
+    int32_t do_forces;
+    const float *J;            // W x nslots x 3
+    int32_t nslots;
+    WalkerTabs tabs;
+    SmallTabs small;
+    ForceView F;
+};
+
+struct AbfArgs {
+    int32_t D;
+    const double *xi;     // W x D
+    const float *J;       // W x nslots x 3
+    int32_t nslots;
+    WalkerTabs tabs;
+    PosView Fsys;         // system forces (float)
+    ForceView F;          // biased forces (+=)
+    uint32_t *N;          // W x nbins
+    double *Fsum;         // W x nbins x D
+    int64_t nbins_total;
+    double lo[kMaxBiasDim], delta[kMaxBiasDim];
+    int32_t nbins[kMaxBiasDim], periodic[kMaxBiasDim];
+    int32_t n_threshold;
+    double *xi_out, *V_out, *dV_out;
+    uint32_t *flags;
+    int64_t step;
+    int64_t *dstep;
+};
+
+// ---------------------------------------------------------------- launchers
+// Each returns the hipError_t of its launch.
+hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *cn_part,
+                     int64_t max_atoms_per_walker, hipStream_t s);
+hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s);
+hipError_t launch_abf(const AbfArgs &a, hipStream_t s);
+hipError_t launch_gather(const WalkerTabs &t, const float *J, int32_t nslots, int32_t D, const double *coef,
+                         double coef_sign, ForceView out, hipStream_t s);
+hipError_t launch_copy_xi(const double *src, double *dst, int64_t n, hipStream_t s);
+hipError_t launch_zero_bytes(void *p, int64_t nbytes, hipStream_t s);
+
+}  // namespace sx
