@@ -256,6 +256,16 @@ sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
  * hipEvents; synchronous. */
 sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const char *cache_path);
 
+/* ------------------------------------------------- measurement probes */
+/* Plain streaming read of `bytes` (multiple of 16) from device memory src
+ * with `grid` workgroups; each workgroup writes one float to sink[grid]
+ * (device).  Enqueued on `stream` (hipStream_t).  Used to calibrate the
+ * traffic counters and to measure the achievable read rate. */
+sx_status sx_probe_read(const void *src, size_t bytes, float *sink, int32_t grid, void *stream);
+/* Plain copy of `bytes` (multiple of 16) from src to dst (device, not
+ * overlapping) with `grid` workgroups, enqueued on `stream`. */
+sx_status sx_probe_copy(void *dst, const void *src, size_t bytes, int32_t grid, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,8 @@ SIGNATURES = {
     "sx_set_tuning": (i32, [P, i32, i32]),
     "sx_get_tuning": (i32, [P, P, P]),
     "sx_autotune": (i32, [P, P, i32, i32, ctypes.c_char_p]),
+    "sx_probe_read": (i32, [P, sz, P, i32, P]),
+    "sx_probe_copy": (i32, [P, P, sz, i32, P]),
 }
 
 _lib = None

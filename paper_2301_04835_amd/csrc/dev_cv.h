@@ -6,6 +6,13 @@
 
 namespace sx {
 
+template <typename T>
+__device__ __forceinline__ double3 ld_pos_t(const PosView &p, int64_t i)
+{
+    const T *q = static_cast<const T *>(p.ptr) + i * p.sa;
+    return make_double3((double)q[0], (double)q[p.sk], (double)q[2 * p.sk]);
+}
+
 __device__ __forceinline__ double3 ld_pos(const PosView &p, int64_t i)
 {
     if (p.f64) {
@@ -31,13 +38,14 @@ __device__ __forceinline__ double3 d3scale(double3 a, double s) { return make_do
 //   dphi/dr1 = (|G|/|A|^2 + F.G/(|A|^2 |G|)) A - H.G/(|B|^2 |G|) B,
 //   dphi/dr2 = -(|G|/|B|^2 - H.G/(|B|^2 |G|)) B - F.G/(|A|^2 |G|) A
 // (Blondel & Karplus 1996).  FP64 throughout.
-__device__ __forceinline__ double dihedral_fp64(const double3 (&r)[4], double3 *g /* 4 or null */)
+template <bool GRAD>
+__device__ __forceinline__ double dihedral_fp64(const double3 (&r)[4], double3 (&g)[4])
 {
     const double3 F = d3sub(r[0], r[1]), G = d3sub(r[1], r[2]), H = d3sub(r[3], r[2]);
     const double3 A = d3cross(F, G), B = d3cross(H, G);
     const double lg = sqrt(d3dot(G, G));
     const double phi = atan2(-lg * d3dot(F, B), d3dot(A, B));
-    if (g) {
+    if (GRAD) {
         const double ia = 1.0 / d3dot(A, A), ib = 1.0 / d3dot(B, B), ig = 1.0 / lg;
         const double fg = d3dot(F, G) * ia * ig, hg = d3dot(H, G) * ib * ig;
         g[0] = d3scale(A, -lg * ia);
@@ -48,13 +56,21 @@ __device__ __forceinline__ double dihedral_fp64(const double3 (&r)[4], double3 *
     return phi;
 }
 
-// Dihedral CV `cv` of the walker whose first atom is aoff.
-__device__ __forceinline__ double dihedral_at(const CvDesc &cv, const PosView &pos, int64_t aoff, double3 *g)
+// Dihedral CV `cv` of the walker whose first atom is aoff; T is the
+// position type, so the twelve coordinate loads are straight-line code.
+template <typename T, bool GRAD>
+__device__ __forceinline__ double dihedral_at_t(const CvDesc &cv, const PosView &pos, int64_t aoff, double3 (&g)[4])
 {
     double3 r[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) r[s] = ld_pos(pos, aoff + cv.atom[s]);
-    return dihedral_fp64(r, g);
+    for (int s = 0; s < 4; ++s) r[s] = ld_pos_t<T>(pos, aoff + cv.atom[s]);
+    return dihedral_fp64<GRAD>(r, g);
+}
+
+template <bool GRAD>
+__device__ __forceinline__ double dihedral_at(const CvDesc &cv, const PosView &pos, int64_t aoff, double3 (&g)[4])
+{
+    return pos.f64 ? dihedral_at_t<double, GRAD>(cv, pos, aoff, g) : dihedral_at_t<float, GRAD>(cv, pos, aoff, g);
 }
 
 }  // namespace sx

@@ -99,18 +99,88 @@ __device__ __forceinline__ void gather_forces(const WalkerTabs &t, const float *
 
 constexpr int kBatch = 4;  // float4 groups loaded per lane before use
 
-template <int D, int U, bool FUSE>
-__global__ void __launch_bounds__(kBlock) k_hill_tiles(HillArgs a, CvSet cs, PosView pos)
+// Dihedral `cv` (CV index d) of the tile's walker, FP64.  Writes xi to the
+// workgroup's LDS slot; the walker's first tile also keeps xi and the
+// Jacobian rows in the workspace for kernel B.
+// Loads through the constant address space: the value is the same for the
+// whole workgroup and does not change while the kernel runs, so it comes
+// through the scalar cache into SGPRs.
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T *p)
 {
-    __shared__ double lds[(1 + D) * (kBlock / 64)];
-    __shared__ double s_xi[D];
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) T *)(p);
+#else
+    return *p;
+#endif
+}
+
+// Lane d (< D) of wave 0 evaluates dihedral d of the tile's walker (FP64).
+// The atom indices are selected from the kernel arguments with selects, not
+// memory loads.  The walker's first tile also keeps xi and the Jacobian rows
+// in the workspace for kernel B.
+template <int D>
+__device__ __forceinline__ void fused_dihedrals(const HillArgs &a, const CvSet &cs, const PosView &pos,
+                                                const TileRec &tr, double *s_xi)
+{
+    const int d = threadIdx.x;
+    CvDesc cv = cs.cv[0];
+    int32_t at[4] = {cs.cv[0].atom[0], cs.cv[0].atom[1], cs.cv[0].atom[2], cs.cv[0].atom[3]};
+    int32_t slot0 = cs.cv[0].slot0;
+#pragma unroll
+    for (int dd = 1; dd < D; ++dd) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) at[q] = d == dd ? cs.cv[dd].atom[q] : at[q];
+        slot0 = d == dd ? cs.cv[dd].slot0 : slot0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cv.atom[q] = at[q];
+    double3 g[4];
+    if (tr.h0 == 0 && a.do_forces) {
+        const double phi = dihedral_at<true>(cv, pos, tr.aoff, g);
+        s_xi[d] = phi;
+        a.xi_save[(int64_t)tr.w * D + d] = phi;
+        float *J = a.J + ((int64_t)tr.w * a.nslots + slot0) * 3;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            J[q * 3 + 0] = (float)g[q].x;
+            J[q * 3 + 1] = (float)g[q].y;
+            J[q * 3 + 2] = (float)g[q].z;
+        }
+    } else {
+        const double phi = dihedral_at<false>(cv, pos, tr.aoff, g);
+        s_xi[d] = phi;
+        if (tr.h0 == 0) a.xi_save[(int64_t)tr.w * D + d] = phi;
+    }
+}
+
+// Kernel A.  One tile per loop trip (persistent when the grid is smaller
+// than the tile count).  Load pattern per lane and batch: UB float4 of each
+// centre array and of the heights at float4 index q0 + u * kBlock, from
+// uniform (scalar) base pointers with 32-bit lane offsets; the scheduling
+// barrier keeps every load of the batch ahead of the arithmetic.
+// One tile: partial (V, sum e D_d) of hills [h0, h0 + 1024 U) of one walker.
+template <int D, int U, bool FUSE>
+__device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, const PosView &pos, int t, double *lds,
+                                          double *s_xi)
+{
     constexpr int UB = U < kBatch ? U : kBatch;
-    if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
-    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        const TileRec tr = a.tiles[t];
-        const int32_t w = tr.w, h0 = tr.h0, klast = tr.klast;
+        const TileRec tr = ld_uniform(a.tiles + t);
+        const int32_t w = tr.w;
         const int64_t hb = (int64_t)tr.hb4 * 4;
-        const int32_t n = a.count[w];
+        const float4 *cb[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) cb[d] = reinterpret_cast<const float4 *>(a.c[d] + hb);
+        const float4 *hp = reinterpret_cast<const float4 *>(a.h + hb);
+        const uint32_t q0 = (uint32_t)(tr.h0 / kHillsPerLoad) + threadIdx.x;
+        const uint32_t qlast = (uint32_t)(tr.klast / kHillsPerLoad);
+        const int32_t n = ld_uniform(a.count + w);
+        // fused CVs: lane d of wave 0 evaluates dihedral d (FP64) before any
+        // hill load is issued, so the angle's registers and the hill batch's
+        // registers are never live together; the other waves go straight to
+        // their loads and meet wave 0 at the barrier below.
+        if (FUSE && (int)threadIdx.x < D) fused_dihedrals<D>(a, cs, pos, tr, s_xi);
+        __builtin_amdgcn_sched_barrier(0);
         double xi[D];
         double acc[1 + D];
 #pragma unroll
@@ -120,14 +190,14 @@ __global__ void __launch_bounds__(kBlock) k_hill_tiles(HillArgs a, CvSet cs, Pos
             float4 cv[UB][D], hv[UB];
 #pragma unroll
             for (int q = 0; q < UB; ++q) {
-                const int32_t k = min(h0 + ((ub + q) * kBlock + (int)threadIdx.x) * kHillsPerLoad, klast);
+                const uint32_t qi = min(q0 + (uint32_t)((ub + q) * kBlock), qlast);
 #pragma unroll
-                for (int d = 0; d < D; ++d) cv[q][d] = *reinterpret_cast<const float4 *>(a.c[d] + hb + k);
-                hv[q] = *reinterpret_cast<const float4 *>(a.h + hb + k);
+                for (int d = 0; d < D; ++d) cv[q][d] = cb[d][qi];
+                hv[q] = hp[qi];
             }
+            __builtin_amdgcn_sched_barrier(0);
             if (ub == 0) {
                 if (FUSE) {
-                    if ((int)threadIdx.x < D) s_xi[threadIdx.x] = dihedral_at(cs.cv[threadIdx.x], pos, tr.aoff, nullptr);
                     __syncthreads();
 #pragma unroll
                     for (int d = 0; d < D; ++d) xi[d] = s_xi[d];
@@ -138,7 +208,7 @@ __global__ void __launch_bounds__(kBlock) k_hill_tiles(HillArgs a, CvSet cs, Pos
             }
 #pragma unroll
             for (int q = 0; q < UB; ++q) {
-                const int32_t k = h0 + ((ub + q) * kBlock + (int)threadIdx.x) * kHillsPerLoad;
+                const int32_t k = (int32_t)(q0 + (uint32_t)((ub + q) * kBlock)) * kHillsPerLoad;
                 float sv = 0.f, sg[D];
 #pragma unroll
                 for (int d = 0; d < D; ++d) sg[d] = 0.f;
@@ -164,6 +234,29 @@ __global__ void __launch_bounds__(kBlock) k_hill_tiles(HillArgs a, CvSet cs, Pos
 #pragma unroll
             for (int j = 0; j <= D; ++j) p[j] = acc[j];
         }
+}
+
+// One workgroup per tile: the tile record is read before any store, so it
+// comes through the scalar cache.
+template <int D, int U, bool FUSE>
+__global__ void __launch_bounds__(kBlock) k_hill_tiles(HillArgs a, CvSet cs, PosView pos)
+{
+    __shared__ double lds[(1 + D) * (kBlock / 64)];
+    __shared__ double s_xi[D];
+    if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
+    hill_tile<D, U, FUSE>(a, cs, pos, blockIdx.x, lds, s_xi);
+}
+
+// Persistent grid: each workgroup strides over the tiles.
+template <int D, int U, bool FUSE>
+__global__ void __launch_bounds__(kBlock) k_hill_tiles_persist(HillArgs a, CvSet cs, PosView pos)
+{
+    __shared__ double lds[(1 + D) * (kBlock / 64)];
+    __shared__ double s_xi[D];
+    if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        hill_tile<D, U, FUSE>(a, cs, pos, __builtin_amdgcn_readfirstlane(t), lds, s_xi);
+        __syncthreads();  // lds / s_xi reuse by the next tile
     }
 }
 
@@ -181,9 +274,8 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     __shared__ double lds[(1 + D) * (kBlock / 64)];
     __shared__ double s_coef[kMaxCv];
     __shared__ double s_xi[kMaxBiasDim];
-    __shared__ float s_J[kMaxBiasDim * 4 * 3];
     const int32_t w = blockIdx.x;
-    const WalkerRec wr = a.wrec[w];
+    const WalkerRec wr = ld_uniform(a.wrec + w);
     // small gather table: prefetch the forces this lane will update
     SmallGather sg{0.f, 0.f, 0.f, nullptr};
     const bool small_lane = a.do_forces && a.small.on && (int)threadIdx.x < a.small.U;
@@ -193,21 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
         sg.f1 = sg.dst[a.F.sk];
         sg.f2 = sg.dst[2 * a.F.sk];
     }
-    if ((int)threadIdx.x < D) {
-        if (FUSE) {
-            double3 g[4];
-            const CvDesc &cv = cs.cv[threadIdx.x];
-            s_xi[threadIdx.x] = dihedral_at(cv, pos, wr.aoff, a.do_forces ? g : nullptr);
-            if (a.do_forces)
-                for (int q = 0; q < 4; ++q) {
-                    s_J[(cv.slot0 + q) * 3 + 0] = (float)g[q].x;
-                    s_J[(cv.slot0 + q) * 3 + 1] = (float)g[q].y;
-                    s_J[(cv.slot0 + q) * 3 + 2] = (float)g[q].z;
-                }
-        } else {
-            s_xi[threadIdx.x] = a.xi[(int64_t)w * D + threadIdx.x];
-        }
-    }
+    if ((int)threadIdx.x < D) s_xi[threadIdx.x] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + threadIdx.x];
     double acc[1 + D];
 #pragma unroll
     for (int j = 0; j <= D; ++j) acc[j] = 0.0;
@@ -216,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
 #pragma unroll
         for (int j = 0; j <= D; ++j) acc[j] += p[j];
     }
-    block_sum0<1 + D>(acc, lds);  // also orders the s_xi / s_J writes
+    block_sum0<1 + D>(acc, lds);  // also orders the s_xi writes
     if (threadIdx.x == 0) {
         const double V = acc[0];
         bool finite = isfinite(V);
@@ -225,9 +303,6 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
         if (a.xi_out)
 #pragma unroll
             for (int d = 0; d < D; ++d) a.xi_out[(int64_t)w * D + d] = s_xi[d];
-        if (FUSE && a.xi_save)
-#pragma unroll
-            for (int d = 0; d < D; ++d) a.xi_save[(int64_t)w * D + d] = s_xi[d];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const double dv = -acc[1 + d] * a.inv_sig2[d];
@@ -254,7 +329,7 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     }
     __syncthreads();
     if (!a.do_forces) return;
-    const float *Jw = FUSE ? s_J : a.J + (int64_t)w * a.nslots * 3;
+    const float *Jw = a.J + (int64_t)w * a.nslots * 3;
     if (a.small.on) {
         if (small_lane) {
             double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -279,14 +354,23 @@ template <int D, bool FUSE>
 hipError_t launch_hill_d(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s)
 {
     const int g = (grid > 0 && grid < a.ntiles) ? grid : a.ntiles;
+    const bool persist = g < a.ntiles;
+#define SX_TILE_CASE(UU)                                                                                       \
+    case UU:                                                                                                   \
+        if (persist)                                                                                           \
+            hipLaunchKernelGGL((k_hill_tiles_persist<D, UU, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_hill_tiles<D, UU, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos);         \
+        break;
     switch (a.tile_units) {
-    case 1: hipLaunchKernelGGL((k_hill_tiles<D, 1, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
-    case 2: hipLaunchKernelGGL((k_hill_tiles<D, 2, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
-    case 4: hipLaunchKernelGGL((k_hill_tiles<D, 4, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
-    case 8: hipLaunchKernelGGL((k_hill_tiles<D, 8, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
-    case 16: hipLaunchKernelGGL((k_hill_tiles<D, 16, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); break;
+        SX_TILE_CASE(1)
+        SX_TILE_CASE(2)
+        SX_TILE_CASE(4)
+        SX_TILE_CASE(8)
+        SX_TILE_CASE(16)
     default: return hipErrorInvalidValue;
     }
+#undef SX_TILE_CASE
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_hill_finalize<D, FUSE>), dim3(a.tabs.W), dim3(kBlock), 0, s, a, cs, pos);

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kBlock) k_dihedral(CvSet cs, WalkerTabs t, Pos
         if (cs.cv[c].kind == CV_DIHEDRAL && seen++ == j) break;
     const CvDesc cv = cs.cv[c];
     double3 g[4];
-    const double phi = dihedral_at(cv, pos, t.atom_off[w], J ? g : nullptr);
+    const double phi = J ? dihedral_at<true>(cv, pos, t.atom_off[w], g) : dihedral_at<false>(cv, pos, t.atom_off[w], g);
     xi[(int64_t)w * cs.D + cv.d] = phi;
     if (J) {
         const int64_t sb = (int64_t)w * cs.nslots + cv.slot0;

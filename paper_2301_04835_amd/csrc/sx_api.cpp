@@ -1186,7 +1186,7 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
             // step count, no forces; CVs fused exactly as in sx_step
             HillArgs a = hill_args(ctx, xi);
             a.fuse = fuse;
-            a.xi_save = nullptr;
+            a.xi_save = xi;  // fused kernels rewrite the same CV values here
             a.deposit = 0;
             a.count_step = 0;
             a.do_forces = 0;

@@ -125,7 +125,7 @@ struct HillArgs {
     uint32_t *flags;
     // forces
     int32_t do_forces;
-    const float *J;            // W x nslots x 3
+    float *J;                  // W x nslots x 3 (fused dihedrals: written by kernel A)
     int32_t nslots;
     WalkerTabs tabs;
     SmallTabs small;

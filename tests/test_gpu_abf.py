@@ -1,0 +1,137 @@
+"""GPU parity of the adaptive-biasing-force path against the FP64 oracle.
+
+Per step: xi, the bias along xi (-dV/dxi = b) and the atom forces; after the
+run: the histogram (exact, integer) and the force sums.  theta is formed
+from the float32 Jacobian on the GPU and the FP64 one in the oracle, so the
+grid sums compare to 1e-5 relative; bins whose edge lies within the CV
+tolerance of a sample are reported (none occur with these seeds).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2301_04835_amd import Sampler, synth
+
+from gpu_util import dev, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def run_abf(cvs, box, frames, fsys, n_atoms, lo, hi, nbins, thr, atom_off=None):
+    """GPU: write each frame's active atoms into the engine buffer, step."""
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    if box is not None:
+        s.set_box(box)
+    W = 1 if atom_off is None else len(atom_off) - 1
+    s.set_walkers(np.array([0, n_atoms]) if atom_off is None else atom_off)
+    s.abf(lo, hi, nbins, thr)
+    s.bind()
+    T, nact = frames.shape[0], frames.shape[1]
+    D = len(cvs)
+    P = torch.zeros((n_atoms, 3), dtype=torch.float32, device="cuda")
+    Fs = torch.zeros_like(P)
+    fr, ff = dev(frames), dev(fsys)
+    xi = torch.zeros((T, W, D), dtype=torch.float64, device="cuda")
+    dV = torch.zeros((T, W, D), dtype=torch.float64, device="cuda")
+    F = torch.zeros((T, nact, 3), dtype=torch.float32, device="cuda")
+    Fbuf = torch.zeros_like(P)
+    for t in range(T):
+        P[:nact] = fr[t]
+        Fs[:nact] = ff[t]
+        Fbuf.zero_()
+        s.step(P, forces=Fbuf, step=t, xi_out=xi[t], dV_out=dV[t], sys_forces=Fs)
+        F[t] = Fbuf[:nact]
+    s.check()
+    grids = [s.abf_grid(w) for w in range(W)]
+    return s, xi.cpu().numpy(), dV.cpu().numpy(), F.cpu().numpy(), grids
+
+
+def near_edge(x, lo, hi, nb, tol):
+    u = (x - lo) / ((hi - lo) / nb)
+    return abs(u - np.rint(u)) < tol * max(1.0, abs(u))
+
+
+def test_abf50k_full_size_300_steps(gpu):
+    p = synth.ABF50K
+    cvs = synth.abf50k_cvs()
+    box = np.full(3, p["box"])
+    T = 300
+    frames, fsys = synth.abf50k_frames(T, seed=2)
+    s, xi, dV, F, grids = run_abf(cvs, box, frames, fsys, p["n_atoms"], p["lo"], p["hi"], p["nbins"],
+                                  p["n_threshold"])
+    g = oracle.AbfGrid(p["lo"], p["hi"], p["nbins"], [False, False], p["n_threshold"])
+    worst = {"xi_rg": 0.0, "xi_cn": 0.0, "b": 0.0, "F": 0.0}
+    amb = 0
+    for t in range(T):
+        x, J = oracle.cv_eval(frames[t].astype(np.float64), cvs, box)
+        b, Fb, k, th = oracle.abf_step(g, x, J, fsys[t].astype(np.float64))
+        worst["xi_rg"] = max(worst["xi_rg"], abs(xi[t, 0, 0] - x[0]) / x[0])
+        worst["xi_cn"] = max(worst["xi_cn"], abs(xi[t, 0, 1] - x[1]) / x[1])
+        if np.any(b != 0):
+            worst["b"] = max(worst["b"], rel_inf(-dV[t, 0], b))
+            worst["F"] = max(worst["F"], rel_inf(F[t], Fb))
+        else:
+            assert np.all(dV[t, 0] == 0) and np.all(F[t] == 0)
+        amb += any(near_edge(x[d], p["lo"][d], p["hi"][d], p["nbins"][d], 1e-6) for d in range(2))
+    print("worst:", worst, "ambiguous samples:", amb)
+    assert amb == 0
+    assert worst["xi_rg"] <= 1e-9 and worst["xi_cn"] <= 1e-6
+    assert worst["b"] <= 1e-5 and worst["F"] <= 1e-5
+    N, Fsum = grids[0]
+    assert np.array_equal(N.astype(np.int64), g.N)
+    assert N.sum() == T  # every sample in range with this grid
+    nz = g.N > 0
+    assert rel_inf(Fsum[nz], g.Fsum[nz]) <= 1e-5
+    assert s.get_step() == T
+
+
+def test_abf_dihedrals_periodic_bins_walkers(gpu):
+    """phi/psi of three walkers: periodic bins (50 per CV, the alanine
+    dipeptide grid of the appendix), shared atoms in the Gram matrix,
+    a low threshold so the bias is exercised, per-walker grids."""
+    W, n, T = 3, 22, 400
+    tmpl = synth.chain_template(n, 5)
+    g0 = np.random.default_rng(8)
+    frames = np.stack([synth.noisy_frames(tmpl, T, 10 + w, 0.15, np.float32) for w in range(W)], axis=1)
+    frames = frames.reshape(T, W * n, 3)
+    fsys = g0.normal(0, 50.0, size=(T, W * n, 3)).astype(np.float32)
+    cvs = synth.backbone_cvs(4)
+    lo, hi, nb, thr = [-np.pi, -np.pi], [np.pi, np.pi], [50, 50], 5
+    off = np.arange(W + 1) * n
+    s, xi, dV, F, grids = run_abf(cvs, None, frames, fsys, W * n, lo, hi, nb, thr, atom_off=off)
+    for w in range(W):
+        g = oracle.AbfGrid(lo, hi, nb, [True, True], thr)
+        errF = errb = 0.0
+        for t in range(T):
+            sl = slice(off[w], off[w + 1])
+            x, J = oracle.cv_eval(frames[t, sl].astype(np.float64), cvs)
+            assert not any(near_edge(x[d], lo[d], hi[d], nb[d], 1e-9) for d in range(2))
+            b, Fb, k, th = oracle.abf_step(g, x, J, fsys[t, sl].astype(np.float64))
+            assert np.max(np.abs(xi[t, w] - x)) <= 1e-9
+            errb = max(errb, rel_inf(-dV[t, w], b) if np.any(b) else np.max(np.abs(dV[t, w])))
+            errF = max(errF, rel_inf(F[t, sl], Fb) if np.any(b) else np.max(np.abs(F[t, sl])))
+        N, Fsum = grids[w]
+        assert np.array_equal(N.astype(np.int64), g.N)
+        assert rel_inf(Fsum[g.N > 0], g.Fsum[g.N > 0]) <= 1e-5
+        assert errb <= 1e-5 and errF <= 1e-5, (w, errb, errF)
+
+
+def test_abf_out_of_range_samples_are_dropped(gpu):
+    cvs = synth.backbone_cvs(4)
+    tmpl = synth.chain_template(22, 5)
+    frames = synth.noisy_frames(tmpl, 20, 3, 0.02, np.float32)
+    fsys = np.random.default_rng(1).normal(0, 10, size=frames.shape).astype(np.float32)
+    # the second CV (Rg of 8 atoms, ~0.2 nm) never reaches the grid [10, 11)
+    s = Sampler(0)
+    s.add_dihedral(cvs[0]["idx"])
+    s.add_gyration(list(range(4, 12)))  # non-periodic second CV
+    s.abf([-np.pi, 10.0], [np.pi, 11.0], [10, 10], 0)
+    s.bind()
+    P = dev(frames[0])
+    Fb = torch.zeros_like(P)
+    dV = torch.ones((1, 2), dtype=torch.float64, device="cuda")
+    s.step(P, forces=Fb, step=0, dV_out=dV, sys_forces=dev(fsys[0]))
+    N, _ = s.abf_grid(0)
+    assert N.sum() == 0 and torch.all(dV == 0) and torch.all(Fb == 0)
