@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU sample")
     ap.add_argument("--hill-reps", type=int, default=200, help="launches timed for the hill-sum kernel")
+    ap.add_argument("--probe-copy-mb", type=int, default=0,
+                    help="after the run, copy this many MiB with the plain copy probe (counter calibration)")
     return ap.parse_args()
 
 
@@ -55,6 +57,25 @@ def build_context(d, p):
     pos = torch.from_numpy(d["pos"]).cuda()
     forces = torch.zeros_like(pos)
     return s, pos, forces
+
+
+def measured_traffic(bytes_per_launch):
+    """HBM bytes per launch of the tile kernel from the committed counter
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hill_tiles_walkers256_traffic.txt")
+    src = os.path.join(ROOT, "paper_2301_04835_amd", "csrc", "k_bias.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("k_bias_sha") != sha or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(d, p, target_s):
@@ -135,21 +156,13 @@ def main():
     ev_ms_step = e0.elapsed_time(e1) / steps
     # hill counts after the run (deposits every `stride` steps add hills)
     counts_total = int(np.sum(s.hill_counts()))
-    # hill-sum kernel alone: events around back-to-back launches on the
-    # context's stream (same kernel, tiles and hills as in the step)
-    xi_now = xi.clone()
-    for _ in range(10):
-        s.hillsum(xi_now)
-    torch.cuda.synchronize()
-    h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    h0.record(stream)
-    for _ in range(args.hill_reps):
-        s.hillsum(xi_now)
-    h1.record(stream)
-    torch.cuda.synchronize()
-    hill_ms = h0.elapsed_time(h1) / args.hill_reps
+    # the step's hill-sum kernels alone: hipEvents around back-to-back
+    # launches on the context's stream (same configuration as the step;
+    # no deposition), tile kernel (A) and finalize kernel (B) separately
+    ms_a, ms_b = s.time_hill(pos, forces=forces, reps=args.hill_reps)
     bytes_per_launch = counts_total * 12  # 2 float32 centres + 1 float32 height per hill
-    achieved = bytes_per_launch / (hill_ms * 1e-3) / 1e9
+    achieved = bytes_per_launch / (ms_a * 1e-3) / 1e9
+    traffic = measured_traffic(bytes_per_launch)
     out = {
         "metric": "biased steps/s (CV+bias+force), 256 walkers",
         "value": steps / wall,
@@ -169,10 +182,19 @@ def main():
                    "tile_hills": tile, "grid": grid, "graph_steps": gsteps},
         "hill_evals_per_s": counts_total * steps / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_hill_private<2,%d>" % (tile // 1024), "kernel_ms": hill_ms,
-                     "bytes_per_launch": bytes_per_launch},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_hill_tiles<2,%d,fused>" % (tile // 1024), "kernel_ms": ms_a,
+                     "finalize_kernel_ms": ms_b, "bytes_per_launch": bytes_per_launch},
     }
+    if args.probe_copy_mb:
+        import ctypes
+        nb = args.probe_copy_mb << 20
+        src = torch.ones(nb // 4, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            s.L.sx_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nb, 2048,
+                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, p, args.cpu_seconds)
     print(json.dumps(out))

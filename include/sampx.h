@@ -214,8 +214,15 @@ sx_status sx_cv_vjp(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout,
  * xi[W][D] (all device).  No deposition, no forces. */
 sx_status sx_hillsum(sx_ctx *ctx, const double *xi, double *V_out, double *dVdxi_out);
 /* Deposit one hill per walker at xi[W][D] (device) now, whatever the step,
- * with the well-tempered height from the current bias at xi. */
+ * with the well-tempered height from the current bias at xi.  With a shared
+ * list the W hills are appended in walker order, all or none. */
 sx_status sx_deposit(sx_ctx *ctx, const double *xi);
+/* Metadynamics bias of one hill list at n arbitrary points: xi[n][D] ->
+ * V_out[n], dVdxi_out[n][D] (device; outputs may be NULL).  walker selects
+ * the private list (ignored with a shared list).  Same arithmetic as the
+ * step's sum; evaluated in batches of 65536 points.  Used for surrogate
+ * training labels and certification. */
+sx_status sx_bias_eval(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double *V_out, double *dVdxi_out);
 
 /* ------------------------------------------------------------ state I/O */
 /* Host copies, synchronous.  Walker -1 (or any walker) addresses the shared
@@ -241,8 +248,8 @@ sx_status sx_graph_capture(sx_ctx *ctx, int32_t n_steps, const void *pos, int32_
                            double *xi_out, double *V_out, double *dVdxi_out, float *forces,
                            const float *sys_forces);
 sx_status sx_graph_launch(sx_ctx *ctx);
-/* Launch parameters of the hill-sum kernel: hills per tile (multiple of
- * 1024, at most 16384) and persistent grid size (0: one workgroup per
+/* Launch parameters of the hill-sum kernel: hills per tile (1024, 2048,
+ * 4096 or 8192) and persistent grid size (0: one workgroup per
  * tile).  Changing the tile rebuilds the tile table (host, synchronous). */
 sx_status sx_set_tuning(sx_ctx *ctx, int32_t tile_hills, int32_t grid);
 sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
@@ -257,6 +264,15 @@ sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
 sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const char *cache_path);
 
 /* ------------------------------------------------- measurement probes */
+/* Average duration of the step's two hill-sum kernels: `reps` back-to-back
+ * launches of the tile kernel, then `reps` of the finalize kernel, bracketed
+ * by hipEvents on the context's stream, with the step's configuration (CVs
+ * from pos as sx_step evaluates them; tiling as tuned).  Nothing is
+ * deposited and the step counter is untouched; if forces (device, layout of
+ * pos) is not NULL the bias force is added to it `reps` times.
+ * Synchronous.  ms_tiles / ms_finalize: host, milliseconds per launch. */
+sx_status sx_time_hill(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
+                       float *ms_tiles, float *ms_finalize);
 /* Plain streaming read of `bytes` (multiple of 16) from device memory src
  * with `grid` workgroups; each workgroup writes one float to sink[grid]
  * (device).  Enqueued on `stream` (hipStream_t).  Used to calibrate the

@@ -49,6 +49,7 @@ SIGNATURES = {
     "sx_cv_vjp": (i32, [P, P, i32, i32, P, P]),
     "sx_hillsum": (i32, [P, P, P, P]),
     "sx_deposit": (i32, [P, P]),
+    "sx_bias_eval": (i32, [P, i32, P, i64, P, P]),
     "sx_hills_set": (i32, [P, i32, P, P, i64]),
     "sx_hills_get": (i32, [P, i32, P, P, i64, P]),
     "sx_abf_grid_get": (i32, [P, i32, P, P]),
@@ -61,6 +62,7 @@ SIGNATURES = {
     "sx_set_tuning": (i32, [P, i32, i32]),
     "sx_get_tuning": (i32, [P, P, P]),
     "sx_autotune": (i32, [P, P, i32, i32, ctypes.c_char_p]),
+    "sx_time_hill": (i32, [P, P, i32, i32, P, i32, P, P]),
     "sx_probe_read": (i32, [P, sz, P, i32, P]),
     "sx_probe_copy": (i32, [P, P, sz, i32, P]),
 }

@@ -196,6 +196,15 @@ class Sampler:
         self._check(self.L.sx_hillsum(self.h, _ptr(xi), _ptr(V), _ptr(dV)))
         return V, dV
 
+    def bias_eval(self, xi, walker=0, grad=True):
+        """Bias V and dV/dxi of a hill list at query points xi (n x D, device
+        float64): the step's arithmetic at arbitrary points."""
+        n = xi.shape[0]
+        V = torch.empty(n, dtype=torch.float64, device=self.device)
+        dV = torch.empty((n, self.D), dtype=torch.float64, device=self.device) if grad else None
+        self._check(self.L.sx_bias_eval(self.h, int(walker), _ptr(xi.contiguous()), n, _ptr(V), _ptr(dV)))
+        return V, dV
+
     def deposit(self, xi):
         self._check(self.L.sx_deposit(self.h, _ptr(xi)))
 
@@ -265,6 +274,14 @@ class Sampler:
         g = ctypes.c_int32()
         self._check(self.L.sx_get_tuning(self.h, ctypes.byref(t), ctypes.byref(g)))
         return t.value, g.value
+
+    def time_hill(self, pos, forces=None, reps=100, layout="aos3"):
+        """(ms per tile-kernel launch, ms per finalize-kernel launch) measured
+        with hipEvents on the context's stream (see sx_time_hill)."""
+        m1, m2 = ctypes.c_float(), ctypes.c_float()
+        self._check(self.L.sx_time_hill(self.h, _ptr(pos), _pos_dtype(pos), _LAYOUTS[layout], _ptr(forces), int(reps),
+                                        ctypes.byref(m1), ctypes.byref(m2)))
+        return m1.value, m2.value
 
     def autotune(self, pos=None, cache_path=None, layout="aos3"):
         """Pick the hill-sum tiling by timing the step's kernels (see sx_autotune)."""

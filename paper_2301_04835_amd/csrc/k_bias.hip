@@ -97,7 +97,7 @@ __device__ __forceinline__ void gather_forces(const WalkerTabs &t, const float *
     }
 }
 
-constexpr int kBatch = 4;  // float4 groups loaded per lane before use
+constexpr int kBatch = 8;  // float4 groups loaded per lane before use
 
 // Dihedral `cv` (CV index d) of the tile's walker, FP64.  Writes xi to the
 // workgroup's LDS slot; the walker's first tile also keeps xi and the
@@ -115,29 +115,61 @@ __device__ __forceinline__ T ld_uniform(const T *p)
 #endif
 }
 
-// Lane d (< D) of wave 0 evaluates dihedral d of the tile's walker (FP64).
-// The atom indices are selected from the kernel arguments with selects, not
-// memory loads.  The walker's first tile also keeps xi and the Jacobian rows
-// in the workspace for kernel B.
+// Lane d (< D) of wave 0 evaluates dihedral d of the tile's walker (FP64):
+// first its four positions are requested (atom indices selected from the
+// kernel arguments with selects, not loads), then -- after the hill loads
+// of the tile are in flight -- the angle is computed.  The walker's first
+// tile also keeps xi and the Jacobian rows in the workspace for kernel B.
 template <int D>
-__device__ __forceinline__ void fused_dihedrals(const HillArgs &a, const CvSet &cs, const PosView &pos,
-                                                const TileRec &tr, double *s_xi)
+__device__ __forceinline__ int32_t dihedral_atom(const CvSet &cs, int d, int q)
+{
+    int32_t at = cs.cv[0].atom[q];
+#pragma unroll
+    for (int dd = 1; dd < D; ++dd) at = d == dd ? cs.cv[dd].atom[q] : at;
+    return at;
+}
+
+// Raw coordinates of a dihedral's four atoms as loaded (T: the position
+// type); conversion waits until the values are used, so the loads stay in
+// flight while the hill loads are issued.
+template <typename T>
+struct RawAtoms {
+    T v[12];
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void fetch_dihedral_atoms(const CvSet &cs, const PosView &pos, int64_t aoff,
+                                                     RawAtoms<T> &ra)
 {
     const int d = threadIdx.x;
-    CvDesc cv = cs.cv[0];
-    int32_t at[4] = {cs.cv[0].atom[0], cs.cv[0].atom[1], cs.cv[0].atom[2], cs.cv[0].atom[3]};
-    int32_t slot0 = cs.cv[0].slot0;
 #pragma unroll
-    for (int dd = 1; dd < D; ++dd) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) at[q] = d == dd ? cs.cv[dd].atom[q] : at[q];
-        slot0 = d == dd ? cs.cv[dd].slot0 : slot0;
+    for (int q = 0; q < 4; ++q) {
+        const T *p = static_cast<const T *>(pos.ptr) + (aoff + dihedral_atom<D>(cs, d, q)) * pos.sa;
+        ra.v[3 * q + 0] = p[0];
+        ra.v[3 * q + 1] = p[pos.sk];
+        ra.v[3 * q + 2] = p[2 * pos.sk];
     }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void finish_dihedral(const HillArgs &a, const CvSet &cs, const TileRec &tr,
+                                                const RawAtoms<T> &ra, double *s_xi)
+{
+    const int d = threadIdx.x;
+    T v[12];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) cv.atom[q] = at[q];
-    double3 g[4];
+    for (int k = 0; k < 12; ++k) {
+        v[k] = ra.v[k];
+        asm volatile("" : "+v"(v[k]));  // keep the use (and the wait) here, after the hill loads
+    }
+    double3 r[4], g[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = make_double3((double)v[3 * q], (double)v[3 * q + 1], (double)v[3 * q + 2]);
     if (tr.h0 == 0 && a.do_forces) {
-        const double phi = dihedral_at<true>(cv, pos, tr.aoff, g);
+        int32_t slot0 = cs.cv[0].slot0;
+#pragma unroll
+        for (int dd = 1; dd < D; ++dd) slot0 = d == dd ? cs.cv[dd].slot0 : slot0;
+        const double phi = dihedral_fp64<true>(r, g);
         s_xi[d] = phi;
         a.xi_save[(int64_t)tr.w * D + d] = phi;
         float *J = a.J + ((int64_t)tr.w * a.nslots + slot0) * 3;
@@ -148,7 +180,7 @@ __device__ __forceinline__ void fused_dihedrals(const HillArgs &a, const CvSet &
             J[q * 3 + 2] = (float)g[q].z;
         }
     } else {
-        const double phi = dihedral_at<false>(cv, pos, tr.aoff, g);
+        const double phi = dihedral_fp64<false>(r, g);
         s_xi[d] = phi;
         if (tr.h0 == 0) a.xi_save[(int64_t)tr.w * D + d] = phi;
     }
@@ -160,12 +192,14 @@ __device__ __forceinline__ void fused_dihedrals(const HillArgs &a, const CvSet &
 // uniform (scalar) base pointers with 32-bit lane offsets; the scheduling
 // barrier keeps every load of the batch ahead of the arithmetic.
 // One tile: partial (V, sum e D_d) of hills [h0, h0 + 1024 U) of one walker.
-template <int D, int U, bool FUSE>
+template <int D, int U, bool FUSE, typename T>
 __device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, const PosView &pos, int t, double *lds,
                                           double *s_xi)
 {
     constexpr int UB = U < kBatch ? U : kBatch;
         const TileRec tr = ld_uniform(a.tiles + t);
+        const int64_t aoff = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(tr.aoff_hi) << 32) |
+                                       (uint32_t)__builtin_amdgcn_readfirstlane(tr.aoff_lo));
         const int32_t w = tr.w;
         const int64_t hb = (int64_t)tr.hb4 * 4;
         const float4 *cb[D];
@@ -175,11 +209,12 @@ __device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, co
         const uint32_t q0 = (uint32_t)(tr.h0 / kHillsPerLoad) + threadIdx.x;
         const uint32_t qlast = (uint32_t)(tr.klast / kHillsPerLoad);
         const int32_t n = ld_uniform(a.count + w);
-        // fused CVs: lane d of wave 0 evaluates dihedral d (FP64) before any
-        // hill load is issued, so the angle's registers and the hill batch's
-        // registers are never live together; the other waves go straight to
-        // their loads and meet wave 0 at the barrier below.
-        if (FUSE && (int)threadIdx.x < D) fused_dihedrals<D>(a, cs, pos, tr, s_xi);
+        // fused CVs: lane d of wave 0 requests the positions of dihedral d
+        // before the hill loads, computes the angle (FP64) while those are
+        // in flight, and meets the other waves at the barrier below
+        const bool cv_lane = FUSE && (int)threadIdx.x < D;
+        RawAtoms<T> ra;
+        if (cv_lane) fetch_dihedral_atoms<D, T>(cs, pos, aoff, ra);
         __builtin_amdgcn_sched_barrier(0);
         double xi[D];
         double acc[1 + D];
@@ -198,6 +233,7 @@ __device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, co
             __builtin_amdgcn_sched_barrier(0);
             if (ub == 0) {
                 if (FUSE) {
+                    if (cv_lane) finish_dihedral<D, T>(a, cs, tr, ra, s_xi);
                     __syncthreads();
 #pragma unroll
                     for (int d = 0; d < D; ++d) xi[d] = s_xi[d];
@@ -238,24 +274,24 @@ __device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, co
 
 // One workgroup per tile: the tile record is read before any store, so it
 // comes through the scalar cache.
-template <int D, int U, bool FUSE>
+template <int D, int U, bool FUSE, typename T>
 __global__ void __launch_bounds__(kBlock) k_hill_tiles(HillArgs a, CvSet cs, PosView pos)
 {
     __shared__ double lds[(1 + D) * (kBlock / 64)];
     __shared__ double s_xi[D];
     if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
-    hill_tile<D, U, FUSE>(a, cs, pos, blockIdx.x, lds, s_xi);
+    hill_tile<D, U, FUSE, T>(a, cs, pos, blockIdx.x, lds, s_xi);
 }
 
 // Persistent grid: each workgroup strides over the tiles.
-template <int D, int U, bool FUSE>
+template <int D, int U, bool FUSE, typename T>
 __global__ void __launch_bounds__(kBlock) k_hill_tiles_persist(HillArgs a, CvSet cs, PosView pos)
 {
     __shared__ double lds[(1 + D) * (kBlock / 64)];
     __shared__ double s_xi[D];
     if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
     for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        hill_tile<D, U, FUSE>(a, cs, pos, __builtin_amdgcn_readfirstlane(t), lds, s_xi);
+        hill_tile<D, U, FUSE, T>(a, cs, pos, __builtin_amdgcn_readfirstlane(t), lds, s_xi);
         __syncthreads();  // lds / s_xi reuse by the next tile
     }
 }
@@ -276,14 +312,35 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     __shared__ double s_xi[kMaxBiasDim];
     const int32_t w = blockIdx.x;
     const WalkerRec wr = ld_uniform(a.wrec + w);
-    // small gather table: prefetch the forces this lane will update
-    SmallGather sg{0.f, 0.f, 0.f, nullptr};
+    // values thread 0 needs after the reduction, requested up front; the
+    // step counter was set by kernel A and is constant during this kernel
+    const int64_t next_step = a.deposit == 1 ? ld_uniform(a.dstep) : 0;
+    const int32_t cnt0 = a.deposit ? a.count[w] : 0;
+    // small gather table: lane u < U requests its atom's force and the
+    // Jacobian rows it will combine before the reduction, so that only the
+    // multiply-adds and the stores follow the barrier
     const bool small_lane = a.do_forces && a.small.on && (int)threadIdx.x < a.small.U;
+    SmallGather sg{0.f, 0.f, 0.f, nullptr};
+    int nent = 0;
+    int32_t cvq[kSmallPer];
+    float jr[kSmallPer][3];
     if (small_lane) {
-        sg.dst = a.F.ptr + (wr.aoff + a.small.touched[threadIdx.x]) * a.F.sa;
+        const int u = threadIdx.x;
+        const float *Jw = a.J + (int64_t)w * a.nslots * 3;
+        nent = a.small.nent[u];
+        sg.dst = a.F.ptr + (wr.aoff + a.small.touched[u]) * a.F.sa;
         sg.f0 = sg.dst[0];
         sg.f1 = sg.dst[a.F.sk];
         sg.f2 = sg.dst[2 * a.F.sk];
+#pragma unroll
+        for (int q = 0; q < kSmallPer; ++q) {
+            const int32_t e = q < nent ? a.small.ent[u][q] : 0;
+            cvq[q] = e >> 20;
+            const int32_t slot = e & 0xFFFFF;
+            jr[q][0] = q < nent ? Jw[slot * 3 + 0] : 0.f;
+            jr[q][1] = q < nent ? Jw[slot * 3 + 1] : 0.f;
+            jr[q][2] = q < nent ? Jw[slot * 3 + 2] : 0.f;
+        }
     }
     if ((int)threadIdx.x < D) s_xi[threadIdx.x] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + threadIdx.x];
     double acc[1 + D];
@@ -313,9 +370,9 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
         }
         if (!finite) atomicOr(a.flags, kFlagNonFinite);
         bool dep = a.deposit == 2;
-        if (a.deposit == 1 && a.stride > 0) dep = (*a.dstep - 1) % a.stride == 0;  // kernel A set the counter
+        if (a.deposit == 1 && a.stride > 0) dep = (next_step - 1) % a.stride == 0;  // kernel A set the counter
         if (dep) {
-            const int32_t cnt = a.count[w];
+            const int32_t cnt = cnt0;
             if (cnt < wr.cap) {
                 const int64_t k = (int64_t)wr.hb4 * 4 + cnt;
 #pragma unroll
@@ -329,58 +386,67 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     }
     __syncthreads();
     if (!a.do_forces) return;
-    const float *Jw = a.J + (int64_t)w * a.nslots * 3;
     if (a.small.on) {
         if (small_lane) {
             double fx = 0.0, fy = 0.0, fz = 0.0;
-            for (int q = 0; q < a.small.nent[threadIdx.x]; ++q) {
-                const int32_t e = a.small.ent[threadIdx.x][q];
-                const int32_t slot = e & 0xFFFFF, cvi = e >> 20;
-                const double cf = s_coef[cvi];
-                fx += cf * (double)Jw[slot * 3 + 0];
-                fy += cf * (double)Jw[slot * 3 + 1];
-                fz += cf * (double)Jw[slot * 3 + 2];
+#pragma unroll
+            for (int q = 0; q < kSmallPer; ++q) {
+                const double cf = q < nent ? s_coef[cvq[q]] : 0.0;
+                fx += cf * (double)jr[q][0];
+                fy += cf * (double)jr[q][1];
+                fz += cf * (double)jr[q][2];
             }
             sg.dst[0] = sg.f0 + (float)fx;
             sg.dst[a.F.sk] = sg.f1 + (float)fy;
             sg.dst[2 * a.F.sk] = sg.f2 + (float)fz;
         }
     } else {
-        gather_forces(a.tabs, Jw, w, s_coef, a.F);
+        gather_forces(a.tabs, a.J + (int64_t)w * a.nslots * 3, w, s_coef, a.F);
     }
 }
 
-template <int D, bool FUSE>
-hipError_t launch_hill_d(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s)
+template <int D, bool FUSE, typename T>
+hipError_t launch_tiles(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t g, hipStream_t s)
 {
-    const int g = (grid > 0 && grid < a.ntiles) ? grid : a.ntiles;
     const bool persist = g < a.ntiles;
-#define SX_TILE_CASE(UU)                                                                                       \
-    case UU:                                                                                                   \
-        if (persist)                                                                                           \
-            hipLaunchKernelGGL((k_hill_tiles_persist<D, UU, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); \
-        else                                                                                                   \
-            hipLaunchKernelGGL((k_hill_tiles<D, UU, FUSE>), dim3(g), dim3(kBlock), 0, s, a, cs, pos);         \
+#define SX_TILE_CASE(UU)                                                                                          \
+    case UU:                                                                                                      \
+        if (persist)                                                                                              \
+            hipLaunchKernelGGL((k_hill_tiles_persist<D, UU, FUSE, T>), dim3(g), dim3(kBlock), 0, s, a, cs, pos); \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_hill_tiles<D, UU, FUSE, T>), dim3(g), dim3(kBlock), 0, s, a, cs, pos);         \
         break;
     switch (a.tile_units) {
         SX_TILE_CASE(1)
         SX_TILE_CASE(2)
         SX_TILE_CASE(4)
         SX_TILE_CASE(8)
-        SX_TILE_CASE(16)
     default: return hipErrorInvalidValue;
     }
 #undef SX_TILE_CASE
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_hill_finalize<D, FUSE>), dim3(a.tabs.W), dim3(kBlock), 0, s, a, cs, pos);
+    return hipGetLastError();
+}
+
+template <int D, bool FUSE>
+hipError_t launch_hill_d(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s,
+                         int which)
+{
+    const int g = (grid > 0 && grid < a.ntiles) ? grid : a.ntiles;
+    if (which & 1) {
+        hipError_t e = (FUSE && pos.f64) ? launch_tiles<D, FUSE, double>(a, cs, pos, g, s)
+                                         : launch_tiles<D, FUSE, float>(a, cs, pos, g, s);
+        if (e != hipSuccess) return e;
+    }
+    if (which & 2) hipLaunchKernelGGL((k_hill_finalize<D, FUSE>), dim3(a.tabs.W), dim3(kBlock), 0, s, a, cs, pos);
     return hipGetLastError();
 }
 
 template <int D>
-hipError_t launch_hill_dd(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s)
+hipError_t launch_hill_dd(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s,
+                          int which)
 {
-    return a.fuse ? launch_hill_d<D, true>(a, cs, pos, grid, s) : launch_hill_d<D, false>(a, cs, pos, grid, s);
+    return a.fuse ? launch_hill_d<D, true>(a, cs, pos, grid, s, which)
+                  : launch_hill_d<D, false>(a, cs, pos, grid, s, which);
 }
 
 // ----------------------------------------------------------------- ABF grid
@@ -529,12 +595,13 @@ __global__ void k_zero_u32(uint32_t *p, int64_t n)
 
 }  // namespace
 
-hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s)
+hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s,
+                               int which)
 {
     switch (a.D) {
-    case 1: return launch_hill_dd<1>(a, cs, pos, grid, s);
-    case 2: return launch_hill_dd<2>(a, cs, pos, grid, s);
-    case 3: return launch_hill_dd<3>(a, cs, pos, grid, s);
+    case 1: return launch_hill_dd<1>(a, cs, pos, grid, s, which);
+    case 2: return launch_hill_dd<2>(a, cs, pos, grid, s, which);
+    case 3: return launch_hill_dd<3>(a, cs, pos, grid, s, which);
     default: return hipErrorInvalidValue;
     }
 }

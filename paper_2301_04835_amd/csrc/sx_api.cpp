@@ -30,6 +30,7 @@ namespace {
 constexpr double kBoltzmann = 0.008314462618;  // kJ/(mol K), R/1000 (CODATA 2018)
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr uint64_t kCkptMagic = 0x53414d5058434b31ull;  // "SAMPXCK1"
+constexpr int64_t kEvalBatch = 65536;  // query points per shared-sum launch in sx_bias_eval
 
 struct CvDef {
     int32_t kind;
@@ -54,6 +55,7 @@ struct Plan {
     bool all_dihedral = false;  // the hill kernels compute xi and J themselves
     int64_t total_atoms = 0, total_cap = 0;
     int32_t ntiles_max = 0;
+    int64_t shared_records = 0;  // partial records of shared-list sums
     std::vector<int64_t> atom_off, hill_base;
     std::vector<int32_t> hill_cap;
     std::vector<int32_t> slot_atom, slot_cv, touched, inv_ptr, inv_slot;
@@ -166,7 +168,8 @@ void build_tiles(sx_ctx *c)
             tr.h0 = i * T;
             tr.klast = ((cap + 3) & ~3) - 4;
             tr.hb4 = wr.hb4;
-            tr.aoff = p.atom_off[w];
+            tr.aoff_lo = (int32_t)(uint32_t)(p.atom_off[w] & 0xffffffffll);
+            tr.aoff_hi = (int32_t)(p.atom_off[w] >> 32);
             c->tiles.push_back(tr);
         }
     }
@@ -291,7 +294,22 @@ sx_status make_plan(sx_ctx *c)
         total += (cap + 3) / 4 * 4;
     }
     p.total_cap = total;
-    for (int w = 0; w < nlists; ++w) p.ntiles_max += std::max(1, (p.hill_cap[w] + kTileUnit - 1) / kTileUnit);
+    if (!c->shared)
+        for (int w = 0; w < nlists; ++w) p.ntiles_max += std::max(1, (p.hill_cap[w] + kTileUnit - 1) / kTileUnit);
+    // shared-list sums (the shared step, and bias evaluation at query points
+    // in batches of kEvalBatch for any list): partial records
+    int64_t maxcap = 1;
+    for (int w = 0; w < nlists; ++w) maxcap = std::max<int64_t>(maxcap, p.hill_cap[w]);
+    int32_t ch, nch;
+    p.shared_records = 0;
+    if (c->method == M_METAD) {
+        shared_split(maxcap, kEvalBatch, ch, nch);
+        p.shared_records = (int64_t)nch * kEvalBatch;
+        if (c->shared) {
+            shared_split(maxcap, p.W, ch, nch);
+            p.shared_records = std::max<int64_t>(p.shared_records, (int64_t)nch * p.W);
+        }
+    }
     // ABF grid
     p.nbins_total = 0;
     if (c->method == M_ABF) {
@@ -313,7 +331,7 @@ sx_status make_plan(sx_ctx *c)
     p.w_V = lw.take(sizeof(double) * p.W);
     p.w_dV = lw.take(sizeof(double) * p.W * p.D);
     p.w_J = lw.take(sizeof(float) * 3 * (size_t)p.W * p.nslots);
-    p.w_part = lw.take(sizeof(double) * 4 * (size_t)p.ntiles_max);
+    p.w_part = lw.take(sizeof(double) * 4 * (size_t)std::max<int64_t>(p.ntiles_max, p.shared_records));
     p.w_cnpart = lw.take(32 * (size_t)p.W * part);
     p.w_atom_off = lw.take(sizeof(int64_t) * (p.W + 1));
     p.w_tiles = lw.take(sizeof(TileRec) * p.ntiles_max);
@@ -432,6 +450,38 @@ HillArgs hill_args(sx_ctx *c, const double *xi)
     return a;
 }
 
+// Shared-list sum arguments over list `wl` (the shared list, or walker wl's
+// private list) at nq query points xi.
+SharedArgs shared_args(sx_ctx *c, int wl, const double *xi, int64_t nq)
+{
+    const Plan &p = c->plan;
+    SharedArgs a{};
+    a.D = p.D;
+    const int64_t hb = p.hill_base[wl];
+    for (int d = 0; d < kMaxBiasDim; ++d) a.c[d] = d < p.D ? at<float>(c->state, p.s_c[d]) + hb : nullptr;
+    a.h = at<float>(c->state, p.s_h) + hb;
+    a.count = at<int32_t>(c->state, p.s_count) + wl;
+    a.cap = p.hill_cap[wl];
+    for (int d = 0; d < p.D; ++d) {
+        const bool per = cv_periodic(c->cvs[d]);
+        a.period[d] = per ? kTwoPi : 0.0;
+        a.inv_period[d] = per ? 1.0 / kTwoPi : 0.0;
+        const double s2 = c->sigma[d] * c->sigma[d];
+        a.a2[d] = (float)(1.4426950408889634 / (2.0 * s2));
+        a.inv_sig2[d] = 1.0 / s2;
+    }
+    a.xi = xi;
+    a.nq = nq;
+    a.partial = at<double>(c->ws, p.w_part);
+    shared_split(a.cap, nq, a.chunk, a.nchunk);
+    a.stride = c->stride;
+    a.height = c->height;
+    a.inv_kdT = c->kdT > 0 && std::isfinite(c->kdT) ? 1.0 / c->kdT : 0.0;
+    a.dstep = at<int64_t>(c->state, p.s_hdr);
+    a.flags = reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8);
+    return a;
+}
+
 sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J)
 {
     const Plan &p = c->plan;
@@ -450,12 +500,26 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
     double *xi = at<double>(c->ws, p.w_xi);
     float *J = at<float>(c->ws, p.w_J);
     if (c->method == M_NONE) return fail(c, SX_ESTATE, "no method configured (sx_metad_config / sx_abf_config)");
-    const bool fuse = c->method == M_METAD && p.all_dihedral;
+    const bool fuse = c->method == M_METAD && p.all_dihedral && !c->shared;
     if (!fuse) {
         sx_status st = launch_cvs(c, pv, xi, J);
         if (st != SX_OK) return st;
     }
-    if (c->method == M_METAD) {
+    if (c->method == M_METAD && c->shared) {
+        SharedArgs a = shared_args(c, 0, xi, p.W);
+        a.V_ws = at<double>(c->ws, p.w_V);
+        a.dV_ws = at<double>(c->ws, p.w_dV);
+        a.xi_out = xi_out;
+        a.V_out = V_out;
+        a.dV_out = dVdxi_out;
+        a.deposit = 1;
+        a.count_step = 1;
+        a.step = step;
+        hipError_t e = launch_hill_shared(a, c->stream);
+        if (e == hipSuccess && forces)
+            e = launch_gather(tabs_of(c), J, p.nslots, p.D, a.dV_ws, -1.0, force_view(c, forces, layout), c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "shared hill-sum kernels");
+    } else if (c->method == M_METAD) {
         HillArgs a = hill_args(c, xi);
         a.fuse = fuse;
         a.xi_save = xi;
@@ -685,7 +749,6 @@ sx_status sx_set_walkers(sx_ctx *ctx, int32_t n_walkers, const int64_t *atom_off
             if (hill_capacity[w] < 1) return fail(ctx, SX_EINVAL, "hill capacities must be >= 1");
         ctx->cap_user.assign(hill_capacity, hill_capacity + nl);
     }
-    if (ctx->shared) return fail(ctx, SX_EINVAL, "shared hill lists are not supported by this build");
     invalidate(ctx);
     return SX_OK;
     SX_GUARD_END
@@ -810,7 +873,8 @@ sx_status sx_bind(sx_ctx *ctx, void *dev_state, size_t state_bytes, void *dev_ws
     if (e == hipSuccess) e = up(p.w_inv_slot, p.inv_slot.data(), sizeof(int32_t) * p.nslots);
     if (e != hipSuccess) return hip_fail(ctx, e, "table upload");
     ctx->bound = true;
-    if (ctx->method != M_METAD) return hipStreamSynchronize(ctx->stream) == hipSuccess ? SX_OK : fail(ctx, SX_EDEVICE, "bind");
+    if (ctx->method != M_METAD || ctx->shared)
+        return hipStreamSynchronize(ctx->stream) == hipSuccess ? SX_OK : fail(ctx, SX_EDEVICE, "bind");
     build_tiles(ctx);
     return upload_tiles(ctx);
     SX_GUARD_END
@@ -896,6 +960,13 @@ sx_status sx_hillsum(sx_ctx *ctx, const double *xi, double *V_out, double *dVdxi
     if (sx_status s = require_bound(ctx)) return s;
     if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
     if (!xi) return fail(ctx, SX_EINVAL, "xi is NULL");
+    if (ctx->shared) {
+        SharedArgs sa = shared_args(ctx, 0, xi, ctx->plan.W);
+        sa.V_out = V_out;
+        sa.dV_out = dVdxi_out;
+        hipError_t e = launch_hill_shared(sa, ctx->stream);
+        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "shared hill-sum kernels");
+    }
     HillArgs a = hill_args(ctx, xi);
     a.V_out = V_out;
     a.dV_out = dVdxi_out;
@@ -913,6 +984,12 @@ sx_status sx_deposit(sx_ctx *ctx, const double *xi)
     if (sx_status s = require_bound(ctx)) return s;
     if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
     if (!xi) return fail(ctx, SX_EINVAL, "xi is NULL");
+    if (ctx->shared) {
+        SharedArgs sa = shared_args(ctx, 0, xi, ctx->plan.W);
+        sa.deposit = 2;
+        hipError_t e = launch_hill_shared(sa, ctx->stream);
+        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "shared deposit kernels");
+    }
     HillArgs a = hill_args(ctx, xi);
     a.deposit = 2;
     a.step = 0;
@@ -921,6 +998,27 @@ sx_status sx_deposit(sx_ctx *ctx, const double *xi)
     hipError_t e = launch_hill_private(a, ctx->plan.cs, PosView{}, ctx->grid, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "deposit kernel");
     return SX_OK;
+}
+
+sx_status sx_bias_eval(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double *V_out, double *dVdxi_out)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
+    const int wl = walker_list(ctx, walker);
+    if (wl < 0 || wl >= ctx->plan.W) return fail(ctx, SX_EINVAL, "walker out of range");
+    if (n < 0 || (n > 0 && !xi)) return fail(ctx, SX_EINVAL, "bad query points");
+    const int D = ctx->plan.D;
+    for (int64_t i0 = 0; i0 < n; i0 += kEvalBatch) {
+        const int64_t m = std::min<int64_t>(kEvalBatch, n - i0);
+        SharedArgs a = shared_args(ctx, wl, xi + i0 * D, m);
+        a.V_out = V_out ? V_out + i0 : nullptr;
+        a.dV_out = dVdxi_out ? dVdxi_out + i0 * D : nullptr;
+        hipError_t e = launch_hill_shared(a, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "bias evaluation kernels");
+    }
+    return SX_OK;
+    SX_GUARD_END
 }
 
 sx_status sx_hills_set(sx_ctx *ctx, int32_t walker, const float *centers, const float *heights, int64_t K)
@@ -1012,7 +1110,7 @@ static uint64_t config_hash(const sx_ctx *c)
 {
     std::ostringstream os;
     os.precision(17);
-    os << c->method << ' ' << c->plan.W << ' ' << c->plan.D << ' ' << c->plan.nslots << ' ' << c->plan.total_cap << ' '
+    os << c->method << ' ' << c->shared << ' ' << c->plan.W << ' ' << c->plan.D << ' ' << c->plan.nslots << ' ' << c->plan.total_cap << ' '
        << c->plan.nbins_total << ' ' << c->height << ' ' << c->kdT << ' ' << c->stride;
     for (int d = 0; d < c->plan.D; ++d) os << ' ' << c->sigma[d] << ' ' << c->lo[d] << ' ' << c->hi[d];
     for (auto v : c->plan.hill_cap) os << ' ' << v;
@@ -1118,12 +1216,12 @@ sx_status sx_set_tuning(sx_ctx *ctx, int32_t tile_hills, int32_t grid)
     if (!ctx) return SX_EINVAL;
     if (tile_hills % kTileUnit != 0) return fail(ctx, SX_EINVAL, "tile must be a multiple of 1024 hills");
     const int u = tile_hills / kTileUnit;
-    if (u != 1 && u != 2 && u != 4 && u != 8 && u != 16) return fail(ctx, SX_EINVAL, "tile must be 1024 * {1,2,4,8,16}");
+    if (u != 1 && u != 2 && u != 4 && u != 8) return fail(ctx, SX_EINVAL, "tile must be 1024 * {1,2,4,8}");
     if (grid < 0) return fail(ctx, SX_EINVAL, "grid must be >= 0");
     ctx->grid = grid;
     if (u != ctx->tile_units) {
         ctx->tile_units = u;
-        if (ctx->bound && ctx->method == M_METAD) {
+        if (ctx->bound && ctx->method == M_METAD && !ctx->shared) {
             if (ctx->gexec) return fail(ctx, SX_ESTATE, "release the captured graph before retiling");
             build_tiles(ctx);
             return upload_tiles(ctx);
@@ -1144,7 +1242,7 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
 {
     if (sx_status s = require_bound(ctx)) return s;
     SX_GUARD_BEGIN
-    if (ctx->method != M_METAD) return SX_OK;  // only the hill sum has launch choices
+    if (ctx->method != M_METAD || ctx->shared) return SX_OK;  // only the private hill sum has launch choices
     if (ctx->gexec) return fail(ctx, SX_ESTATE, "release the captured graph before tuning");
     const Plan &p = ctx->plan;
     PosView pv{};
@@ -1169,7 +1267,7 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
         if (it != cache.end()) return sx_set_tuning(ctx, it->second.first, it->second.second);
     }
     const int ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    const int tiles[] = {1024, 2048, 4096, 8192, 16384};
+    const int tiles[] = {1024, 2048, 4096, 8192};
     const int gmul[] = {0, 2, 4, 8};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ctx, SX_EDEVICE, "events");
@@ -1191,19 +1289,25 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
             a.count_step = 0;
             a.do_forces = 0;
             for (int r = 0; r < 3; ++r) launch_hill_private(a, p.cs, pv, g, ctx->stream);
-            hipEventRecord(e0, ctx->stream);
-            const int reps = 20;
-            for (int r = 0; r < reps; ++r) launch_hill_private(a, p.cs, pv, g, ctx->stream);
-            hipEventRecord(e1, ctx->stream);
-            hipError_t e = hipEventSynchronize(e1);
-            if (e != hipSuccess) {
-                st = hip_fail(ctx, e, "autotune timing");
-                break;
+            float ms = 1e30f;
+            for (int round = 0; round < 3 && st == SX_OK; ++round) {  // best of three rounds
+                hipEventRecord(e0, ctx->stream);
+                const int reps = 20;
+                for (int r = 0; r < reps; ++r) launch_hill_private(a, p.cs, pv, g, ctx->stream);
+                hipEventRecord(e1, ctx->stream);
+                hipError_t e = hipEventSynchronize(e1);
+                if (e != hipSuccess) {
+                    st = hip_fail(ctx, e, "autotune timing");
+                    break;
+                }
+                float m = 0;
+                hipEventElapsedTime(&m, e0, e1);
+                ms = std::min(ms, m);
             }
-            float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) {
-                best = ms;
+            // a persistent grid must win by 2% over one workgroup per tile
+            const float handicap = g ? 1.02f : 1.0f;
+            if (st == SX_OK && ms * handicap < best) {
+                best = ms * handicap;
                 bt = t;
                 bg = g;
             }
@@ -1224,6 +1328,49 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
                 << (++i < cache.size() ? ",\n" : "\n");
         out << "}\n";
     }
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_time_hill(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
+                       float *ms_tiles, float *ms_finalize)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (ctx->method != M_METAD || ctx->shared) return fail(ctx, SX_ESTATE, "no private hill lists on this context");
+    if (reps < 1 || !ms_tiles || !ms_finalize) return fail(ctx, SX_EINVAL, "reps >= 1 and both outputs needed");
+    const Plan &p = ctx->plan;
+    PosView pv;
+    if (!pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
+    const bool fuse = p.all_dihedral;
+    double *xi = at<double>(ctx->ws, p.w_xi);
+    if (!fuse) {
+        if (sx_status st = launch_cvs(ctx, pv, xi, at<float>(ctx->ws, p.w_J))) return st;
+    }
+    HillArgs a = hill_args(ctx, xi);
+    a.fuse = fuse;
+    a.xi_save = xi;
+    a.deposit = 0;
+    a.count_step = 0;
+    a.do_forces = forces != nullptr;
+    a.F = force_view(ctx, forces, layout);
+    hipEvent_t e[3];
+    for (auto &ev : e)
+        if (hipEventCreate(&ev) != hipSuccess) return fail(ctx, SX_EDEVICE, "events");
+    hipError_t err = launch_hill_private(a, p.cs, pv, ctx->grid, ctx->stream, 1);  // warm: J and xi for kernel B
+    if (err == hipSuccess) err = hipEventRecord(e[0], ctx->stream);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_hill_private(a, p.cs, pv, ctx->grid, ctx->stream, 1);
+    if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_hill_private(a, p.cs, pv, ctx->grid, ctx->stream, 2);
+    if (err == hipSuccess) err = hipEventRecord(e[2], ctx->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e[2]);
+    float m1 = 0, m2 = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&m1, e[0], e[1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&m2, e[1], e[2]);
+    for (auto &ev : e) hipEventDestroy(ev);
+    if (err != hipSuccess) return hip_fail(ctx, err, "hill kernel timing");
+    *ms_tiles = m1 / reps;
+    *ms_finalize = m2 / reps;
     return SX_OK;
     SX_GUARD_END
 }

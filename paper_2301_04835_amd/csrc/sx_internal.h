@@ -12,7 +12,7 @@ constexpr int kMaxBiasDim = 3;   // CVs a bias (hills / ABF grid) may span
 constexpr int kBlock = 256;      // threads per workgroup of the main kernels
 constexpr int kHillsPerLoad = 4; // float4 per lane
 constexpr int kTileUnit = kBlock * kHillsPerLoad;  // 1024 hills: smallest tile
-constexpr int kMaxTileUnits = 16;                  // largest tile: 16384 hills
+constexpr int kMaxTileUnits = 8;                   // largest tile: 8192 hills
 
 enum CvKind : int32_t { CV_DIHEDRAL = 0, CV_GYRATION = 1, CV_COORD = 2 };
 
@@ -74,7 +74,7 @@ struct WalkerTabs {
 // walker's first atom.
 struct __align__(16) TileRec {
     int32_t w, h0, klast, hb4;
-    int64_t aoff;
+    int32_t aoff_lo, aoff_hi;  // first atom of the walker (64-bit, split)
     int32_t pad[2];
 };
 // Packed per-walker record for the finalize kernel.
@@ -152,12 +152,65 @@ struct AbfArgs {
     int64_t *dstep;
 };
 
+// Hill sum over one shared list at nq query points.
+struct SharedArgs {
+    int32_t D;
+    float *c[kMaxBiasDim];
+    float *h;
+    int32_t *count;
+    int64_t cap;
+    double period[kMaxBiasDim], inv_period[kMaxBiasDim];
+    float a2[kMaxBiasDim];
+    double inv_sig2[kMaxBiasDim];
+    const double *xi;  // nq x D (with qlist: rows of the walkers in the list)
+    int64_t nq;        // queries (with qlist: the list's capacity)
+    const int32_t *qlist, *qcount;  // optional: query q is walker qlist[q], q < *qcount
+    double *partial;   // nchunk x nq x 4
+    int32_t chunk, nchunk;
+    double *V_ws, *dV_ws, *xi_out, *V_out, *dV_out;  // may be null
+    int32_t deposit, count_step, stride;
+    int64_t step;
+    double height, inv_kdT;
+    int64_t *dstep;
+    uint32_t *flags;
+};
+
+// Surrogate network (bf16 copies as raw 16-bit words in host code).
+struct MlpArgs {
+    int32_t D, H;
+    int32_t periodic[kMaxBiasDim];
+    double mu[kMaxBiasDim], inv_s[kMaxBiasDim];  // standardisation of non-periodic CVs
+    const uint16_t *Pb;  // bf16 parameters (read)
+    uint16_t *Pw;        // the same, written by the optimiser
+    float *P32, *m, *v;  // FP32 master parameters, Adam moments
+    int64_t nmax;        // row stride of the training tangents
+    double cert_lo[kMaxBiasDim], cert_inv_h[kMaxBiasDim];
+    int32_t cert_n;
+    const uint8_t *mask;  // certified cells (1) of the cert_n^D grid
+};
+
 // ---------------------------------------------------------------- launchers
 // Each returns the hipError_t of its launch.
 hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *cn_part,
                      int64_t max_atoms_per_walker, hipStream_t s);
-hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s);
+// which: 1 = tiles (kernel A), 2 = finalize (kernel B), 3 = both
+hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s,
+                               int which = 3);
 hipError_t launch_abf(const AbfArgs &a, hipStream_t s);
+// chunking of a shared-list sum over nq queries: chunk (hills) and count
+void shared_split(int64_t cap, int64_t nq, int32_t &chunk, int32_t &nchunk);
+hipError_t launch_hill_shared(const SharedArgs &a, hipStream_t s);
+int32_t mlp_param_count(int32_t H, int32_t D);
+int32_t mlp_bwd_blocks(int32_t H, int64_t n);
+hipError_t launch_mlp_fwd(const MlpArgs &a, const double *xi, int64_t n, double *V, double *dV, float *t_a2,
+                          float *t_dz2, float *t_y, float *t_dy, uint8_t *flag, hipStream_t s);
+// one optimisation step over n samples: forward, reverse, Adam (lr > 0) or
+// only the loss (lr <= 0, gradients left in gpart)
+hipError_t launch_mlp_train_step(const MlpArgs &a, const double *xi, const double *Vl, const double *Gl, int64_t n,
+                                 float alpha, float beta, float lr, int64_t t, float *t_a2, float *t_dz2, float *t_y,
+                                 float *t_dy, float *gpart, double *loss_out, hipStream_t s);
+hipError_t launch_mlp_round(const MlpArgs &a, hipStream_t s);
+hipError_t launch_compact(const uint8_t *flag, int32_t n, int32_t *list, int32_t *count, hipStream_t s);
 hipError_t launch_gather(const WalkerTabs &t, const float *J, int32_t nslots, int32_t D, const double *coef,
                          double coef_sign, ForceView out, hipStream_t s);
 hipError_t launch_copy_xi(const double *src, double *dst, int64_t n, hipStream_t s);

@@ -127,7 +127,7 @@ def _oracle_walkers(pos, off, hills, cvs, sigma, W):
     return out
 
 
-@pytest.mark.parametrize("tile,grid", [(1024, 0), (2048, 3), (4096, 0), (16384, 1), (8192, 300)])
+@pytest.mark.parametrize("tile,grid", [(1024, 0), (2048, 3), (4096, 0), (8192, 1), (4096, 300)])
 def test_ragged_walkers_all_tilings(gpu, tile, grid):
     counts = [0, 1, 3, 1023, 1024, 1025, 5000, 17]
     caps = [1, 4, 8, 1024, 1028, 2100, 5001, 40000]
@@ -290,7 +290,7 @@ def test_autotune_keeps_results(gpu, tmp_path):
     cache = str(tmp_path / "tune.json")
     s.autotune(P, cache)
     t, g = s.get_tuning()
-    assert t in (1024, 2048, 4096, 8192, 16384)
+    assert t in (1024, 2048, 4096, 8192)
     V1 = torch.zeros_like(V0)
     s.step(P, forces=torch.zeros_like(P), step=1, V_out=V1)
     assert torch.max(torch.abs(V1 - V0) / V0).item() <= 1e-12
