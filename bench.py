@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--hill-reps", type=int, default=200, help="launches timed for the hill-sum kernel")
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="after the run, copy this many MiB with the plain copy probe (counter calibration)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
+    ap.add_argument("--sg-train-steps", type=int, default=40000, help="Adam steps of the surrogate fit")
+    ap.add_argument("--sg-steps", type=int, default=2000, help="timed steps of each surrogate-workload path")
     return ap.parse_args()
 
 
@@ -110,6 +113,101 @@ def cpu_baseline(d, p, target_s):
     return {"value": n / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": "%d full steps of the same 256-walker workload (%d hills per step), FP64, 1 thread, %.1f s"
                       % (n, int(hoff[-1]), el)}
+
+
+def timed_graph(s, pos, forces, outs, steps, warmup, gsteps=10):
+    """Capture gsteps steps in a HIP graph, replay warmup, then time
+    replays for `steps` steps (wall clock around synchronisations)."""
+    import torch
+    xi, V, dV = outs
+    s.graph_capture(gsteps, pos, forces=forces, xi_out=xi, V_out=V, dV_out=dV)
+    for _ in range(max(1, warmup // gsteps)):
+        s.graph_launch()
+    torch.cuda.synchronize()
+    n = max(1, steps // gsteps)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        s.graph_launch()
+    torch.cuda.synchronize()
+    return n * gsteps / (time.perf_counter() - t0), n * gsteps
+
+
+def surrogate_leg(args):
+    """Surrogate workload: 100,000 shared hills of a converged well-tempered
+    run on two dihedral CVs (sigma 0.3 rad, w ~ U[0.5, 1.5] kJ/mol, T 300 K,
+    bias factor 6); 256 walkers of 22 atoms; a 4-64-64-1 tanh network
+    trained on the GPU on 2^17 torus points, certified on a 512^2 grid at
+    0.1 kJ/mol/rad.  Exact path: the shared hill sum for every walker.
+    Surrogate path: the network for every walker plus the exact sum for the
+    walkers outside certified cells.  Both run as replayed graphs of whole
+    steps (CVs, bias, forces); the bias is frozen (no deposition)."""
+    import torch
+    from paper_2301_04835_amd import Sampler, synth, synth_wt
+
+    K, W = 100000, 256
+    t0 = time.perf_counter()
+    C, H = synth_wt.wt_hills(K)
+    pos_np, off = synth.chain_walkers(W, 22, seed=4)
+    t_gen = time.perf_counter() - t0
+    s = Sampler(0)
+    s.add_cvs(synth.backbone_cvs(4))
+    s.set_walkers(off, [K], shared=True)
+    s.metad([0.3, 0.3], 1.0, 300.0, 6.0, 0, K)
+    s.surrogate(64, max_samples=1 << 17, max_batch=4096, cert_n=512, tol_force=0.1)
+    s.bind()
+    s.hills_set(0, C, H)
+    g = np.random.default_rng(7)
+    P0 = []
+    for fan_in, shape in [(4, (64, 4)), (1, (64,)), (64, (64, 64)), (1, (64,)), (64, (64,)), (1, (1,))]:
+        P0.append((g.uniform(-1, 1, shape) / np.sqrt(fan_in) if fan_in > 1 else np.zeros(shape)).ravel())
+    s.surrogate_params(np.concatenate(P0).astype(np.float32))
+    X = torch.from_numpy(synth_wt.torus_points(1 << 17, 8)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = s.surrogate_train(X, batch=4096, steps=args.sg_train_steps, lr=3e-3, lr_final=1e-5)
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    frac = s.surrogate_certify()
+    t_cert = time.perf_counter() - t0
+    pos = torch.from_numpy(pos_np).cuda()
+    forces = torch.zeros_like(pos)
+    mk = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+    ex = (mk(W, 2), mk(W), mk(W, 2))
+    sg = (mk(W, 2), mk(W), mk(W, 2))
+    rate_exact, n_ex = timed_graph(s, pos, forces, ex, args.sg_steps, 200)
+    s.surrogate_enable(True)
+    rate_sg, n_sg = timed_graph(s, pos, forces, sg, args.sg_steps, 200)
+    nfb = s.surrogate_fallback_count()
+    s.check()
+    dv_net = sg[2].cpu().numpy()
+    dv_ex = ex[2].cpu().numpy()
+    err_vs_exact = float(np.max(np.linalg.norm(dv_net - dv_ex, axis=1)))
+    res = {"workload": "wtmd-surrogate-100k-shared-256-walkers", "hills": K, "walkers": W,
+           "network": "4-64-64-1 tanh, bf16 weights, FP32 accumulate", "train_steps": args.sg_train_steps,
+           "train_batch": 4096, "train_samples": 1 << 17, "train_loss": loss, "train_s": t_train,
+           "certify_grid": "512x512", "certify_s": t_cert, "certified_fraction": frac,
+           "fallback_walkers": nfb, "exact_steps_per_s": rate_exact, "surrogate_steps_per_s": rate_sg,
+           "speedup": rate_sg / rate_exact, "steps_timed": n_sg,
+           "max_dV_err_vs_exact_gpu": err_vs_exact, "tol_force": 0.1, "input_gen_s": t_gen}
+    return res, (C, H, pos_np, off, sg)
+
+
+def surrogate_oracle_check(sg_data):
+    """CPU oracle leg of the surrogate workload: the FP64 hill sum at the
+    walkers' CV values, against which the surrogate step's dV/dxi error is
+    stated (timed as the oracle's cost of one exact step's bias)."""
+    import oracle
+
+    C, H, pos_np, off, sg = sg_data
+    xi = sg[0].cpu().numpy()
+    dv = sg[2].cpu().numpy()
+    t0 = time.perf_counter()
+    _, dVr = oracle.hillsum_batch(xi, None, C.astype(np.float64), H.astype(np.float64), [0.3, 0.3],
+                                  [2 * np.pi, 2 * np.pi], nthreads=1)
+    el = time.perf_counter() - t0
+    err = np.linalg.norm(dv - dVr, axis=1)
+    return {"max_dV_err_vs_oracle": float(err.max()), "median_dV_err_vs_oracle": float(np.median(err)),
+            "oracle_bias_s_per_step_1_thread": el}
 
 
 def main():
@@ -195,8 +293,13 @@ def main():
             s.L.sx_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nb, 2048,
                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
+    sg_data = None
+    if not args.no_surrogate:
+        out["surrogate"], sg_data = surrogate_leg(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, p, args.cpu_seconds)
+        if sg_data is not None:
+            out["surrogate"].update(surrogate_oracle_check(sg_data))
     print(json.dumps(out))
 
 

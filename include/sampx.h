@@ -263,6 +263,86 @@ sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
  * hipEvents; synchronous. */
 sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const char *cache_path);
 
+/* ------------------------------------------------- bias surrogate */
+/* A small tanh network of the CVs that stands in for the metadynamics bias
+ * of hill list 0 (the shared list, or the one walker's list) once the bias
+ * is frozen: the network precedent is the paper's ANN and FUNN methods
+ * (Sec. 2.1.7, 2.1.8) applied to the hill-sum bias of Sec. 2.1.5.
+ *   features f: (sin xi_d, cos xi_d) periodic CV; (u, u^2) otherwise with
+ *               u = (xi_d - mu_d) / s_d (sx_surrogate_norm)
+ *   y = w3 . tanh(W2 tanh(W1 f + b1) + b2) + b3,  V = shift + scale * y
+ * W2 runs on the matrix cores in bf16 with FP32 accumulation; every weight
+ * is used at its bf16 value (FP32 master copies are trained).  dV/dxi is
+ * the network's exact derivative (forward tangents).  Certified cells of a
+ * cert_n^D grid use the network; the others fall back to the exact sum.
+ *
+ * Declare before sx_bind (it sizes state and workspace).  hidden: 64 or
+ * 128 (0 removes the network); max_samples: training points per call;
+ * max_batch: samples per optimiser step; cert_n: grid cells per CV;
+ * tol_force: the largest |dVhat/dxi - dV/dxi| (2-norm over the CVs,
+ * kJ/mol/rad) a certified cell may show.  Needs sx_metad_config, 1-3 CVs. */
+sx_status sx_surrogate_config(sx_ctx *ctx, int32_t hidden, int64_t max_samples, int32_t max_batch, int32_t cert_n,
+                              double tol_force);
+/* Standardisation of non-periodic CVs (host arrays of D; s > 0). */
+sx_status sx_surrogate_norm(sx_ctx *ctx, const double *mu, const double *s);
+/* Number of parameters P = H(2D) + H + H^2 + H + H + 1, stored in the order
+ * W1[H][2D], b1[H], W2[H][H], b2[H], w3[H], b3 (0 without a network). */
+int64_t sx_surrogate_param_count(const sx_ctx *ctx);
+/* FP32 parameters from / to host memory (count == P).  Setting them resets
+ * the optimiser and drops the certification; synchronous. */
+sx_status sx_surrogate_params_set(sx_ctx *ctx, const float *params, int64_t count);
+sx_status sx_surrogate_params_get(sx_ctx *ctx, float *params, int64_t count);
+/* Output affine V = shift + scale * y (scale != 0); sx_surrogate_train sets
+ * it from the mean and spread of its targets. */
+sx_status sx_surrogate_output(sx_ctx *ctx, double scale, double shift);
+sx_status sx_surrogate_output_get(const sx_ctx *ctx, double *scale, double *shift);
+/* Network at n points: xi[n][D] -> V_out[n], dVdxi_out[n][D] (device, FP64;
+ * outputs may be NULL).  fallback (device uint8[n], may be NULL; needs a
+ * certification): 1 where the point's cell is not certified. */
+sx_status sx_surrogate_eval(sx_ctx *ctx, const double *xi, int64_t n, double *V_out, double *dVdxi_out,
+                            uint8_t *fallback);
+/* Sobolev loss of the network over n <= max_batch samples (device xi[n][D],
+ * V[n], G[n][D], physical units; the output affine maps them to network
+ * units) and its gradient with respect to every parameter:
+ *   L = (1/n) sum_i [alpha (y_i - V'_i)^2 + beta sum_d (dy_i/dxi_d - G'_id)^2]
+ * with V' = (V - shift)/scale, G' = G/scale.  grad_host: host double[P]
+ * (FP64 sum of FP32 per-workgroup partials), loss_host: host double.
+ * Synchronous.  Used to check the reverse kernels. */
+sx_status sx_surrogate_loss_grad(sx_ctx *ctx, const double *xi, const double *V, const double *G, int64_t n,
+                                 double alpha, double beta, double *grad_host, double *loss_host);
+/* `steps` Adam steps (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8)
+ * on the Sobolev loss above, over consecutive batches of `batch` samples of
+ * the n device samples (cyclic; give the samples in random order), with the
+ * learning rate decaying from lr to lr_final on a cosine.  loss_out (host,
+ * may be NULL): mean loss of the last batch.  Synchronous at the end. */
+sx_status sx_surrogate_fit(sx_ctx *ctx, const double *xi, const double *V, const double *G, int64_t n, int32_t batch,
+                           int32_t steps, double lr, double lr_final, double alpha, double beta, double *loss_out);
+/* Fit to the exact bias: evaluates V and dV/dxi of hill list 0 at the n
+ * device points xi[n][D] (n <= max_samples), sets the output affine to their
+ * mean and standard deviation, and runs sx_surrogate_fit with alpha = 1 and
+ * beta = 1 / (mean gradient variance in network units).  Synchronous. */
+sx_status sx_surrogate_train(sx_ctx *ctx, const double *xi, int64_t n, int32_t batch, int32_t steps, double lr,
+                             double lr_final, double *loss_out);
+/* Certify cells of a cert_n^D grid over [-pi, pi) for periodic CVs and
+ * [lo_d, hi_d] (host arrays; may be NULL if every CV is periodic) otherwise:
+ * the exact and the network gradient are evaluated at every grid corner; a
+ * cell is certified when the largest corner error plus twice the largest
+ * corner-to-corner change of the error per unit length times the half
+ * diagonal is at most tol_force.  certified_fraction (host, may be NULL).
+ * The certification describes the current hill list and network: setting
+ * hills or parameters, depositing, training or an exact step that may
+ * deposit drops it.  Synchronous. */
+sx_status sx_surrogate_certify(sx_ctx *ctx, const double *lo, const double *hi, double *certified_fraction);
+/* Switch the surrogate into sx_step (needs parameters and a certification;
+ * a shared hill list or one walker).  While on, the step evaluates the
+ * network for every walker, the exact sum of the shared list for the
+ * walkers whose cell is not certified, and deposits nothing (the network
+ * stands for a frozen bias). */
+sx_status sx_surrogate_enable(sx_ctx *ctx, int32_t on);
+/* Walkers that took the exact fallback in the last surrogate step (host
+ * int32; synchronous). */
+sx_status sx_surrogate_fallback_count(sx_ctx *ctx, int32_t *count);
+
 /* ------------------------------------------------- measurement probes */
 /* Average duration of the step's two hill-sum kernels: `reps` back-to-back
  * launches of the tile kernel, then `reps` of the finalize kernel, bracketed

@@ -20,7 +20,8 @@ Adam: Kingma & Ba (2015).
 Parameters are a dict of float64 arrays: W1 (H, F), b1 (H), W2 (H, H),
 b2 (H), w3 (H), b3 (1,).  ``act_round`` is an optional rounding applied to
 the activation vectors that feed the H x H product (the GPU feeds them to a
-BF16 matrix-core product); identity by default.
+BF16 matrix-core product as hi + lo pairs: ``round_bf16x2``); identity by
+default.
 """
 import numpy as np
 
@@ -153,3 +154,12 @@ def round_bf16(x):
     lsb = (b >> 16) & 1
     b = (b + 0x7FFF + lsb) & 0xFFFF0000
     return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_bf16x2(x):
+    """Value of a bfloat16 pair hi + lo with hi = bf16(x), lo = bf16(x - hi)
+    (x first rounded to float32, as the GPU holds it): about 16 significant
+    bits, the form in which activations enter a bf16 matrix product."""
+    f = np.asarray(x, dtype=np.float32).astype(np.float64)
+    hi = round_bf16(f)
+    return hi + round_bf16(f - hi)

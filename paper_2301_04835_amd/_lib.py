@@ -65,6 +65,20 @@ SIGNATURES = {
     "sx_time_hill": (i32, [P, P, i32, i32, P, i32, P, P]),
     "sx_probe_read": (i32, [P, sz, P, i32, P]),
     "sx_probe_copy": (i32, [P, P, sz, i32, P]),
+    "sx_surrogate_config": (i32, [P, i32, i64, i32, i32, f64]),
+    "sx_surrogate_norm": (i32, [P, P, P]),
+    "sx_surrogate_param_count": (i64, [P]),
+    "sx_surrogate_params_set": (i32, [P, P, i64]),
+    "sx_surrogate_params_get": (i32, [P, P, i64]),
+    "sx_surrogate_output": (i32, [P, f64, f64]),
+    "sx_surrogate_output_get": (i32, [P, P, P]),
+    "sx_surrogate_eval": (i32, [P, P, i64, P, P, P]),
+    "sx_surrogate_loss_grad": (i32, [P, P, P, P, i64, f64, f64, P, P]),
+    "sx_surrogate_fit": (i32, [P, P, P, P, i64, i32, i32, f64, f64, f64, f64, P]),
+    "sx_surrogate_train": (i32, [P, P, i64, i32, i32, f64, f64, P]),
+    "sx_surrogate_certify": (i32, [P, P, P, P]),
+    "sx_surrogate_enable": (i32, [P, i32]),
+    "sx_surrogate_fallback_count": (i32, [P, P]),
 }
 
 _lib = None

@@ -256,6 +256,84 @@ class Sampler:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._check(self.L.sx_state_import(self.h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
 
+    # ------------------------------------------------------------ surrogate
+    def surrogate(self, hidden=64, max_samples=1 << 17, max_batch=4096, cert_n=512, tol_force=0.1):
+        """Declare the bias surrogate network (before bind)."""
+        self._check(self.L.sx_surrogate_config(self.h, int(hidden), int(max_samples), int(max_batch), int(cert_n),
+                                               float(tol_force)))
+
+    def surrogate_norm(self, mu, s):
+        m, pm = _host(mu, np.float64)
+        s_, ps = _host(s, np.float64)
+        self._check(self.L.sx_surrogate_norm(self.h, pm, ps))
+
+    def surrogate_param_count(self):
+        return int(self.L.sx_surrogate_param_count(self.h))
+
+    def surrogate_params(self, params=None):
+        """Set (params given, host float32 vector of length P) or get them."""
+        n = self.surrogate_param_count()
+        if params is not None:
+            a, pa = _host(params, np.float32)
+            self._check(self.L.sx_surrogate_params_set(self.h, pa, a.size))
+            return None
+        out = np.zeros(n, dtype=np.float32)
+        self._check(self.L.sx_surrogate_params_get(self.h, out.ctypes.data_as(ctypes.c_void_p), n))
+        return out
+
+    def surrogate_output(self, scale=None, shift=None):
+        if scale is not None:
+            self._check(self.L.sx_surrogate_output(self.h, float(scale), float(shift)))
+            return None
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.sx_surrogate_output_get(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def surrogate_eval(self, xi, fallback=False):
+        n = xi.shape[0]
+        V = torch.empty(n, dtype=torch.float64, device=self.device)
+        dV = torch.empty((n, self.D), dtype=torch.float64, device=self.device)
+        fb = torch.empty(n, dtype=torch.uint8, device=self.device) if fallback else None
+        self._check(self.L.sx_surrogate_eval(self.h, _ptr(xi.contiguous()), n, _ptr(V), _ptr(dV), _ptr(fb)))
+        return (V, dV, fb) if fallback else (V, dV)
+
+    def surrogate_loss_grad(self, xi, V, G, alpha, beta):
+        n = xi.shape[0]
+        g = np.zeros(self.surrogate_param_count(), dtype=np.float64)
+        loss = ctypes.c_double()
+        self._check(self.L.sx_surrogate_loss_grad(self.h, _ptr(xi.contiguous()), _ptr(V.contiguous()),
+                                                  _ptr(G.contiguous()), n, float(alpha), float(beta),
+                                                  g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
+        return loss.value, g
+
+    def surrogate_fit(self, xi, V, G, batch, steps, lr, lr_final=0.0, alpha=1.0, beta=1.0):
+        loss = ctypes.c_double()
+        self._check(self.L.sx_surrogate_fit(self.h, _ptr(xi.contiguous()), _ptr(V.contiguous()), _ptr(G.contiguous()),
+                                            xi.shape[0], int(batch), int(steps), float(lr), float(lr_final),
+                                            float(alpha), float(beta), ctypes.byref(loss)))
+        return loss.value
+
+    def surrogate_train(self, xi, batch=4096, steps=20000, lr=3e-3, lr_final=1e-5):
+        loss = ctypes.c_double()
+        self._check(self.L.sx_surrogate_train(self.h, _ptr(xi.contiguous()), xi.shape[0], int(batch), int(steps),
+                                              float(lr), float(lr_final), ctypes.byref(loss)))
+        return loss.value
+
+    def surrogate_certify(self, lo=None, hi=None):
+        frac = ctypes.c_double()
+        plo = _host(lo, np.float64) if lo is not None else (None, None)
+        phi = _host(hi, np.float64) if hi is not None else (None, None)
+        self._check(self.L.sx_surrogate_certify(self.h, plo[1], phi[1], ctypes.byref(frac)))
+        return frac.value
+
+    def surrogate_enable(self, on=True):
+        self._check(self.L.sx_surrogate_enable(self.h, 1 if on else 0))
+
+    def surrogate_fallback_count(self):
+        c = ctypes.c_int32()
+        self._check(self.L.sx_surrogate_fallback_count(self.h, ctypes.byref(c)))
+        return c.value
+
     # ----------------------------------------------------- graphs / tuning
     def graph_capture(self, n_steps, pos, forces=None, xi_out=None, V_out=None, dV_out=None, sys_forces=None,
                       layout="aos3"):

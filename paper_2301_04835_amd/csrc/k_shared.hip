@@ -31,13 +31,18 @@ __global__ void __launch_bounds__(kBlock) k_hill_shared(SharedArgs a)
     const int32_t n = *a.count;
     const int64_t h0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t q0 = ((int64_t)blockIdx.y * kBlock + threadIdx.x) * Q;
+    // with a query list only its first *qcount entries are live; a
+    // workgroup past them leaves before its first barrier (uniform test)
+    const int64_t nq = a.qlist ? (int64_t)*a.qcount : a.nq;
+    if ((int64_t)blockIdx.y * kBlock * Q >= nq) return;
     double xi[Q][D];
     bool live[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        live[q] = q0 + q < a.nq;
+        live[q] = q0 + q < nq;
+        const int64_t row = !live[q] ? 0 : (a.qlist ? (int64_t)a.qlist[q0 + q] : q0 + q);
 #pragma unroll
-        for (int d = 0; d < D; ++d) xi[q][d] = live[q] ? a.xi[(q0 + q) * D + d] : 0.0;
+        for (int d = 0; d < D; ++d) xi[q][d] = live[q] ? a.xi[row * D + d] : 0.0;
     }
     double acc[Q][1 + D];
 #pragma unroll
@@ -112,7 +117,8 @@ __device__ __forceinline__ void block_sum0(double (&v)[N], double *lds)
         }
 }
 
-// per query: V, dV/dxi, outputs and (all or none) the appended hill
+// per query: V, dV/dxi, outputs and (all or none) the appended hill;
+// w is the query's row (its walker, or its entry of the query list)
 template <int D>
 __device__ __forceinline__ void shared_finish(const SharedArgs &a, int64_t w, const double (&acc)[1 + D])
 {
@@ -150,17 +156,17 @@ __device__ __forceinline__ void shared_finish(const SharedArgs &a, int64_t w, co
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_hill_shared_finalize(SharedArgs a)
 {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.nq) return;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (a.qlist ? (int64_t)*a.qcount : a.nq)) return;
     double acc[1 + D];
 #pragma unroll
     for (int j = 0; j <= D; ++j) acc[j] = 0.0;
     for (int ch = 0; ch < a.nchunk; ++ch) {
-        const double *p = a.partial + ((int64_t)ch * a.nq + w) * 4;
+        const double *p = a.partial + ((int64_t)ch * a.nq + q) * 4;
 #pragma unroll
         for (int j = 0; j <= D; ++j) acc[j] += p[j];
     }
-    shared_finish<D>(a, w, acc);
+    shared_finish<D>(a, a.qlist ? (int64_t)a.qlist[q] : q, acc);
 }
 
 // many chunks: one workgroup per query, lanes stride over the chunks and a
@@ -169,17 +175,18 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_hill_shared_finalize_wg(SharedArgs a)
 {
     __shared__ double lds[(1 + D) * (kBlock / 64)];
-    const int64_t w = blockIdx.x;
+    const int64_t q = blockIdx.x;
+    if (q >= (a.qlist ? (int64_t)*a.qcount : a.nq)) return;  // uniform per workgroup
     double acc[1 + D];
 #pragma unroll
     for (int j = 0; j <= D; ++j) acc[j] = 0.0;
     for (int ch = threadIdx.x; ch < a.nchunk; ch += kBlock) {
-        const double *p = a.partial + ((int64_t)ch * a.nq + w) * 4;
+        const double *p = a.partial + ((int64_t)ch * a.nq + q) * 4;
 #pragma unroll
         for (int j = 0; j <= D; ++j) acc[j] += p[j];
     }
     block_sum0<1 + D>(acc, lds);
-    if (threadIdx.x == 0) shared_finish<D>(a, w, acc);
+    if (threadIdx.x == 0) shared_finish<D>(a, a.qlist ? (int64_t)a.qlist[q] : q, acc);
 }
 
 // the count of a shared list advances after the finalize kernel (kernel

@@ -65,6 +65,13 @@ struct Plan {
     // state sub-buffers
     Sub s_hdr, s_count, s_c[kMaxBiasDim], s_h, s_N, s_Fsum;
     size_t state_bytes = 0;
+    // surrogate network (state: FP32 master weights, bf16 copies, Adam
+    // moments, certified cells; workspace: samples, training tangents)
+    int32_t sgP = 0;
+    int64_t sgN = 0, sgCells = 0, sgCorners = 0;
+    Sub s_sgP32, s_sgPb, s_sgM, s_sgV, s_sgMask;
+    Sub w_sgX, w_sgVt, w_sgGt, w_sgVn, w_sgGn, w_sgA2, w_sgDz2, w_sgY, w_sgDy, w_sgGpart, w_sgGsum, w_sgLoss;
+    Sub w_sgFlag, w_sgList, w_sgCnt;
     // workspace sub-buffers
     Sub w_xi, w_V, w_dV, w_J, w_part, w_cnpart;
     Sub w_atom_off, w_tiles, w_wrec;
@@ -107,6 +114,16 @@ struct sx_ctx {
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // surrogate network of the bias of hill list 0
+    int32_t sg_H = 0;  // 0: none
+    int64_t sg_max_samples = 0;
+    int32_t sg_max_batch = 0, sg_cert_n = 0;
+    double sg_tol = 0.1;
+    double sg_mu[kMaxBiasDim] = {0, 0, 0}, sg_inv_s[kMaxBiasDim] = {1, 1, 1};
+    double sg_out_scale = 1.0, sg_out_shift = 0.0;
+    double sg_cert_lo[kMaxBiasDim] = {0, 0, 0}, sg_cert_inv_h[kMaxBiasDim] = {0, 0, 0};
+    int64_t sg_t = 0;  // Adam steps taken since the parameters were set
+    bool sg_params = false, sg_certified = false, sg_on = false;
 };
 
 namespace {
@@ -324,6 +341,23 @@ sx_status make_plan(sx_ctx *c)
     p.s_h = ls.take(sizeof(float) * total);
     p.s_N = ls.take(sizeof(uint32_t) * p.W * p.nbins_total);
     p.s_Fsum = ls.take(sizeof(double) * p.W * p.nbins_total * p.D);
+    if (c->sg_H) {
+        if (c->method != M_METAD) return fail(c, SX_EINVAL, "the surrogate network fits a metadynamics bias");
+        if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "the surrogate takes at most 3 CVs");
+        p.sgP = mlp_param_count(c->sg_H, p.D);
+        p.sgCells = 1;
+        p.sgCorners = 1;
+        for (int d = 0; d < p.D; ++d) {
+            p.sgCells *= c->sg_cert_n;
+            p.sgCorners *= c->sg_cert_n + (cv_periodic(c->cvs[d]) ? 0 : 1);
+        }
+        p.sgN = std::max<int64_t>(c->sg_max_samples, p.sgCorners);
+        p.s_sgP32 = ls.take(sizeof(float) * p.sgP);
+        p.s_sgPb = ls.take(sizeof(uint16_t) * p.sgP);
+        p.s_sgM = ls.take(sizeof(float) * p.sgP);
+        p.s_sgV = ls.take(sizeof(float) * p.sgP);
+        p.s_sgMask = ls.take((size_t)p.sgCells);
+    }
     p.state_bytes = ls.cur;
     // workspace layout
     Layout lw;
@@ -341,6 +375,24 @@ sx_status make_plan(sx_ctx *c)
     p.w_touched = lw.take(sizeof(int32_t) * p.U);
     p.w_inv_ptr = lw.take(sizeof(int32_t) * (p.U + 1));
     p.w_inv_slot = lw.take(sizeof(int32_t) * p.nslots);
+    if (c->sg_H) {
+        const size_t N = (size_t)p.sgN, B = (size_t)c->sg_max_batch, H = (size_t)c->sg_H, D = (size_t)p.D;
+        p.w_sgX = lw.take(sizeof(double) * N * D);
+        p.w_sgVt = lw.take(sizeof(double) * N);
+        p.w_sgGt = lw.take(sizeof(double) * N * D);
+        p.w_sgVn = lw.take(sizeof(double) * N);
+        p.w_sgGn = lw.take(sizeof(double) * N * D);
+        p.w_sgA2 = lw.take(sizeof(float) * B * H);
+        p.w_sgDz2 = lw.take(sizeof(float) * D * B * H);
+        p.w_sgY = lw.take(sizeof(float) * B);
+        p.w_sgDy = lw.take(sizeof(float) * B * D);
+        p.w_sgGpart = lw.take(sizeof(float) * (size_t)mlp_bwd_blocks(c->sg_H, (int64_t)B) * (p.sgP + 1));
+        p.w_sgGsum = lw.take(sizeof(double) * (p.sgP + 1));
+        p.w_sgLoss = lw.take(sizeof(double));
+        p.w_sgFlag = lw.take((size_t)p.W);
+        p.w_sgList = lw.take(sizeof(int32_t) * p.W);
+        p.w_sgCnt = lw.take(sizeof(int32_t));
+    }
     p.ws_bytes = lw.cur;
     p.valid = true;
     c->plan = std::move(p);
@@ -482,6 +534,63 @@ SharedArgs shared_args(sx_ctx *c, int wl, const double *xi, int64_t nq)
     return a;
 }
 
+MlpArgs mlp_args(sx_ctx *c)
+{
+    const Plan &p = c->plan;
+    MlpArgs a{};
+    a.D = p.D;
+    a.H = c->sg_H;
+    for (int d = 0; d < p.D; ++d) {
+        a.periodic[d] = cv_periodic(c->cvs[d]) ? 1 : 0;
+        a.mu[d] = c->sg_mu[d];
+        a.inv_s[d] = c->sg_inv_s[d];
+        a.cert_lo[d] = c->sg_cert_lo[d];
+        a.cert_inv_h[d] = c->sg_cert_inv_h[d];
+    }
+    a.Pb = at<uint16_t>(c->state, p.s_sgPb);
+    a.Pw = at<uint16_t>(c->state, p.s_sgPb);
+    a.P32 = at<float>(c->state, p.s_sgP32);
+    a.m = at<float>(c->state, p.s_sgM);
+    a.v = at<float>(c->state, p.s_sgV);
+    a.nmax = c->sg_max_batch;
+    a.out_scale = c->sg_out_scale;
+    a.out_shift = c->sg_out_shift;
+    a.cert_n = c->sg_cert_n;
+    a.mask = at<uint8_t>(c->state, p.s_sgMask);
+    return a;
+}
+
+// the surrogate's step: network for every walker, exact sum of the shared
+// list for the walkers outside the certified cells, forces from both
+sx_status enqueue_surrogate_step(sx_ctx *c, int64_t step, double *xi, float *J, double *xi_out, double *V_out,
+                                 double *dVdxi_out, float *forces, int32_t layout)
+{
+    const Plan &p = c->plan;
+    double *V = at<double>(c->ws, p.w_V), *dV = at<double>(c->ws, p.w_dV);
+    uint8_t *flag = at<uint8_t>(c->ws, p.w_sgFlag);
+    int32_t *list = at<int32_t>(c->ws, p.w_sgList), *cnt = at<int32_t>(c->ws, p.w_sgCnt);
+    hipError_t e = launch_mlp_fwd(mlp_args(c), xi, p.W, V, dV, nullptr, nullptr, nullptr, nullptr, flag, c->stream);
+    if (e == hipSuccess) e = launch_compact(flag, p.W, list, cnt, c->stream);
+    if (e == hipSuccess) {
+        SharedArgs a = shared_args(c, 0, xi, p.W);
+        a.qlist = list;
+        a.qcount = cnt;
+        a.V_ws = V;
+        a.dV_ws = dV;
+        a.deposit = 0;  // a surrogate stands in for a frozen bias
+        a.count_step = 1;
+        a.step = step;
+        e = launch_hill_shared(a, c->stream);
+    }
+    if (e == hipSuccess)
+        e = launch_outputs(p.W, p.D, xi, V, dV, xi_out, V_out, dVdxi_out,
+                           reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8), c->stream);
+    if (e == hipSuccess && forces)
+        e = launch_gather(tabs_of(c), J, p.nslots, p.D, dV, -1.0, force_view(c, forces, layout), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "surrogate step kernels");
+    return SX_OK;
+}
+
 sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J)
 {
     const Plan &p = c->plan;
@@ -500,12 +609,15 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
     double *xi = at<double>(c->ws, p.w_xi);
     float *J = at<float>(c->ws, p.w_J);
     if (c->method == M_NONE) return fail(c, SX_ESTATE, "no method configured (sx_metad_config / sx_abf_config)");
-    const bool fuse = c->method == M_METAD && p.all_dihedral && !c->shared;
+    const bool fuse = c->method == M_METAD && p.all_dihedral && !c->shared && !c->sg_on;
     if (!fuse) {
         sx_status st = launch_cvs(c, pv, xi, J);
         if (st != SX_OK) return st;
     }
-    if (c->method == M_METAD && c->shared) {
+    if (c->method == M_METAD && !c->sg_on && c->stride > 0) c->sg_certified = false;  // may deposit
+    if (c->sg_on) {
+        return enqueue_surrogate_step(c, step, xi, J, xi_out, V_out, dVdxi_out, forces, layout);
+    } else if (c->method == M_METAD && c->shared) {
         SharedArgs a = shared_args(c, 0, xi, p.W);
         a.V_ws = at<double>(c->ws, p.w_V);
         a.dV_ws = at<double>(c->ws, p.w_dV);
@@ -981,6 +1093,7 @@ sx_status sx_hillsum(sx_ctx *ctx, const double *xi, double *V_out, double *dVdxi
 
 sx_status sx_deposit(sx_ctx *ctx, const double *xi)
 {
+    if (ctx) ctx->sg_certified = ctx->sg_on = false;  // the bias (or network) changes
     if (sx_status s = require_bound(ctx)) return s;
     if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
     if (!xi) return fail(ctx, SX_EINVAL, "xi is NULL");
@@ -1021,8 +1134,315 @@ sx_status sx_bias_eval(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n,
     SX_GUARD_END
 }
 
+// --------------------------------------------------------------- surrogate
+sx_status sx_surrogate_config(sx_ctx *ctx, int32_t hidden, int64_t max_samples, int32_t max_batch, int32_t cert_n,
+                              double tol_force)
+{
+    if (!ctx) return SX_EINVAL;
+    if (sx_status s = require_unbound(ctx)) return s;
+    if (hidden != 0 && hidden != 64 && hidden != 128) return fail(ctx, SX_EINVAL, "hidden width must be 64 or 128");
+    if (hidden && (max_samples < 1 || max_samples > ((int64_t)1 << 26)))
+        return fail(ctx, SX_EINVAL, "max_samples must be in [1, 2^26]");
+    if (hidden && (max_batch < 1 || max_batch > (1 << 16))) return fail(ctx, SX_EINVAL, "max_batch must be in [1, 65536]");
+    if (hidden && (cert_n < 1 || cert_n > 4096)) return fail(ctx, SX_EINVAL, "cert_n must be in [1, 4096]");
+    if (hidden && !(tol_force > 0)) return fail(ctx, SX_EINVAL, "tol_force must be > 0");
+    ctx->sg_H = hidden;
+    ctx->sg_max_samples = max_samples;
+    ctx->sg_max_batch = max_batch;
+    ctx->sg_cert_n = cert_n;
+    ctx->sg_tol = tol_force;
+    invalidate(ctx);
+    return SX_OK;
+}
+
+sx_status sx_surrogate_norm(sx_ctx *ctx, const double *mu, const double *s)
+{
+    if (!ctx) return SX_EINVAL;
+    const int D = (int)ctx->cvs.size();
+    if (!mu || !s || D < 1 || D > kMaxBiasDim) return fail(ctx, SX_EINVAL, "bad normalisation arrays");
+    for (int d = 0; d < D; ++d)
+        if (!(s[d] > 0) || !std::isfinite(mu[d])) return fail(ctx, SX_EINVAL, "scales must be > 0");
+    for (int d = 0; d < D; ++d) {
+        ctx->sg_mu[d] = mu[d];
+        ctx->sg_inv_s[d] = 1.0 / s[d];
+    }
+    ctx->sg_certified = ctx->sg_on = false;
+    return SX_OK;
+}
+
+int64_t sx_surrogate_param_count(const sx_ctx *ctx)
+{
+    if (!ctx || !ctx->sg_H || ctx->cvs.empty() || ctx->cvs.size() > (size_t)kMaxBiasDim) return 0;
+    return mlp_param_count(ctx->sg_H, (int32_t)ctx->cvs.size());
+}
+
+static sx_status require_surrogate(sx_ctx *ctx)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (!ctx->sg_H) return fail(ctx, SX_ESTATE, "no surrogate configured (sx_surrogate_config)");
+    return SX_OK;
+}
+
+sx_status sx_surrogate_params_set(sx_ctx *ctx, const float *params, int64_t count)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    const Plan &p = ctx->plan;
+    if (!params || count != p.sgP) return fail(ctx, SX_EINVAL, "parameter count mismatch");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(at<float>(ctx->state, p.s_sgP32), params, sizeof(float) * p.sgP, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_zero_bytes(ctx->state + p.s_sgM.off, (int64_t)(sizeof(float) * p.sgP), ctx->stream);
+    if (e == hipSuccess) e = launch_zero_bytes(ctx->state + p.s_sgV.off, (int64_t)(sizeof(float) * p.sgP), ctx->stream);
+    if (e == hipSuccess) e = launch_mlp_round(mlp_args(ctx), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "parameter upload");
+    ctx->sg_t = 0;
+    ctx->sg_params = true;
+    ctx->sg_certified = ctx->sg_on = false;
+    return SX_OK;
+}
+
+sx_status sx_surrogate_params_get(sx_ctx *ctx, float *params, int64_t count)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    const Plan &p = ctx->plan;
+    if (!params || count != p.sgP) return fail(ctx, SX_EINVAL, "parameter count mismatch");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(params, at<float>(ctx->state, p.s_sgP32), sizeof(float) * p.sgP, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "parameter read");
+    return SX_OK;
+}
+
+sx_status sx_surrogate_output(sx_ctx *ctx, double scale, double shift)
+{
+    if (!ctx) return SX_EINVAL;
+    if (!(scale != 0) || !std::isfinite(scale) || !std::isfinite(shift)) return fail(ctx, SX_EINVAL, "bad output affine");
+    ctx->sg_out_scale = scale;
+    ctx->sg_out_shift = shift;
+    ctx->sg_certified = ctx->sg_on = false;
+    return SX_OK;
+}
+
+sx_status sx_surrogate_output_get(const sx_ctx *ctx, double *scale, double *shift)
+{
+    if (!ctx || !scale || !shift) return SX_EINVAL;
+    *scale = ctx->sg_out_scale;
+    *shift = ctx->sg_out_shift;
+    return SX_OK;
+}
+
+sx_status sx_surrogate_eval(sx_ctx *ctx, const double *xi, int64_t n, double *V_out, double *dVdxi_out, uint8_t *fallback)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (!ctx->sg_params) return fail(ctx, SX_ESTATE, "surrogate parameters not set");
+    if (fallback && !ctx->sg_certified) return fail(ctx, SX_ESTATE, "surrogate not certified (sx_surrogate_certify)");
+    if (n < 0 || (n > 0 && !xi)) return fail(ctx, SX_EINVAL, "bad query points");
+    if (n == 0) return SX_OK;
+    hipError_t e = launch_mlp_fwd(mlp_args(ctx), xi, n, V_out, dVdxi_out, nullptr, nullptr, nullptr, nullptr, fallback,
+                                  ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "surrogate forward");
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_surrogate_loss_grad(sx_ctx *ctx, const double *xi, const double *V, const double *G, int64_t n,
+                                 double alpha, double beta, double *grad_host, double *loss_host)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    SX_GUARD_BEGIN
+    const Plan &p = ctx->plan;
+    if (!ctx->sg_params) return fail(ctx, SX_ESTATE, "surrogate parameters not set");
+    if (n < 1 || n > ctx->sg_max_batch || !xi || !V || !G) return fail(ctx, SX_EINVAL, "n must be in [1, max_batch]");
+    const MlpArgs a = mlp_args(ctx);
+    float *gpart = at<float>(ctx->ws, p.w_sgGpart);
+    double *gsum = at<double>(ctx->ws, p.w_sgGsum);
+    hipError_t e = launch_mlp_train_step(a, xi, V, G, n, (float)alpha, (float)beta, 0.f, 1, at<float>(ctx->ws, p.w_sgA2),
+                                         at<float>(ctx->ws, p.w_sgDz2), at<float>(ctx->ws, p.w_sgY),
+                                         at<float>(ctx->ws, p.w_sgDy), gpart, nullptr, ctx->stream);
+    if (e == hipSuccess) e = launch_mlp_grad_sum(a, gpart, n, gsum, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    std::vector<double> g(p.sgP + 1);
+    if (e == hipSuccess) e = hipMemcpy(g.data(), gsum, sizeof(double) * (p.sgP + 1), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "surrogate gradient");
+    if (grad_host) std::memcpy(grad_host, g.data(), sizeof(double) * p.sgP);
+    if (loss_host) *loss_host = g[p.sgP] / (double)n;
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_surrogate_fit(sx_ctx *ctx, const double *xi, const double *V, const double *G, int64_t n, int32_t batch,
+                           int32_t steps, double lr, double lr_final, double alpha, double beta, double *loss_out)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    SX_GUARD_BEGIN
+    const Plan &p = ctx->plan;
+    if (!ctx->sg_params) return fail(ctx, SX_ESTATE, "surrogate parameters not set");
+    if (n < 1 || !xi || !V || !G) return fail(ctx, SX_EINVAL, "bad samples");
+    if (batch < 1 || batch > ctx->sg_max_batch) return fail(ctx, SX_EINVAL, "batch must be in [1, max_batch]");
+    if (steps < 0 || !(lr > 0) || lr_final < 0 || lr_final > lr) return fail(ctx, SX_EINVAL, "bad schedule");
+    const MlpArgs a = mlp_args(ctx);
+    double *loss = at<double>(ctx->ws, p.w_sgLoss);
+    int64_t last = 1;
+    hipError_t e = hipSuccess;
+    for (int32_t k = 0; k < steps && e == hipSuccess; ++k) {
+        const int64_t i0 = ((int64_t)k * batch) % n;
+        const int64_t len = std::min<int64_t>(batch, n - i0);
+        // cosine decay from lr to lr_final over the call
+        const double lr_k = lr_final + (lr - lr_final) * 0.5 * (1.0 + std::cos(M_PI * k / std::max(1, steps)));
+        ++ctx->sg_t;
+        last = len;
+        e = launch_mlp_train_step(a, xi + i0 * p.D, V + i0, G + i0 * p.D, len, (float)alpha, (float)beta, (float)lr_k,
+                                  ctx->sg_t, at<float>(ctx->ws, p.w_sgA2), at<float>(ctx->ws, p.w_sgDz2),
+                                  at<float>(ctx->ws, p.w_sgY), at<float>(ctx->ws, p.w_sgDy),
+                                  at<float>(ctx->ws, p.w_sgGpart), k == steps - 1 ? loss : nullptr, ctx->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    double l = 0;
+    if (e == hipSuccess && steps > 0) e = hipMemcpy(&l, loss, sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "surrogate training");
+    if (loss_out) *loss_out = steps > 0 ? l / (double)last : 0.0;
+    ctx->sg_certified = ctx->sg_on = false;
+    return SX_OK;
+    SX_GUARD_END
+}
+
+// exact V and dV/dxi of hill list 0 at n device points (batched shared sums)
+static sx_status exact_bias(sx_ctx *ctx, const double *xi, int64_t n, double *V, double *G)
+{
+    const int D = ctx->plan.D;
+    for (int64_t i0 = 0; i0 < n; i0 += kEvalBatch) {
+        const int64_t m = std::min<int64_t>(kEvalBatch, n - i0);
+        SharedArgs a = shared_args(ctx, 0, xi + i0 * D, m);
+        a.V_out = V + i0;
+        a.dV_out = G + i0 * D;
+        hipError_t e = launch_hill_shared(a, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "exact bias kernels");
+    }
+    return SX_OK;
+}
+
+sx_status sx_surrogate_train(sx_ctx *ctx, const double *xi, int64_t n, int32_t batch, int32_t steps, double lr,
+                             double lr_final, double *loss_out)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    SX_GUARD_BEGIN
+    const Plan &p = ctx->plan;
+    if (!ctx->sg_params) return fail(ctx, SX_ESTATE, "surrogate parameters not set");
+    if (n < 2 || n > ctx->sg_max_samples || !xi) return fail(ctx, SX_EINVAL, "n must be in [2, max_samples]");
+    double *Vt = at<double>(ctx->ws, p.w_sgVt), *Gt = at<double>(ctx->ws, p.w_sgGt);
+    if (sx_status st = exact_bias(ctx, xi, n, Vt, Gt)) return st;
+    std::vector<double> hv(n), hg((size_t)n * p.D);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(hv.data(), Vt, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hg.data(), Gt, sizeof(double) * n * p.D, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "training targets");
+    // Sobolev loss weights: unit-variance V in network units, and the
+    // gradient term divided by the gradient variance in those units
+    double mv = 0, vv = 0;
+    for (double v : hv) mv += v;
+    mv /= (double)n;
+    for (double v : hv) vv += (v - mv) * (v - mv);
+    const double sv = std::sqrt(vv / (double)(n - 1));
+    if (!(sv > 0) || !std::isfinite(sv)) return fail(ctx, SX_EINVAL, "the bias is constant over the samples");
+    double vg = 0;
+    for (int d = 0; d < p.D; ++d) {
+        double m = 0, q = 0;
+        for (int64_t i = 0; i < n; ++i) m += hg[(size_t)i * p.D + d];
+        m /= (double)n;
+        for (int64_t i = 0; i < n; ++i) q += (hg[(size_t)i * p.D + d] - m) * (hg[(size_t)i * p.D + d] - m);
+        vg += q / (double)(n - 1) / (sv * sv);
+    }
+    vg /= p.D;
+    ctx->sg_out_shift = mv;
+    ctx->sg_out_scale = sv;
+    const double beta = vg > 0 ? 1.0 / vg : 1.0;
+    return sx_surrogate_fit(ctx, xi, Vt, Gt, n, batch, steps, lr, lr_final, 1.0, beta, loss_out);
+    SX_GUARD_END
+}
+
+sx_status sx_surrogate_certify(sx_ctx *ctx, const double *lo, const double *hi, double *certified_fraction)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    SX_GUARD_BEGIN
+    const Plan &p = ctx->plan;
+    if (!ctx->sg_params) return fail(ctx, SX_ESTATE, "surrogate parameters not set");
+    const int D = p.D, n = ctx->sg_cert_n;
+    double h[kMaxBiasDim] = {1, 1, 1};
+    int64_t npts[kMaxBiasDim] = {1, 1, 1};
+    for (int d = 0; d < D; ++d) {
+        if (cv_periodic(ctx->cvs[d])) {
+            ctx->sg_cert_lo[d] = -M_PI;
+            h[d] = kTwoPi / n;
+            npts[d] = n;
+        } else {
+            if (!lo || !hi || !(hi[d] > lo[d])) return fail(ctx, SX_EINVAL, "a non-periodic CV needs lo < hi");
+            ctx->sg_cert_lo[d] = lo[d];
+            h[d] = (hi[d] - lo[d]) / n;
+            npts[d] = n + 1;
+        }
+        ctx->sg_cert_inv_h[d] = 1.0 / h[d];
+    }
+    // grid corners, row-major with the first CV slowest
+    const int64_t M = p.sgCorners;
+    std::vector<double> pts((size_t)M * D);
+    for (int64_t i = 0; i < M; ++i) {
+        int64_t r = i;
+        for (int d = D - 1; d >= 0; --d) {
+            pts[(size_t)i * D + d] = ctx->sg_cert_lo[d] + (double)(r % npts[d]) * h[d];
+            r /= npts[d];
+        }
+    }
+    double *X = at<double>(ctx->ws, p.w_sgX);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(X, pts.data(), sizeof(double) * M * D, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "certification grid upload");
+    double *Gt = at<double>(ctx->ws, p.w_sgGt), *Gn = at<double>(ctx->ws, p.w_sgGn);
+    if (sx_status st = exact_bias(ctx, X, M, at<double>(ctx->ws, p.w_sgVt), Gt)) return st;
+    const MlpArgs a = mlp_args(ctx);
+    uint8_t *mask = at<uint8_t>(ctx->state, p.s_sgMask);
+    e = launch_mlp_fwd(a, X, M, at<double>(ctx->ws, p.w_sgVn), Gn, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       ctx->stream);
+    if (e == hipSuccess) e = launch_cert_mask(a, Gn, Gt, h, ctx->sg_tol, mask, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    std::vector<uint8_t> hm((size_t)p.sgCells);
+    if (e == hipSuccess) e = hipMemcpy(hm.data(), mask, (size_t)p.sgCells, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "certification");
+    int64_t ok = 0;
+    for (uint8_t v : hm) ok += v;
+    if (certified_fraction) *certified_fraction = (double)ok / (double)p.sgCells;
+    ctx->sg_certified = true;
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_surrogate_enable(sx_ctx *ctx, int32_t on)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    if (on) {
+        if (!ctx->sg_params || !ctx->sg_certified)
+            return fail(ctx, SX_ESTATE, "the surrogate needs parameters and a certification first");
+        if (!ctx->shared && ctx->plan.W != 1)
+            return fail(ctx, SX_ESTATE, "the surrogate replaces one bias: use a shared hill list or one walker");
+    }
+    ctx->sg_on = on != 0;
+    return SX_OK;
+}
+
+sx_status sx_surrogate_fallback_count(sx_ctx *ctx, int32_t *count)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    if (!count) return fail(ctx, SX_EINVAL, "NULL count");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(count, at<int32_t>(ctx->ws, ctx->plan.w_sgCnt), 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fallback count read");
+    return SX_OK;
+}
+
 sx_status sx_hills_set(sx_ctx *ctx, int32_t walker, const float *centers, const float *heights, int64_t K)
 {
+    if (ctx) ctx->sg_certified = ctx->sg_on = false;  // the bias (or network) changes
     if (sx_status s = require_bound(ctx)) return s;
     SX_GUARD_BEGIN
     if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
@@ -1111,7 +1531,8 @@ static uint64_t config_hash(const sx_ctx *c)
     std::ostringstream os;
     os.precision(17);
     os << c->method << ' ' << c->shared << ' ' << c->plan.W << ' ' << c->plan.D << ' ' << c->plan.nslots << ' ' << c->plan.total_cap << ' '
-       << c->plan.nbins_total << ' ' << c->height << ' ' << c->kdT << ' ' << c->stride;
+       << c->plan.nbins_total << ' ' << c->height << ' ' << c->kdT << ' ' << c->stride << ' ' << c->sg_H << ' '
+       << c->sg_cert_n << ' ' << c->plan.sgP;
     for (int d = 0; d < c->plan.D; ++d) os << ' ' << c->sigma[d] << ' ' << c->lo[d] << ' ' << c->hi[d];
     for (auto v : c->plan.hill_cap) os << ' ' << v;
     std::string s = os.str();
@@ -1146,6 +1567,8 @@ sx_status sx_state_export(sx_ctx *ctx, void *host, size_t bytes)
 
 sx_status sx_state_import(sx_ctx *ctx, const void *host, size_t bytes)
 {
+    if (ctx) ctx->sg_certified = ctx->sg_on = false;  // the bias (or network) changes
+    if (ctx && ctx->sg_H) ctx->sg_params = true;     // the weights come with the state
     if (sx_status s = require_bound(ctx)) return s;
     const size_t need = 64 + ctx->plan.state_bytes;
     if (!host || bytes < need) return fail(ctx, SX_EINVAL, "checkpoint too short");

@@ -184,6 +184,7 @@ struct MlpArgs {
     uint16_t *Pw;        // the same, written by the optimiser
     float *P32, *m, *v;  // FP32 master parameters, Adam moments
     int64_t nmax;        // row stride of the training tangents
+    double out_scale, out_shift;  // V = out_shift + out_scale * y (FP32 network output y)
     double cert_lo[kMaxBiasDim], cert_inv_h[kMaxBiasDim];
     int32_t cert_n;
     const uint8_t *mask;  // certified cells (1) of the cert_n^D grid
@@ -210,6 +211,20 @@ hipError_t launch_mlp_train_step(const MlpArgs &a, const double *xi, const doubl
                                  float alpha, float beta, float lr, int64_t t, float *t_a2, float *t_dz2, float *t_y,
                                  float *t_dy, float *gpart, double *loss_out, hipStream_t s);
 hipError_t launch_mlp_round(const MlpArgs &a, hipStream_t s);
+// ordered FP64 sum of the per-workgroup gradients of the last reverse pass
+// over n samples into gsum[P] and the loss sum into gsum[P]
+hipError_t launch_mlp_grad_sum(const MlpArgs &a, const float *gpart, int64_t n, double *gsum, hipStream_t s);
+// certification: one lane per cell of the cert_n^D grid; dVhat and dV
+// [M][D] hold the network's and the exact gradient at the M grid corners
+// (row-major, the first CV slowest; periodic CVs: cert_n corners per CV,
+// others cert_n + 1); a cell is certified when the largest corner error
+// plus twice its corner-estimated Lipschitz growth over the half diagonal
+// stays within tol
+hipError_t launch_cert_mask(const MlpArgs &a, const double *dVhat, const double *dV, const double *h, double tol,
+                            uint8_t *mask, hipStream_t s);
+// per-walker outputs after a surrogate step (xi, V, dV/dxi copies, finiteness)
+hipError_t launch_outputs(int32_t W, int32_t D, const double *xi, const double *V, const double *dV, double *xi_out,
+                          double *V_out, double *dV_out, uint32_t *flags, hipStream_t s);
 hipError_t launch_compact(const uint8_t *flag, int32_t n, int32_t *list, int32_t *count, hipStream_t s);
 hipError_t launch_gather(const WalkerTabs &t, const float *J, int32_t nslots, int32_t D, const double *coef,
                          double coef_sign, ForceView out, hipStream_t s);

@@ -163,3 +163,11 @@ def walkers_inputs(n_walkers=256, seed=3, atoms=(22, 5000), hills=(1000, 50000),
     hill_off = np.concatenate([[0], np.cumsum(n_hills)]).astype(np.int64)
     return {"pos": pos.astype(dtype), "atom_off": atom_off, "n_atoms": n_atoms, "n_hills": n_hills,
             "hill_off": hill_off, "centers": centers, "heights": heights, "cvs": backbone_cvs(1)}
+
+
+def chain_walkers(n_walkers, n_atoms=22, seed=4, dtype=np.float32):
+    """n_walkers independent chains of n_atoms atoms (each its own random
+    torsions, so the walkers' dihedrals spread over the torus), stacked:
+    positions (n_walkers * n_atoms, 3) and walker atom offsets."""
+    pos = np.concatenate([chain_template(n_atoms, seed * 100003 + w) for w in range(n_walkers)])
+    return pos.astype(dtype), np.arange(n_walkers + 1, dtype=np.int64) * n_atoms

@@ -96,3 +96,16 @@ def test_bf16_rounding():
     x = rng.normal(size=1000)
     r = mlp.round_bf16(x)
     assert np.max(np.abs(r - x) / np.abs(x)) <= 2 ** -8
+
+
+def test_bf16_pair_rounding():
+    # values with at most 16 significant bits (8 + 8, both halves exact) survive
+    for v in [1.0 + 2 ** -7 + 2 ** -15, -(3.0 + 2 ** -12), 0.75 + 2 ** -20]:
+        assert mlp.round_bf16x2(v) == v
+    x = rng.normal(size=5000)
+    r = mlp.round_bf16x2(x)
+    # hi carries 8 bits, lo rounds the remainder (< half an ulp of hi) to 8 bits
+    assert np.max(np.abs(r - x) / np.abs(x)) <= 2.0 ** -16
+    assert np.max(np.abs(r - x) / np.abs(x)) > 2.0 ** -20  # not the identity
+    # the pair is at least as close as the single bf16 value
+    assert np.all(np.abs(r - x) <= np.abs(mlp.round_bf16(x) - x))
