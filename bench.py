@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="after the run, copy this many MiB with the plain copy probe (counter calibration)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
-    ap.add_argument("--sg-train-steps", type=int, default=40000, help="Adam steps of the surrogate fit")
+    ap.add_argument("--sg-train-steps", type=int, default=100000, help="Adam steps of the surrogate fit")
     ap.add_argument("--sg-steps", type=int, default=2000, help="timed steps of each surrogate-workload path")
     return ap.parse_args()
 

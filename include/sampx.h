@@ -250,7 +250,10 @@ sx_status sx_graph_capture(sx_ctx *ctx, int32_t n_steps, const void *pos, int32_
 sx_status sx_graph_launch(sx_ctx *ctx);
 /* Launch parameters of the hill-sum kernel: hills per tile (1024, 2048,
  * 4096 or 8192) and persistent grid size (0: one workgroup per
- * tile).  Changing the tile rebuilds the tile table (host, synchronous). */
+ * tile).  Changing the tile rebuilds the tile table (host, synchronous).
+ * With a shared hill list `grid` is instead the number of workgroups the
+ * step's shared sum aims at (chunks x query blocks; 0: 2048) and the tile
+ * is unused. */
 sx_status sx_set_tuning(sx_ctx *ctx, int32_t tile_hills, int32_t grid);
 sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
 /* Time candidate tilings of the step's hill-sum kernels on the bound state

@@ -22,6 +22,7 @@
 //      gathers the force onto the walker's atoms.  The kernel boundary is the
 //      only cross-workgroup synchronisation: no fences, no atomics.
 #include "dev_cv.h"
+#include "dev_gather.h"
 
 namespace sx {
 namespace {
@@ -71,30 +72,6 @@ __device__ __forceinline__ float hill_term(const double (&xi)[D], const float (&
 __device__ __forceinline__ float comp(const float4 &v, int i)
 {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
-}
-
-// Gather of a bias force onto walker w's touched atoms:
-//   F_i += sum_{slots s of atom i} coef[cv(s)] * Jw[s]
-// Jw: the walker's Jacobian slots (s x 3 floats).
-__device__ __forceinline__ void gather_forces(const WalkerTabs &t, const float *Jw, int32_t w, const double *coef,
-                                              const ForceView &F)
-{
-    const int64_t ab = t.atom_off[w];
-    for (int u = threadIdx.x; u < t.U; u += blockDim.x) {
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
-            const int32_t s = t.inv_slot[q];
-            const double cf = coef[t.slot_cv[s]];
-            const float *js = Jw + (int64_t)s * 3;
-            fx += cf * (double)js[0];
-            fy += cf * (double)js[1];
-            fz += cf * (double)js[2];
-        }
-        float *f = F.ptr + (ab + t.touched[u]) * F.sa;
-        f[0] += (float)fx;
-        f[F.sk] += (float)fy;
-        f[2 * F.sk] += (float)fz;
-    }
 }
 
 constexpr int kBatch = 8;  // float4 groups loaded per lane before use

@@ -22,6 +22,8 @@
 //               Adam (Kingma & Ba 2015) to the FP32 master weights, then
 //               refreshes their bf16 copies.
 #include "sx_internal.h"
+#include "dev_cv.h"
+#include "dev_gather.h"
 
 namespace sx {
 namespace {
@@ -42,6 +44,15 @@ __host__ __device__ constexpr POff poff(int H, int F)
 }
 
 __device__ __forceinline__ float bf(const uint16_t *p, int i) { return (float)reinterpret_cast<const __bf16 *>(p)[i]; }
+
+// tanh x = sign(x) (1 - 2 / (exp(2|x|) + 1)) with v_exp_f32 and v_rcp_f32:
+// absolute error a few 1e-8, no overflow (exp -> inf gives 1)
+__device__ __forceinline__ float tanh_fast(float x)
+{
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * fabsf(x));  // 2 log2(e) |x|
+    const float t = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+    return copysignf(t, x);
+}
 
 // features and their CV tangents for one sample
 template <int D>
@@ -75,24 +86,77 @@ __device__ __forceinline__ void featurize(const MlpArgs &a, const double *xi, fl
 // (FP64); for training, the per-sample a2[n][H], dz2[D][n][H], y[n],
 // dy[n][D] (FP32).  Inference with a certification mask: mask != null marks
 // samples whose cell is not certified (flag[i] = 1).
-template <int H, int D>
+// certification flag of one sample: 1 if its cell of the cert_n^D grid is
+// not certified (or lies outside the grid)
+template <int D>
+__device__ __forceinline__ uint8_t fallback_flag(const MlpArgs &a, const double *x)
+{
+    int64_t cell = 0;
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        int64_t i = (int64_t)floor((x[d] - a.cert_lo[d]) * a.cert_inv_h[d]);
+        if (a.periodic[d]) {
+            i %= a.cert_n;
+            if (i < 0) i += a.cert_n;
+        } else if (i < 0 || i >= a.cert_n) {
+            inside = false;
+        }
+        cell = cell * a.cert_n + (inside ? i : 0);
+    }
+    return (inside && a.mask[cell]) ? 0 : 1;
+}
+
+template <int H, int D, bool CVF>
 __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi, int64_t n, double *V, double *dV,
                                                      float *t_a2, float *t_dz2, float *t_y, float *t_dy,
-                                                     uint8_t *flag)
+                                                     uint8_t *flag, MlpStep st, int32_t step_on)
 {
     constexpr int F = 2 * D;
     constexpr int KB = H / 32;  // 32-wide K blocks of the H x H product
     constexpr int NT = H / 16;  // 16-wide output tiles
     constexpr POff o = poff(H, F);
+    __shared__ double s_coef[kSamplesPerWave][D];  // surrogate step: -dV/dxi per sample
+    __shared__ uint8_t s_fb[kSamplesPerWave];
     const int lane = threadIdx.x & 63;
-    const int64_t s0 = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kSamplesPerWave;
-    if (s0 >= n) return;  // whole wavefront idle (no barrier in this kernel)
+    const int64_t s0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * kSamplesPerWave;
+    // whole wavefront idle; its workgroup is this wavefront alone whenever the
+    // one barrier below is used
+    if (s0 >= n) return;
     const int row = lane & 15, kg = lane >> 4;
     const int64_t si = s0 + row;  // this lane's sample in the A operand
     const bool live = si < n;
     double x[D];
+    if (CVF) {
+        // the 16 lanes of row group 0 evaluate their walker's dihedrals
+        // (FP64) and store xi and the Jacobian slots; a shuffle hands xi to
+        // the lanes of the other row groups
+        if (kg == 0 && live) {
+            const int64_t aoff = st.tabs.atom_off[si];
 #pragma unroll
-    for (int d = 0; d < D; ++d) x[d] = live ? xi[si * D + d] : 0.0;
+            for (int d = 0; d < D; ++d) {
+                const CvDesc &cv = st.cs.cv[d];
+                double3 g[4];
+                x[d] = dihedral_at<true>(cv, st.pos, aoff, g);
+                st.xi_ws[si * D + d] = x[d];
+                float *js = st.J + (si * st.nslots + cv.slot0) * 3;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    js[3 * q] = (float)g[q].x;
+                    js[3 * q + 1] = (float)g[q].y;
+                    js[3 * q + 2] = (float)g[q].z;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < D; ++d) x[d] = 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = __shfl(x[d], row, 64);
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = live ? xi[si * D + d] : 0.0;
+    }
     float f[F], u[D][F];
     featurize<D>(a, x, f, u);
     // layer 1 for this lane's 8 K entries of every K block (+ tangents),
@@ -114,7 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
 #pragma unroll
                 for (int d = 0; d < D; ++d) dz[d] = fmaf(w, u[d][q], dz[d]);
             }
-            const float a1 = tanhf(z);
+            const float a1 = tanh_fast(z);
             const __bf16 h = (__bf16)a1;
             av[kb][t] = h;
             al[kb][t] = (__bf16)(a1 - (float)h);
@@ -154,7 +218,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
         const float b2 = bf(a.Pb, o.b2 + j), w3 = bf(a.Pb, o.w3 + j);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float a2 = tanhf(acc[r] + b2);
+            const float a2 = tanh_fast(acc[r] + b2);
             const float g = 1.f - a2 * a2;
             yp[r] = fmaf(w3, a2, yp[r]);
             const int64_t sr = crow0 + r;
@@ -175,6 +239,13 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
             for (int d = 0; d < D; ++d) dyp[d][r] += __shfl_xor(dyp[d][r], m, 64);
         }
     }
+    // CVs of this lane's four output samples (rows kg*4 + r), for the
+    // certification lookup and the outputs
+    double xo[4][D];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int d = 0; d < D; ++d) xo[r][d] = __shfl(x[d], kg * 4 + r, 64);
     if (row == 0) {
         const float b3 = bf(a.Pb, o.b3);
 #pragma unroll
@@ -182,31 +253,52 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
             const int64_t sr = crow0 + r;
             if (sr >= n) continue;
             const float y = yp[r] + b3;
-            if (V) V[sr] = a.out_shift + a.out_scale * (double)y;
+            const double Vs = a.out_shift + a.out_scale * (double)y;
+            double dvs[D], xs[D];
+            bool finite = isfinite(Vs);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                dvs[d] = a.out_scale * (double)dyp[d][r];
+                finite = finite && isfinite(dvs[d]);
+            }
+            if (V) V[sr] = Vs;
             if (t_y) t_y[sr] = y;
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                if (dV) dV[sr * D + d] = a.out_scale * (double)dyp[d][r];
+                if (dV) dV[sr * D + d] = dvs[d];
                 if (t_dy) t_dy[sr * D + d] = dyp[d][r];
             }
+            if (!flag) continue;
+#pragma unroll
+            for (int d = 0; d < D; ++d) xs[d] = xo[r][d];
+            const uint8_t fb = fallback_flag<D>(a, xs);
+            flag[sr] = fb;
+            if (!step_on) continue;
+            // a surrogate step: outputs (the fallback overwrites its walkers'
+            // V and dV later) and the force of the walkers served here
+            if (st.V_out) st.V_out[sr] = Vs;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                if (st.dV_out) st.dV_out[sr * D + d] = dvs[d];
+                if (st.xi_out) st.xi_out[sr * D + d] = xs[d];
+            }
+            if (!fb && !finite && st.flags) atomicOr(st.flags, kFlagNonFinite);
+            s_fb[kg * 4 + r] = fb;
+#pragma unroll
+            for (int d = 0; d < D; ++d) s_coef[kg * 4 + r][d] = -dvs[d];
         }
     }
-    // certification mask: lane `row` of group 0 checks its own sample's cell
-    if (flag && kg == 0 && live) {
-        int64_t cell = 0;
-        bool inside = true;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            int64_t i = (int64_t)floor((x[d] - a.cert_lo[d]) * a.cert_inv_h[d]);
-            if (a.periodic[d]) {
-                i %= a.cert_n;
-                if (i < 0) i += a.cert_n;
-            } else if (i < 0 || i >= a.cert_n) {
-                inside = false;
-            }
-            cell = cell * a.cert_n + (inside ? i : 0);
-        }
-        flag[si] = (inside && a.mask[cell]) ? 0 : 1;
+    // force gather of the walkers served here: (sample, touched atom) pairs
+    // over all 64 lanes.  A surrogate step launches one wavefront per
+    // workgroup, so this barrier only orders the wavefront's own LDS traffic.
+    if (!step_on || !st.do_forces) return;
+    __syncthreads();
+    const int U = st.tabs.U;
+    for (int pi = lane; pi < kSamplesPerWave * U; pi += 64) {
+        const int sl = pi / U, u = pi % U;
+        const int64_t sr = s0 + sl;
+        if (sr >= n || s_fb[sl]) continue;
+        gather_atom(st.tabs, st.J + sr * st.nslots * 3, (int32_t)sr, s_coef[sl], st.F, u);
     }
 }
 
@@ -332,7 +424,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
 #pragma unroll
             for (int d = 0; d < D; ++d) dz1[d] = fmaf(w, s_u[sl][d][q], dz1[d]);
         }
-        const float a1 = tanhf(z), g1 = 1.f - a1 * a1;
+        const float a1 = tanh_fast(z), g1 = 1.f - a1 * a1;
         s_a1r[sl][k] = round_bf2(a1);
         float a1b = 0.f, da1b[D];
 #pragma unroll
@@ -393,16 +485,29 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
     }
 }
 
-// one lane per parameter: ordered sum of the workgroup gradients (FP64),
-// Adam on the FP32 master value, refresh of its bf16 copy; lane 0 also
-// sums the loss.
-__global__ void __launch_bounds__(kBlock) k_mlp_adam(MlpArgs a, const float *gpart, int32_t nblk, int32_t P, int64_t t,
+// stage 1 of the gradient sum: lane p of slice y sums the workgroup
+// partials [y * per, (y + 1) * per) of parameter p (index P: the loss) in
+// order, in FP64
+__global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float *gpart, int32_t nblk, int32_t P, int32_t per,
+                                                        double *red)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > P) return;
+    const int b0 = blockIdx.y * per, b1 = min(nblk, b0 + per);
+    double g = 0.0;
+    for (int b = b0; b < b1; ++b) g += (double)gpart[(int64_t)b * (P + 1) + p];
+    red[(int64_t)blockIdx.y * (P + 1) + p] = g;
+}
+
+// stage 2, one lane per parameter: the slices in order, Adam on the FP32
+// master value, refresh of its bf16 copy; lane P writes the loss sum.
+__global__ void __launch_bounds__(kBlock) k_mlp_adam(MlpArgs a, const double *red, int32_t ns, int32_t P, int64_t t,
                                                       float lr, double *loss_out, int32_t update, double *gsum)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p > P) return;
     double g = 0.0;
-    for (int b = 0; b < nblk; ++b) g += (double)gpart[(int64_t)b * (P + 1) + p];
+    for (int y = 0; y < ns; ++y) g += red[(int64_t)y * (P + 1) + p];
     if (gsum) gsum[p] = g;
     if (p == P) {
         if (loss_out) *loss_out = g;  // sum of per-sample losses
@@ -429,13 +534,22 @@ __global__ void k_mlp_round(MlpArgs a, int32_t P)
 
 template <int H, int D>
 hipError_t mlp_fwd_hd(const MlpArgs &a, const double *xi, int64_t n, double *V, double *dV, float *t_a2, float *t_dz2,
-                      float *t_y, float *t_dy, uint8_t *flag, hipStream_t s)
+                      float *t_y, float *t_dy, uint8_t *flag, hipStream_t s, const MlpStep *step)
 {
+    // one wavefront per 16 samples; single-wavefront workgroups spread a
+    // small batch over as many CUs as it has wavefronts
     const int64_t waves = (n + kSamplesPerWave - 1) / kSamplesPerWave;
-    const unsigned blocks = (unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64));
+    const int per = (waves >= 4096 && !step) ? kBlock / 64 : 1;  // a step: one wavefront per workgroup
+    const unsigned blocks = (unsigned)((waves + per - 1) / per);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_mlp_fwd<H, D>), dim3(blocks), dim3(kBlock), 0, s, a, xi, n, V, dV, t_a2, t_dz2, t_y, t_dy,
-                       flag);
+    MlpStep st{};
+    if (step) st = *step;
+    if (step && step->fuse_cv)
+        hipLaunchKernelGGL((k_mlp_fwd<H, D, true>), dim3(blocks), dim3(64 * per), 0, s, a, xi, n, V, dV, t_a2, t_dz2,
+                           t_y, t_dy, flag, st, 1);
+    else
+        hipLaunchKernelGGL((k_mlp_fwd<H, D, false>), dim3(blocks), dim3(64 * per), 0, s, a, xi, n, V, dV, t_a2, t_dz2,
+                           t_y, t_dy, flag, st, step ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -456,36 +570,6 @@ hipError_t mlp_bwd_hd(const MlpArgs &a, const double *xi, const double *Vl, cons
 int32_t mlp_param_count(int32_t H, int32_t D) { return poff(H, 2 * D).P; }
 int32_t mlp_bwd_blocks(int32_t H, int64_t n) { return (int32_t)((n + (H >= 128 ? 8 : 16) - 1) / (H >= 128 ? 8 : 16)); }
 
-// fallback list: walkers whose cell is not certified, in walker order
-// (one workgroup, block-wide exclusive scan over chunks of kBlock walkers)
-__global__ void __launch_bounds__(kBlock) k_compact(const uint8_t *flag, int32_t n, int32_t *list, int32_t *count)
-{
-    __shared__ int32_t s_sum[kBlock];
-    int32_t base = 0;
-    for (int32_t c0 = 0; c0 < n; c0 += kBlock) {
-        const int32_t i = c0 + threadIdx.x;
-        const int32_t v = (i < n && flag[i]) ? 1 : 0;
-        s_sum[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < kBlock; off <<= 1) {  // Hillis-Steele inclusive scan
-            const int32_t add = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0;
-            __syncthreads();
-            s_sum[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (v) list[base + s_sum[threadIdx.x] - 1] = i;
-        base += s_sum[kBlock - 1];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *count = base;
-}
-
-hipError_t launch_compact(const uint8_t *flag, int32_t n, int32_t *list, int32_t *count, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(kBlock), 0, s, flag, n, list, count);
-    return hipGetLastError();
-}
-
 #define SX_MLP_DISPATCH(FN, ...)                                                   \
     switch (a.H * 10 + a.D) {                                                      \
     case 641: return FN<64, 1>(__VA_ARGS__);                                       \
@@ -498,14 +582,29 @@ hipError_t launch_compact(const uint8_t *flag, int32_t n, int32_t *list, int32_t
     }
 
 hipError_t launch_mlp_fwd(const MlpArgs &a, const double *xi, int64_t n, double *V, double *dV, float *t_a2,
-                          float *t_dz2, float *t_y, float *t_dy, uint8_t *flag, hipStream_t s)
+                          float *t_dz2, float *t_y, float *t_dy, uint8_t *flag, hipStream_t s, const MlpStep *step)
 {
-    SX_MLP_DISPATCH(mlp_fwd_hd, a, xi, n, V, dV, t_a2, t_dz2, t_y, t_dy, flag, s)
+    SX_MLP_DISPATCH(mlp_fwd_hd, a, xi, n, V, dV, t_a2, t_dz2, t_y, t_dy, flag, s, step)
+}
+
+static hipError_t reduce_and_adam(const MlpArgs &a, const float *gpart, int32_t nblk, double *red, float lr, int64_t t,
+                                  double *loss_out, int32_t update, double *gsum, hipStream_t s)
+{
+    const int P = mlp_param_count(a.H, a.D);
+    const int ns = nblk < kMlpRedSlices ? nblk : kMlpRedSlices;
+    const int per = (nblk + ns - 1) / ns;
+    const unsigned gx = (unsigned)((P + 1 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(gx, ns), dim3(kBlock), 0, s, gpart, nblk, P, per, red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_adam, dim3(gx), dim3(kBlock), 0, s, a, (const double *)red, ns, P, t, lr, loss_out, update,
+                       gsum);
+    return hipGetLastError();
 }
 
 hipError_t launch_mlp_train_step(const MlpArgs &a, const double *xi, const double *Vl, const double *Gl, int64_t n,
                                  float alpha, float beta, float lr, int64_t t, float *t_a2, float *t_dz2, float *t_y,
-                                 float *t_dy, float *gpart, double *loss_out, hipStream_t s)
+                                 float *t_dy, float *gpart, double *red, double *loss_out, hipStream_t s)
 {
     hipError_t e = launch_mlp_fwd(a, xi, n, nullptr, nullptr, t_a2, t_dz2, t_y, t_dy, nullptr, s);
     if (e != hipSuccess) return e;
@@ -521,23 +620,14 @@ hipError_t launch_mlp_train_step(const MlpArgs &a, const double *xi, const doubl
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    const int P = mlp_param_count(a.H, a.D);
-    if (lr > 0.f)
-        hipLaunchKernelGGL(k_mlp_adam, dim3((P + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, gpart, nblk, P, t,
-                           lr, loss_out, 1, (double *)nullptr);
-    else if (loss_out)  // gradient only: just the loss sum (lane P)
-        hipLaunchKernelGGL(k_mlp_adam, dim3((P + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, gpart, nblk, P, t,
-                           lr, loss_out, 0, (double *)nullptr);
-    return hipGetLastError();
+    if (lr > 0.f) return reduce_and_adam(a, gpart, nblk, red, lr, t, loss_out, 1, nullptr, s);
+    return hipSuccess;  // gradient only: launch_mlp_grad_sum reads gpart
 }
 
-hipError_t launch_mlp_grad_sum(const MlpArgs &a, const float *gpart, int64_t n, double *gsum, hipStream_t s)
+hipError_t launch_mlp_grad_sum(const MlpArgs &a, const float *gpart, int64_t n, double *red, double *gsum,
+                               hipStream_t s)
 {
-    const int P = mlp_param_count(a.H, a.D);
-    const int32_t nblk = mlp_bwd_blocks(a.H, n);
-    hipLaunchKernelGGL(k_mlp_adam, dim3((P + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a, gpart, nblk, P,
-                       (int64_t)1, 0.f, (double *)nullptr, 0, gsum);
-    return hipGetLastError();
+    return reduce_and_adam(a, gpart, mlp_bwd_blocks(a.H, n), red, 0.f, 1, nullptr, 0, gsum, s);
 }
 
 // ------------------------------------------------------- certification mask
@@ -601,22 +691,6 @@ __global__ void __launch_bounds__(kBlock) k_cert_mask(MlpArgs a, const double *d
     mask[cell] = (isfinite(bound) && bound <= tol) ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_outputs(int32_t W, int32_t D, const double *xi, const double *V,
-                                                     const double *dV, double *xi_out, double *V_out, double *dV_out,
-                                                     uint32_t *flags)
-{
-    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= W) return;
-    bool fin = isfinite(V[w]);
-    if (V_out) V_out[w] = V[w];
-    for (int d = 0; d < D; ++d) {
-        fin = fin && isfinite(dV[(int64_t)w * D + d]);
-        if (xi_out) xi_out[(int64_t)w * D + d] = xi[(int64_t)w * D + d];
-        if (dV_out) dV_out[(int64_t)w * D + d] = dV[(int64_t)w * D + d];
-    }
-    if (!fin && flags) atomicOr(flags, kFlagNonFinite);
-}
-
 hipError_t launch_cert_mask(const MlpArgs &a, const double *dVhat, const double *dV, const double *h, double tol,
                             uint8_t *mask, hipStream_t s)
 {
@@ -633,13 +707,6 @@ hipError_t launch_cert_mask(const MlpArgs &a, const double *dVhat, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_outputs(int32_t W, int32_t D, const double *xi, const double *V, const double *dV, double *xi_out,
-                          double *V_out, double *dV_out, uint32_t *flags, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_outputs, dim3((W + kBlock - 1) / kBlock), dim3(kBlock), 0, s, W, D, xi, V, dV, xi_out, V_out,
-                       dV_out, flags);
-    return hipGetLastError();
-}
 
 hipError_t launch_mlp_round(const MlpArgs &a, hipStream_t s)
 {

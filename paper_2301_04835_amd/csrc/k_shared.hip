@@ -4,96 +4,129 @@
 //
 // Unlike the private-list sum, every hill is reused by every query, so the
 // work is bound by VALU arithmetic, not by HBM:
-//   * grid x: hill chunks (a multiple of 256 hills, sized so that chunks x
-//     query blocks fill the chip); grid y: blocks of kBlock*Q queries;
-//   * a workgroup stages its chunk in LDS, 256 hills at a time (SoA, one
-//     hill per lane per stage), and every lane evaluates its Q queries
-//     against every staged hill (LDS broadcast reads, no bank conflicts);
-//   * the displacement, the periodic wrap, the quadratic form and every sum
-//     are FP64 (the same VALU rate as unpacked FP32 on CDNA4); only the
-//     exponential is FP32 (v_exp_f32): summing the products e * dxi in FP32
-//     loses digits where the terms of dV/dxi cancel;
+//   * grid x: hill chunks (multiples of 256 hills, sized so that chunks x
+//     query blocks fill the chip); grid y: blocks of 64 Q queries;
+//   * the four wavefronts of a workgroup hold the same 64 Q queries (Q per
+//     lane) and split every staged group of 256 hills in four, so a small
+//     query set (a step's walkers) still gives several wavefronts per
+//     SIMD; a fixed-order LDS reduction joins the four;
+//   * staging converts each hill once: centres to FP64, scaled by
+//     s_d = sqrt(log2(e) / (2 sigma_d^2)), so that a (hill, query) pair costs
+//     the scaled displacement and its periodic wrap (FP64), the quadratic
+//     form (FP64 FMAs), one v_exp_f32, and FP64 sums of e and e * dx: about
+//     17 VALU operations for two CVs.  Summing the products e * dxi in FP32
+//     would lose digits where the terms of dV/dxi cancel;
+//   * periodicity is a template parameter (all, none, or per CV);
 //   * each (chunk, query) partial has one writer; the finalize kernel sums a
 //     query's chunks in chunk order (bitwise deterministic), forms dV/dxi,
 //     and appends one hill per walker for a deposition step, in walker order.
 #include "sx_internal.h"
+#include "dev_gather.h"
 
 namespace sx {
 namespace {
 
-constexpr int kStage = kBlock;  // hills staged in LDS at a time
+constexpr int kStage = kBlock;  // hills staged in LDS at a time (one per lane)
+constexpr int kQueryLanes = 64;  // queries of a block per Q
 
-template <int D, int Q>
+enum { kPerNone = 0, kPerAll = 1, kPerMixed = 2 };
+
+template <int D, int Q, int PER>
 __global__ void __launch_bounds__(kBlock) k_hill_shared(SharedArgs a)
 {
-    __shared__ float s_c[D][kStage];
+    __shared__ double s_c[D][kStage];
     __shared__ float s_h[kStage];
+    __shared__ double s_red[3][Q * (1 + D)][kQueryLanes];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the step counter moves here (the finalize, which may deposit, reads it)
+    if (a.count_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
     const int32_t n = *a.count;
-    const int64_t h0 = (int64_t)blockIdx.x * a.chunk;
-    const int64_t q0 = ((int64_t)blockIdx.y * kBlock + threadIdx.x) * Q;
-    // with a query list only its first *qcount entries are live; a
-    // workgroup past them leaves before its first barrier (uniform test)
-    const int64_t nq = a.qlist ? (int64_t)*a.qcount : a.nq;
-    if ((int64_t)blockIdx.y * kBlock * Q >= nq) return;
-    double xi[Q][D];
+    const int64_t qb0 = (int64_t)blockIdx.y * kQueryLanes * Q;
+    const int64_t nq = a.nq;
+    double sc[D], per[D], iper[D];
+    bool wrap[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        sc[d] = sqrt(0.7213475204444817 * a.inv_sig2[d]);  // log2(e) / 2 = 0.72134...
+        wrap[d] = PER == kPerAll || (PER == kPerMixed && a.period[d] > 0.0);
+        per[d] = a.period[d] * sc[d];
+        iper[d] = a.inv_period[d] / sc[d];
+    }
+    double xs[Q][D];
     bool live[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        live[q] = q0 + q < nq;
-        const int64_t row = !live[q] ? 0 : (a.qlist ? (int64_t)a.qlist[q0 + q] : q0 + q);
+    for (int i = 0; i < Q; ++i) {
+        const int64_t q = qb0 + lane + (int64_t)kQueryLanes * i;
+        live[i] = q < nq;
 #pragma unroll
-        for (int d = 0; d < D; ++d) xi[q][d] = live[q] ? a.xi[row * D + d] : 0.0;
+        for (int d = 0; d < D; ++d) xs[i][d] = live[i] ? a.xi[q * D + d] * sc[d] : 0.0;
     }
     double acc[Q][1 + D];
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+    for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int j = 0; j <= D; ++j) acc[q][j] = 0.0;
+        for (int j = 0; j <= D; ++j) acc[i][j] = 0.0;
+    const int64_t h0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t hend = min((int64_t)n, h0 + a.chunk);
-    // exponent scale log2(e) / (2 sigma^2) in FP64: the quadratic form and the
-    // sums are FP64 (full VALU rate here); only the exponential is FP32
-    double a2[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) a2[d] = 0.7213475204444817 * a.inv_sig2[d];
     for (int64_t s0 = h0; s0 < hend; s0 += kStage) {
         const int64_t k = s0 + threadIdx.x;
         const bool ok = k < hend;
 #pragma unroll
-        for (int d = 0; d < D; ++d) s_c[d][threadIdx.x] = ok ? a.c[d][k] : 0.f;
+        for (int d = 0; d < D; ++d) s_c[d][threadIdx.x] = ok ? (double)a.c[d][k] * sc[d] : 0.0;
         s_h[threadIdx.x] = ok ? a.h[k] : 0.f;  // zero height: no contribution
         __syncthreads();
+        // this wavefront's quarter of the staged hills
         const int m = (int)min((int64_t)kStage, hend - s0);
-        for (int j0 = 0; j0 < m; j0 += 4) {
+        const int j0 = wave * 64, j1 = min(j0 + 64, m);
+        for (int jb = j0; jb < j1; jb += 4) {
 #pragma unroll
-            for (int j = j0; j < j0 + 4; ++j) {
+            for (int j = jb; j < jb + 4; ++j) {  // j < j0 + 64 <= kStage; past m: zero height
                 double c[D];
 #pragma unroll
-                for (int d = 0; d < D; ++d) c[d] = (double)s_c[d][j];
-                const float h = s_h[j];  // j >= m: staged as zero height
+                for (int d = 0; d < D; ++d) c[d] = s_c[d][j];
+                const float h = s_h[j];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
+                for (int i = 0; i < Q; ++i) {
                     double x[D], qd = 0.0;
 #pragma unroll
                     for (int d = 0; d < D; ++d) {
-                        x[d] = xi[q][d] - c[d];
-                        if (a.period[d] > 0.0) x[d] = fma(-a.period[d], rint(x[d] * a.inv_period[d]), x[d]);
-                        qd = fma(x[d] * a2[d], x[d], qd);
+                        x[d] = xs[i][d] - c[d];
+                        if (wrap[d]) x[d] = fma(-per[d], rint(x[d] * iper[d]), x[d]);
+                        qd = fma(x[d], x[d], qd);
                     }
                     const double e = (double)(h * __builtin_amdgcn_exp2f(-(float)qd));
-                    acc[q][0] += e;
+                    acc[i][0] += e;
 #pragma unroll
-                    for (int d = 0; d < D; ++d) acc[q][1 + d] = fma(e, x[d], acc[q][1 + d]);
+                    for (int d = 0; d < D; ++d) acc[i][1 + d] = fma(e, x[d], acc[i][1 + d]);
                 }
             }
         }
         __syncthreads();
     }
+    // join the four wavefronts in a fixed order (0 + 1 + 2 + 3)
+    if (wave > 0) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if (!live[q]) continue;
-        double *p = a.partial + ((int64_t)blockIdx.x * a.nq + q0 + q) * 4;
+        for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int j = 0; j <= D; ++j) p[j] = acc[q][j];
+            for (int j = 0; j <= D; ++j) s_red[wave - 1][i * (1 + D) + j][lane] = acc[i][j];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int j = 0; j <= D; ++j) acc[i][j] += s_red[w][i * (1 + D) + j][lane];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (!live[i]) continue;
+        const int64_t q = qb0 + lane + (int64_t)kQueryLanes * i;
+        double *p = a.partial + ((int64_t)blockIdx.x * a.nq + q) * 4;
+        p[0] = acc[i][0];
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[1 + d] = acc[i][1 + d] / sc[d];  // back to CV units
     }
 }
 
@@ -118,9 +151,10 @@ __device__ __forceinline__ void block_sum0(double (&v)[N], double *lds)
 }
 
 // per query: V, dV/dxi, outputs and (all or none) the appended hill;
-// w is the query's row (its walker, or its entry of the query list)
+// w is the query's row (its walker, or its evaluation point)
 template <int D>
-__device__ __forceinline__ void shared_finish(const SharedArgs &a, int64_t w, const double (&acc)[1 + D])
+__device__ __forceinline__ void shared_finish(const SharedArgs &a, int64_t w, const double (&acc)[1 + D],
+                                              double (&dv)[D])
 {
     const double V = acc[0];
     bool finite = isfinite(V);
@@ -128,10 +162,10 @@ __device__ __forceinline__ void shared_finish(const SharedArgs &a, int64_t w, co
     if (a.V_out) a.V_out[w] = V;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const double dv = -acc[1 + d] * a.inv_sig2[d];
-        finite = finite && isfinite(dv);
-        if (a.dV_ws) a.dV_ws[w * D + d] = dv;
-        if (a.dV_out) a.dV_out[w * D + d] = dv;
+        dv[d] = -acc[1 + d] * a.inv_sig2[d];
+        finite = finite && isfinite(dv[d]);
+        if (a.dV_ws) a.dV_ws[w * D + d] = dv[d];
+        if (a.dV_out) a.dV_out[w * D + d] = dv[d];
         if (a.xi_out) a.xi_out[w * D + d] = a.xi[w * D + d];
     }
     if (!finite && a.flags) atomicOr(a.flags, kFlagNonFinite);
@@ -152,12 +186,12 @@ __device__ __forceinline__ void shared_finish(const SharedArgs &a, int64_t w, co
     }
 }
 
-// few chunks: one lane per query sums its chunks in order
+// few chunks: one lane per query sums its chunks in order (no fallback mode)
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_hill_shared_finalize(SharedArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (a.qlist ? (int64_t)*a.qcount : a.nq)) return;
+    if (q >= a.nq) return;
     double acc[1 + D];
 #pragma unroll
     for (int j = 0; j <= D; ++j) acc[j] = 0.0;
@@ -166,17 +200,27 @@ __global__ void __launch_bounds__(kBlock) k_hill_shared_finalize(SharedArgs a)
 #pragma unroll
         for (int j = 0; j <= D; ++j) acc[j] += p[j];
     }
-    shared_finish<D>(a, a.qlist ? (int64_t)a.qlist[q] : q, acc);
+    double dv[D];
+    shared_finish<D>(a, q, acc, dv);
+    if (a.do_forces) {  // coefficients -dV/dxi; this lane owns the walker's atoms
+        double coef[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) coef[d] = -dv[d];
+        const float *Jw = a.J + q * a.nslots * 3;
+        for (int u = 0; u < a.tabs.U; ++u) gather_atom(a.tabs, Jw, (int32_t)q, coef, a.F, u);
+    }
 }
 
-// many chunks: one workgroup per query, lanes stride over the chunks and a
-// fixed reduction tree combines them (deterministic)
+// many chunks, or fallback sums: one workgroup per query (walker), lanes
+// stride over the chunks and a fixed reduction tree combines them
+// (deterministic); then the walker's force gather
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_hill_shared_finalize_wg(SharedArgs a)
 {
     __shared__ double lds[(1 + D) * (kBlock / 64)];
-    const int64_t q = blockIdx.x;
-    if (q >= (a.qlist ? (int64_t)*a.qcount : a.nq)) return;  // uniform per workgroup
+    __shared__ double s_coef[D];
+    const int64_t w = blockIdx.x, q = w;  // fallback mode: records per walker
+    if (a.fb && !a.fb[w]) return;           // uniform per workgroup
     double acc[1 + D];
 #pragma unroll
     for (int j = 0; j <= D; ++j) acc[j] = 0.0;
@@ -186,7 +230,93 @@ __global__ void __launch_bounds__(kBlock) k_hill_shared_finalize_wg(SharedArgs a
         for (int j = 0; j <= D; ++j) acc[j] += p[j];
     }
     block_sum0<1 + D>(acc, lds);
-    if (threadIdx.x == 0) shared_finish<D>(a, a.qlist ? (int64_t)a.qlist[q] : q, acc);
+    if (threadIdx.x == 0) {
+        double dv[D];
+        shared_finish<D>(a, w, acc, dv);
+#pragma unroll
+        for (int d = 0; d < D; ++d) s_coef[d] = -dv[d];
+    }
+    if (!a.do_forces) return;  // uniform
+    __syncthreads();
+    gather_forces(a.tabs, a.J + w * a.nslots * 3, (int32_t)w, s_coef, a.F);
+}
+
+// Fallback sums of a surrogate step (the few walkers outside certified
+// cells): one workgroup per (flagged walker, chunk of kQmChunk hills), lanes
+// over hills with float4 loads all issued before use (the list is read from
+// L2 once per fallback walker), a fixed-order reduction, one partial record
+// per (chunk, walker); the finalize kernel then sums a walker's chunks in
+// order.  Workgroups of walkers the network serves leave at once.
+constexpr int kQmChunk = 4096;               // hills per workgroup
+constexpr int kQmGroups = kQmChunk / (4 * kBlock);  // float4 groups per lane
+
+template <int D, int PER>
+__global__ void __launch_bounds__(kBlock) k_hill_shared_qm(SharedArgs a)
+{
+    __shared__ double lds[(1 + D) * (kBlock / 64)];
+    const int64_t w = blockIdx.y;
+    if (a.count_step && blockIdx.x == 0 && w == 0 && threadIdx.x == 0)
+        *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
+    if (!a.fb[w]) return;  // uniform per workgroup
+    const int32_t n = *a.count;
+    const int64_t h0 = (int64_t)blockIdx.x * kQmChunk;
+    if (h0 >= n) return;  // uniform
+    double sc[D], per[D], iper[D], xs[D];
+    bool wrap[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        sc[d] = sqrt(0.7213475204444817 * a.inv_sig2[d]);
+        wrap[d] = PER == kPerAll || (PER == kPerMixed && a.period[d] > 0.0);
+        per[d] = a.period[d] * sc[d];
+        iper[d] = a.inv_period[d] / sc[d];
+        xs[d] = a.xi[w * D + d] * sc[d];
+    }
+    // groups of 4 hills; the list's storage is padded to a multiple of 4
+    // floats and 16-byte aligned: a group past the count reads group 0 and
+    // gets zero heights
+    float4 cv[kQmGroups][D], hv[kQmGroups];
+    int64_t kk[kQmGroups];
+#pragma unroll
+    for (int it = 0; it < kQmGroups; ++it) {
+        const int64_t k = h0 + 4 * ((int64_t)it * kBlock + threadIdx.x);
+        kk[it] = k;
+        const int64_t ks = k < n ? k : 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) cv[it][d] = *reinterpret_cast<const float4 *>(a.c[d] + ks);
+        hv[it] = *reinterpret_cast<const float4 *>(a.h + ks);
+    }
+    double acc[1 + D];
+#pragma unroll
+    for (int j = 0; j <= D; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int it = 0; it < kQmGroups; ++it) {
+        const int64_t k = kk[it];
+        const float hh[4] = {k < n ? hv[it].x : 0.f, k + 1 < n ? hv[it].y : 0.f, k + 2 < n ? hv[it].z : 0.f,
+                             k + 3 < n ? hv[it].w : 0.f};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double x[D], qd = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const float4 &c4 = cv[it][d];
+                const float c = j == 0 ? c4.x : (j == 1 ? c4.y : (j == 2 ? c4.z : c4.w));
+                x[d] = xs[d] - (double)c * sc[d];
+                if (wrap[d]) x[d] = fma(-per[d], rint(x[d] * iper[d]), x[d]);
+                qd = fma(x[d], x[d], qd);
+            }
+            const double e = (double)(hh[j] * __builtin_amdgcn_exp2f(-(float)qd));
+            acc[0] += e;
+#pragma unroll
+            for (int d = 0; d < D; ++d) acc[1 + d] = fma(e, x[d], acc[1 + d]);
+        }
+    }
+    block_sum0<1 + D>(acc, lds);
+    if (threadIdx.x == 0) {
+        double *p = a.partial + ((int64_t)blockIdx.x * a.nq + w) * 4;
+        p[0] = acc[0];
+#pragma unroll
+        for (int d = 0; d < D; ++d) p[1 + d] = acc[1 + d] / sc[d];  // back to CV units
+    }
 }
 
 // the count of a shared list advances after the finalize kernel (kernel
@@ -199,26 +329,47 @@ __global__ void k_shared_count(SharedArgs a)
     if (dep && (int64_t)*a.count + a.nq <= a.cap) *a.count = (int32_t)(*a.count + a.nq);
 }
 
-__global__ void k_set_step(int64_t *dstep, int64_t step)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *dstep = step >= 0 ? step + 1 : *dstep + 1;
-}
-
 template <int D>
 hipError_t launch_shared_d(const SharedArgs &a, hipStream_t s)
 {
-    if (a.count_step) {
-        hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, a.dstep, a.step);
+    if (a.fb) {  // fallback walkers of a surrogate step: query-major sums, finalize per walker
+        SharedArgs b = a;
+        b.chunk = kQmChunk;
+        b.nchunk = (int32_t)std::max<int64_t>(1, (a.cap + kQmChunk - 1) / kQmChunk);
+        bool any = false, all = true;
+        for (int d = 0; d < D; ++d) {
+            any = any || a.period[d] > 0.0;
+            all = all && a.period[d] > 0.0;
+        }
+        const dim3 g(b.nchunk, (unsigned)a.nq);
+        if (all) hipLaunchKernelGGL((k_hill_shared_qm<D, kPerAll>), g, dim3(kBlock), 0, s, b);
+        else if (!any) hipLaunchKernelGGL((k_hill_shared_qm<D, kPerNone>), g, dim3(kBlock), 0, s, b);
+        else hipLaunchKernelGGL((k_hill_shared_qm<D, kPerMixed>), g, dim3(kBlock), 0, s, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_hill_shared_finalize_wg<D>), dim3((unsigned)a.nq), dim3(kBlock), 0, s, b);
+        return hipGetLastError();
     }
     // queries per lane: 1 for small query sets (more workgroups), 4 for many
     const int Q = a.nq >= 65536 ? 4 : 1;
-    dim3 grid(a.nchunk, (unsigned)((a.nq + kBlock * Q - 1) / (kBlock * Q)));
-    if (Q == 4)
-        hipLaunchKernelGGL((k_hill_shared<D, 4>), grid, dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_hill_shared<D, 1>), grid, dim3(kBlock), 0, s, a);
+    dim3 grid(a.nchunk, (unsigned)((a.nq + kQueryLanes * Q - 1) / (kQueryLanes * Q)));
+    bool any = false, all = true;
+    for (int d = 0; d < D; ++d) {
+        any = any || a.period[d] > 0.0;
+        all = all && a.period[d] > 0.0;
+    }
+    const int per = all ? kPerAll : (any ? kPerMixed : kPerNone);
+#define SX_SHARED_LAUNCH(QQ, PP) hipLaunchKernelGGL((k_hill_shared<D, QQ, PP>), grid, dim3(kBlock), 0, s, a)
+    if (Q == 4) {
+        if (per == kPerAll) SX_SHARED_LAUNCH(4, kPerAll);
+        else if (per == kPerNone) SX_SHARED_LAUNCH(4, kPerNone);
+        else SX_SHARED_LAUNCH(4, kPerMixed);
+    } else {
+        if (per == kPerAll) SX_SHARED_LAUNCH(1, kPerAll);
+        else if (per == kPerNone) SX_SHARED_LAUNCH(1, kPerNone);
+        else SX_SHARED_LAUNCH(1, kPerMixed);
+    }
+#undef SX_SHARED_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (a.nchunk >= 32)
@@ -228,7 +379,7 @@ hipError_t launch_shared_d(const SharedArgs &a, hipStream_t s)
                            0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (a.deposit) {
+    if (a.deposit == 2 || (a.deposit == 1 && a.stride > 0)) {
         hipLaunchKernelGGL(k_shared_count, dim3(1), dim3(64), 0, s, a);
         e = hipGetLastError();
     }
@@ -237,12 +388,13 @@ hipError_t launch_shared_d(const SharedArgs &a, hipStream_t s)
 
 }  // namespace
 
-void shared_split(int64_t cap, int64_t nq, int32_t &chunk, int32_t &nchunk)
+void shared_split(int64_t cap, int64_t nq, int32_t &chunk, int32_t &nchunk, int32_t target)
 {
     const int Q = nq >= 65536 ? 4 : 1;
-    const int64_t nqb = std::max<int64_t>(1, (nq + (int64_t)kBlock * Q - 1) / ((int64_t)kBlock * Q));
+    const int64_t nqb = std::max<int64_t>(1, (nq + (int64_t)kQueryLanes * Q - 1) / ((int64_t)kQueryLanes * Q));
     const int64_t stages = std::max<int64_t>(1, (cap + kStage - 1) / kStage);
-    int64_t nc = std::min<int64_t>(stages, std::max<int64_t>(1, (2048 + nqb - 1) / nqb));
+    // about `target` workgroups (chunks x query blocks), at least one stage each
+    int64_t nc = std::min<int64_t>(stages, std::max<int64_t>(1, (target + nqb - 1) / nqb));
     const int64_t per = (stages + nc - 1) / nc;  // stages per chunk
     chunk = (int32_t)(per * kStage);
     nchunk = (int32_t)((cap + chunk - 1) / chunk);

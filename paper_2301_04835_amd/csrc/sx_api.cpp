@@ -71,7 +71,7 @@ struct Plan {
     int64_t sgN = 0, sgCells = 0, sgCorners = 0;
     Sub s_sgP32, s_sgPb, s_sgM, s_sgV, s_sgMask;
     Sub w_sgX, w_sgVt, w_sgGt, w_sgVn, w_sgGn, w_sgA2, w_sgDz2, w_sgY, w_sgDy, w_sgGpart, w_sgGsum, w_sgLoss;
-    Sub w_sgFlag, w_sgList, w_sgCnt;
+    Sub w_sgFlag, w_sgRed;
     // workspace sub-buffers
     Sub w_xi, w_V, w_dV, w_J, w_part, w_cnpart;
     Sub w_atom_off, w_tiles, w_wrec;
@@ -322,10 +322,8 @@ sx_status make_plan(sx_ctx *c)
     if (c->method == M_METAD) {
         shared_split(maxcap, kEvalBatch, ch, nch);
         p.shared_records = (int64_t)nch * kEvalBatch;
-        if (c->shared) {
-            shared_split(maxcap, p.W, ch, nch);
-            p.shared_records = std::max<int64_t>(p.shared_records, (int64_t)nch * p.W);
-        }
+        if (c->shared)  // the step's sum at any tuning: at most one chunk per 256-hill stage
+            p.shared_records = std::max<int64_t>(p.shared_records, (maxcap + 255) / 256 * (int64_t)p.W);
     }
     // ABF grid
     p.nbins_total = 0;
@@ -390,8 +388,7 @@ sx_status make_plan(sx_ctx *c)
         p.w_sgGsum = lw.take(sizeof(double) * (p.sgP + 1));
         p.w_sgLoss = lw.take(sizeof(double));
         p.w_sgFlag = lw.take((size_t)p.W);
-        p.w_sgList = lw.take(sizeof(int32_t) * p.W);
-        p.w_sgCnt = lw.take(sizeof(int32_t));
+        p.w_sgRed = lw.take(sizeof(double) * kMlpRedSlices * (p.sgP + 1));
     }
     p.ws_bytes = lw.cur;
     p.valid = true;
@@ -504,7 +501,7 @@ HillArgs hill_args(sx_ctx *c, const double *xi)
 
 // Shared-list sum arguments over list `wl` (the shared list, or walker wl's
 // private list) at nq query points xi.
-SharedArgs shared_args(sx_ctx *c, int wl, const double *xi, int64_t nq)
+SharedArgs shared_args(sx_ctx *c, int wl, const double *xi, int64_t nq, int32_t target = kSharedTarget)
 {
     const Plan &p = c->plan;
     SharedArgs a{};
@@ -525,13 +522,24 @@ SharedArgs shared_args(sx_ctx *c, int wl, const double *xi, int64_t nq)
     a.xi = xi;
     a.nq = nq;
     a.partial = at<double>(c->ws, p.w_part);
-    shared_split(a.cap, nq, a.chunk, a.nchunk);
+    shared_split(a.cap, nq, a.chunk, a.nchunk, target);
     a.stride = c->stride;
     a.height = c->height;
     a.inv_kdT = c->kdT > 0 && std::isfinite(c->kdT) ? 1.0 / c->kdT : 0.0;
     a.dstep = at<int64_t>(c->state, p.s_hdr);
     a.flags = reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8);
     return a;
+}
+
+// the shared-list finalize gathers the forces of the walkers it serves
+void set_forces(sx_ctx *c, SharedArgs &a, const float *J, float *forces, int32_t layout)
+{
+    const Plan &p = c->plan;
+    a.do_forces = forces != nullptr;
+    a.nslots = p.nslots;
+    a.J = J;
+    a.tabs = tabs_of(c);
+    a.F = force_view(c, forces, layout);
 }
 
 MlpArgs mlp_args(sx_ctx *c)
@@ -560,33 +568,52 @@ MlpArgs mlp_args(sx_ctx *c)
     return a;
 }
 
-// the surrogate's step: network for every walker, exact sum of the shared
-// list for the walkers outside the certified cells, forces from both
-sx_status enqueue_surrogate_step(sx_ctx *c, int64_t step, double *xi, float *J, double *xi_out, double *V_out,
-                                 double *dVdxi_out, float *forces, int32_t layout)
+sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J);
+
+// the surrogate's step: network for every walker (outputs, certification
+// flags, forces of the walkers it serves), then the exact sum of the shared
+// list for the flagged walkers only (it overwrites their outputs and gathers
+// their forces)
+sx_status enqueue_surrogate_step(sx_ctx *c, const PosView &pv, int64_t step, double *xi, float *J, double *xi_out,
+                                 double *V_out, double *dVdxi_out, float *forces, int32_t layout)
 {
     const Plan &p = c->plan;
     double *V = at<double>(c->ws, p.w_V), *dV = at<double>(c->ws, p.w_dV);
     uint8_t *flag = at<uint8_t>(c->ws, p.w_sgFlag);
-    int32_t *list = at<int32_t>(c->ws, p.w_sgList), *cnt = at<int32_t>(c->ws, p.w_sgCnt);
-    hipError_t e = launch_mlp_fwd(mlp_args(c), xi, p.W, V, dV, nullptr, nullptr, nullptr, nullptr, flag, c->stream);
-    if (e == hipSuccess) e = launch_compact(flag, p.W, list, cnt, c->stream);
+    uint32_t *flags = reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8);
+    MlpStep st{};
+    st.xi_out = xi_out;
+    st.V_out = V_out;
+    st.dV_out = dVdxi_out;
+    st.flags = flags;
+    st.do_forces = forces != nullptr;
+    st.nslots = p.nslots;
+    st.J = J;
+    st.tabs = tabs_of(c);
+    st.F = force_view(c, forces, layout);
+    if (p.all_dihedral) {  // the network kernel evaluates the CVs itself
+        st.fuse_cv = 1;
+        st.cs = p.cs;
+        st.pos = pv;
+        st.xi_ws = xi;
+    } else if (sx_status s2 = launch_cvs(c, pv, xi, J)) {
+        return s2;
+    }
+    hipError_t e = launch_mlp_fwd(mlp_args(c), xi, p.W, V, dV, nullptr, nullptr, nullptr, nullptr, flag, c->stream, &st);
     if (e == hipSuccess) {
-        SharedArgs a = shared_args(c, 0, xi, p.W);
-        a.qlist = list;
-        a.qcount = cnt;
+        SharedArgs a = shared_args(c, 0, xi, p.W, c->grid > 0 ? c->grid : kSharedTarget);
+        a.fb = flag;
         a.V_ws = V;
         a.dV_ws = dV;
+        a.xi_out = xi_out;
+        a.V_out = V_out;
+        a.dV_out = dVdxi_out;
         a.deposit = 0;  // a surrogate stands in for a frozen bias
         a.count_step = 1;
         a.step = step;
+        set_forces(c, a, J, forces, layout);
         e = launch_hill_shared(a, c->stream);
     }
-    if (e == hipSuccess)
-        e = launch_outputs(p.W, p.D, xi, V, dV, xi_out, V_out, dVdxi_out,
-                           reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8), c->stream);
-    if (e == hipSuccess && forces)
-        e = launch_gather(tabs_of(c), J, p.nslots, p.D, dV, -1.0, force_view(c, forces, layout), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "surrogate step kernels");
     return SX_OK;
 }
@@ -610,15 +637,14 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
     float *J = at<float>(c->ws, p.w_J);
     if (c->method == M_NONE) return fail(c, SX_ESTATE, "no method configured (sx_metad_config / sx_abf_config)");
     const bool fuse = c->method == M_METAD && p.all_dihedral && !c->shared && !c->sg_on;
+    if (c->sg_on) return enqueue_surrogate_step(c, pv, step, xi, J, xi_out, V_out, dVdxi_out, forces, layout);
     if (!fuse) {
         sx_status st = launch_cvs(c, pv, xi, J);
         if (st != SX_OK) return st;
     }
     if (c->method == M_METAD && !c->sg_on && c->stride > 0) c->sg_certified = false;  // may deposit
-    if (c->sg_on) {
-        return enqueue_surrogate_step(c, step, xi, J, xi_out, V_out, dVdxi_out, forces, layout);
-    } else if (c->method == M_METAD && c->shared) {
-        SharedArgs a = shared_args(c, 0, xi, p.W);
+    if (c->method == M_METAD && c->shared) {
+        SharedArgs a = shared_args(c, 0, xi, p.W, c->grid > 0 ? c->grid : kSharedTarget);
         a.V_ws = at<double>(c->ws, p.w_V);
         a.dV_ws = at<double>(c->ws, p.w_dV);
         a.xi_out = xi_out;
@@ -627,9 +653,8 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.deposit = 1;
         a.count_step = 1;
         a.step = step;
+        set_forces(c, a, J, forces, layout);
         hipError_t e = launch_hill_shared(a, c->stream);
-        if (e == hipSuccess && forces)
-            e = launch_gather(tabs_of(c), J, p.nslots, p.D, a.dV_ws, -1.0, force_view(c, forces, layout), c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "shared hill-sum kernels");
     } else if (c->method == M_METAD) {
         HillArgs a = hill_args(c, xi);
@@ -1258,10 +1283,11 @@ sx_status sx_surrogate_loss_grad(sx_ctx *ctx, const double *xi, const double *V,
     const MlpArgs a = mlp_args(ctx);
     float *gpart = at<float>(ctx->ws, p.w_sgGpart);
     double *gsum = at<double>(ctx->ws, p.w_sgGsum);
+    double *red = at<double>(ctx->ws, p.w_sgRed);
     hipError_t e = launch_mlp_train_step(a, xi, V, G, n, (float)alpha, (float)beta, 0.f, 1, at<float>(ctx->ws, p.w_sgA2),
                                          at<float>(ctx->ws, p.w_sgDz2), at<float>(ctx->ws, p.w_sgY),
-                                         at<float>(ctx->ws, p.w_sgDy), gpart, nullptr, ctx->stream);
-    if (e == hipSuccess) e = launch_mlp_grad_sum(a, gpart, n, gsum, ctx->stream);
+                                         at<float>(ctx->ws, p.w_sgDy), gpart, red, nullptr, ctx->stream);
+    if (e == hipSuccess) e = launch_mlp_grad_sum(a, gpart, n, red, gsum, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     std::vector<double> g(p.sgP + 1);
     if (e == hipSuccess) e = hipMemcpy(g.data(), gsum, sizeof(double) * (p.sgP + 1), hipMemcpyDeviceToHost);
@@ -1296,7 +1322,8 @@ sx_status sx_surrogate_fit(sx_ctx *ctx, const double *xi, const double *V, const
         e = launch_mlp_train_step(a, xi + i0 * p.D, V + i0, G + i0 * p.D, len, (float)alpha, (float)beta, (float)lr_k,
                                   ctx->sg_t, at<float>(ctx->ws, p.w_sgA2), at<float>(ctx->ws, p.w_sgDz2),
                                   at<float>(ctx->ws, p.w_sgY), at<float>(ctx->ws, p.w_sgDy),
-                                  at<float>(ctx->ws, p.w_sgGpart), k == steps - 1 ? loss : nullptr, ctx->stream);
+                                  at<float>(ctx->ws, p.w_sgGpart), at<double>(ctx->ws, p.w_sgRed),
+                                  k == steps - 1 ? loss : nullptr, ctx->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     double l = 0;
@@ -1434,9 +1461,14 @@ sx_status sx_surrogate_fallback_count(sx_ctx *ctx, int32_t *count)
 {
     if (sx_status s = require_surrogate(ctx)) return s;
     if (!count) return fail(ctx, SX_EINVAL, "NULL count");
+    std::vector<uint8_t> f((size_t)ctx->plan.W);
     hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (e == hipSuccess) e = hipMemcpy(count, at<int32_t>(ctx->ws, ctx->plan.w_sgCnt), 4, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(ctx, e, "fallback count read");
+    if (e == hipSuccess)
+        e = hipMemcpy(f.data(), at<uint8_t>(ctx->ws, ctx->plan.w_sgFlag), f.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fallback flags read");
+    int32_t n = 0;
+    for (uint8_t v : f) n += v ? 1 : 0;
+    *count = n;
     return SX_OK;
 }
 

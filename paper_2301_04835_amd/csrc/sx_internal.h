@@ -162,9 +162,11 @@ struct SharedArgs {
     double period[kMaxBiasDim], inv_period[kMaxBiasDim];
     float a2[kMaxBiasDim];
     double inv_sig2[kMaxBiasDim];
-    const double *xi;  // nq x D (with qlist: rows of the walkers in the list)
-    int64_t nq;        // queries (with qlist: the list's capacity)
-    const int32_t *qlist, *qcount;  // optional: query q is walker qlist[q], q < *qcount
+    const double *xi;  // nq x D
+    int64_t nq;        // queries (walkers, or evaluation points)
+    // fallback mode (fb != null): only walkers w with fb[w] = 1 are queries,
+    // in walker order; query q is the q-th of them
+    const uint8_t *fb;
     double *partial;   // nchunk x nq x 4
     int32_t chunk, nchunk;
     double *V_ws, *dV_ws, *xi_out, *V_out, *dV_out;  // may be null
@@ -173,6 +175,29 @@ struct SharedArgs {
     double height, inv_kdT;
     int64_t *dstep;
     uint32_t *flags;
+    // forces of the queried walkers (the finalize gathers them): do_forces
+    int32_t do_forces, nslots;
+    const float *J;
+    WalkerTabs tabs;
+    ForceView F;
+};
+
+// What a surrogate step adds to the network's forward pass: per-walker
+// outputs, finiteness flag, and the force gather of the walkers the network
+// serves (the others are overwritten and gathered by the exact fallback).
+struct MlpStep {
+    double *xi_out, *V_out, *dV_out;  // may be null
+    uint32_t *flags;
+    int32_t do_forces, nslots;
+    float *J;
+    WalkerTabs tabs;
+    ForceView F;
+    // every CV a dihedral: the kernel evaluates them from the positions
+    // (values into xi_ws, gradients into J) instead of reading xi
+    int32_t fuse_cv;
+    CvSet cs;
+    PosView pos;
+    double *xi_ws;
 };
 
 // Surrogate network (bf16 copies as raw 16-bit words in host code).
@@ -199,21 +224,28 @@ hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView
                                int which = 3);
 hipError_t launch_abf(const AbfArgs &a, hipStream_t s);
 // chunking of a shared-list sum over nq queries: chunk (hills) and count
-void shared_split(int64_t cap, int64_t nq, int32_t &chunk, int32_t &nchunk);
+// chunking of a shared-list sum: about `target` workgroups, chunks of whole
+// 256-hill stages (nchunk <= ceil(cap / 256))
+constexpr int32_t kSharedTarget = 2048;
+void shared_split(int64_t cap, int64_t nq, int32_t &chunk, int32_t &nchunk, int32_t target = kSharedTarget);
 hipError_t launch_hill_shared(const SharedArgs &a, hipStream_t s);
 int32_t mlp_param_count(int32_t H, int32_t D);
 int32_t mlp_bwd_blocks(int32_t H, int64_t n);
 hipError_t launch_mlp_fwd(const MlpArgs &a, const double *xi, int64_t n, double *V, double *dV, float *t_a2,
-                          float *t_dz2, float *t_y, float *t_dy, uint8_t *flag, hipStream_t s);
+                          float *t_dz2, float *t_y, float *t_dy, uint8_t *flag, hipStream_t s,
+                          const MlpStep *step = nullptr);
 // one optimisation step over n samples: forward, reverse, Adam (lr > 0) or
 // only the loss (lr <= 0, gradients left in gpart)
 hipError_t launch_mlp_train_step(const MlpArgs &a, const double *xi, const double *Vl, const double *Gl, int64_t n,
                                  float alpha, float beta, float lr, int64_t t, float *t_a2, float *t_dz2, float *t_y,
-                                 float *t_dy, float *gpart, double *loss_out, hipStream_t s);
+                                 float *t_dy, float *gpart, double *red, double *loss_out, hipStream_t s);
 hipError_t launch_mlp_round(const MlpArgs &a, hipStream_t s);
 // ordered FP64 sum of the per-workgroup gradients of the last reverse pass
-// over n samples into gsum[P] and the loss sum into gsum[P]
-hipError_t launch_mlp_grad_sum(const MlpArgs &a, const float *gpart, int64_t n, double *gsum, hipStream_t s);
+// over n samples into gsum[0..P) and the loss sum into gsum[P]; red:
+// kMlpRedSlices x (P + 1) doubles of scratch
+constexpr int kMlpRedSlices = 16;
+hipError_t launch_mlp_grad_sum(const MlpArgs &a, const float *gpart, int64_t n, double *red, double *gsum,
+                               hipStream_t s);
 // certification: one lane per cell of the cert_n^D grid; dVhat and dV
 // [M][D] hold the network's and the exact gradient at the M grid corners
 // (row-major, the first CV slowest; periodic CVs: cert_n corners per CV,
@@ -222,10 +254,6 @@ hipError_t launch_mlp_grad_sum(const MlpArgs &a, const float *gpart, int64_t n, 
 // stays within tol
 hipError_t launch_cert_mask(const MlpArgs &a, const double *dVhat, const double *dV, const double *h, double tol,
                             uint8_t *mask, hipStream_t s);
-// per-walker outputs after a surrogate step (xi, V, dV/dxi copies, finiteness)
-hipError_t launch_outputs(int32_t W, int32_t D, const double *xi, const double *V, const double *dV, double *xi_out,
-                          double *V_out, double *dV_out, uint32_t *flags, hipStream_t s);
-hipError_t launch_compact(const uint8_t *flag, int32_t n, int32_t *list, int32_t *count, hipStream_t s);
 hipError_t launch_gather(const WalkerTabs &t, const float *J, int32_t nslots, int32_t D, const double *coef,
                          double coef_sign, ForceView out, hipStream_t s);
 hipError_t launch_copy_xi(const double *src, double *dst, int64_t n, hipStream_t s);

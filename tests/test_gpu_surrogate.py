@@ -184,7 +184,7 @@ def c4(request):
     s.surrogate_params(P0)
     frac0 = s.surrogate_certify()
     X = synth_wt.torus_points(1 << 17, 8)
-    loss = s.surrogate_train(dev(X), batch=4096, steps=40000, lr=3e-3, lr_final=1e-5)
+    loss = s.surrogate_train(dev(X), batch=4096, steps=100000, lr=3e-3, lr_final=1e-5)
     frac = s.surrogate_certify()
     print(f"surrogate: loss {loss:.3e}, certified fraction untrained {frac0:.3f} -> trained {frac:.3f}")
     return dict(s=s, C=C.astype(np.float64), H=H.astype(np.float64), pos=pos, off=off, frac0=frac0, frac=frac)
@@ -192,7 +192,7 @@ def c4(request):
 
 def test_training_gains_certified_cells(c4):
     assert c4["frac0"] <= 0.01
-    assert c4["frac"] >= 0.15
+    assert c4["frac"] >= 0.6
 
 
 def test_certified_cells_hold_the_force_bound(c4):
