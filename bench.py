@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="after the run, copy this many MiB with the plain copy probe (counter calibration)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
+    ap.add_argument("--no-bust", action="store_true", help="skip the cache-busting replica of the hill kernel")
+    ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2301_04835_amd", "tuning_mi355x.json"),
+                    help="autotuner cache (JSON): an entry for this problem shape is reused, else searched and added")
     ap.add_argument("--sg-train-steps", type=int, default=100000, help="Adam steps of the surrogate fit")
     ap.add_argument("--sg-steps", type=int, default=2000, help="timed steps of each surrogate-workload path")
     return ap.parse_args()
@@ -62,12 +65,23 @@ def build_context(d, p):
     return s, pos, forces
 
 
-def measured_traffic(bytes_per_launch):
-    """HBM bytes per launch of the tile kernel from the committed counter
-    summary, or None if the kernel source changed since it was taken."""
+TRAFFIC_SOURCES = ("k_bias.hip", "dev_cv.h", "dev_gather.h")
+
+
+def kernel_sources_sha():
+    """sha256 (first 16 hex digits) of the tile kernel's sources."""
     import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2301_04835_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tile):
+    """HBM bytes per launch of the tile kernel at this tile size, from the
+    committed counter summary, or None if the kernel's sources changed since
+    the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hill_tiles_walkers256_traffic.txt")
-    src = os.path.join(ROOT, "paper_2301_04835_amd", "csrc", "k_bias.hip")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -75,10 +89,10 @@ def measured_traffic(bytes_per_launch):
         if "=" in line and not line.startswith("#"):
             k, v = line.strip().split("=", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if kv.get("k_bias_sha") != sha or "traffic_bytes_per_launch" not in kv:
+    key = "traffic_bytes_per_launch.tile%d" % tile
+    if kv.get("kernel_sources_sha") != kernel_sources_sha() or key not in kv:
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return float(kv[key])
 
 
 def cpu_baseline(d, p, target_s):
@@ -113,6 +127,36 @@ def cpu_baseline(d, p, target_s):
     return {"value": n / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": "%d full steps of the same 256-walker workload (%d hills per step), FP64, 1 thread, %.1f s"
                       % (n, int(hoff[-1]), el)}
+
+
+def bust_leg(d, p, tile, grid, reps):
+    """The hill-sum kernel on four copies of the workload at once (1,024
+    walkers, about 310 MB of hills: above the 256 MB Infinity Cache, so no
+    launch finds its hills in the cache of the previous one); the same tiling.
+    Returns the kernel's algorithmic read rate, i.e. an HBM-only figure."""
+    import torch
+    from paper_2301_04835_amd import Sampler
+
+    R, W = 4, p["n_walkers"]
+    na = int(d["atom_off"][-1])
+    atom_off = np.concatenate([d["atom_off"][:-1] + r * na for r in range(R)] + [[R * na]])
+    s = Sampler(0)
+    s.add_cvs(d["cvs"])
+    s.set_walkers(atom_off, np.tile(d["n_hills"] + 64, R))
+    s.metad(p["sigma"], p["w"], p["T"], p["bias_factor"], p["stride"], 1)
+    s.bind()
+    hoff = d["hill_off"]
+    for r in range(R):
+        for w in range(W):
+            s.hills_set(r * W + w, d["centers"][hoff[w]:hoff[w + 1]], d["heights"][hoff[w]:hoff[w + 1]])
+    s.set_tuning(tile, grid)
+    pos = torch.from_numpy(np.tile(d["pos"], (R, 1))).cuda()
+    forces = torch.zeros_like(pos)
+    ms_a, ms_b = s.time_hill(pos, forces=forces, reps=reps)
+    nbytes = int(np.sum(s.hill_counts())) * 12
+    return {"walkers": R * W, "hill_bytes": nbytes, "kernel_ms": ms_a, "finalize_kernel_ms": ms_b,
+            "achieved": nbytes / (ms_a * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": nbytes / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def timed_graph(s, pos, forces, outs, steps, warmup, gsteps=10):
@@ -230,7 +274,7 @@ def main():
     # first eager step (also provides xi for tuning), then tile autotune
     s.step(pos, forces=forces, xi_out=xi, V_out=V, dV_out=dV)
     torch.cuda.synchronize()
-    s.autotune(pos)
+    s.autotune(pos, cache_path=args.tuning_cache)
     tile, grid = s.get_tuning()
     gsteps = args.graph_steps if args.steps % args.graph_steps == 0 else 1
     s.graph_capture(gsteps, pos, forces=forces, xi_out=xi, V_out=V, dV_out=dV)
@@ -260,7 +304,7 @@ def main():
     ms_a, ms_b = s.time_hill(pos, forces=forces, reps=args.hill_reps)
     bytes_per_launch = counts_total * 12  # 2 float32 centres + 1 float32 height per hill
     achieved = bytes_per_launch / (ms_a * 1e-3) / 1e9
-    traffic = measured_traffic(bytes_per_launch)
+    traffic = measured_traffic(tile)
     out = {
         "metric": "biased steps/s (CV+bias+force), 256 walkers",
         "value": steps / wall,
@@ -281,7 +325,8 @@ def main():
         "hill_evals_per_s": counts_total * steps / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_hill_tiles<2,%d,fused>" % (tile // 1024), "kernel_ms": ms_a,
+                     "kernel": "k_hill_tiles%s<2,%d,fused,float>" % ("_persist" if grid else "", tile // 1024),
+                     "kernel_ms": ms_a,
                      "finalize_kernel_ms": ms_b, "bytes_per_launch": bytes_per_launch},
     }
     if args.probe_copy_mb:
@@ -293,6 +338,8 @@ def main():
             s.L.sx_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nb, 2048,
                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
+    if not args.no_bust:
+        out["roofline_above_infinity_cache"] = bust_leg(d, p, tile, grid, args.hill_reps)
     sg_data = None
     if not args.no_surrogate:
         out["surrogate"], sg_data = surrogate_leg(args)

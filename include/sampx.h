@@ -253,7 +253,8 @@ sx_status sx_graph_launch(sx_ctx *ctx);
  * tile).  Changing the tile rebuilds the tile table (host, synchronous).
  * With a shared hill list `grid` is instead the number of workgroups the
  * step's shared sum aims at (chunks x query blocks; 0: 2048) and the tile
- * is unused. */
+ * is unused.  A change releases a captured graph (sx_graph_launch then
+ * returns SX_ESTATE until the next sx_graph_capture); so does sx_autotune. */
 sx_status sx_set_tuning(sx_ctx *ctx, int32_t tile_hills, int32_t grid);
 sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
 /* Time candidate tilings of the step's hill-sum kernels on the bound state

@@ -1666,6 +1666,15 @@ sx_status sx_graph_launch(sx_ctx *ctx)
     return SX_OK;
 }
 
+// a captured graph holds the launch shapes it was captured with
+static void drop_graph(sx_ctx *ctx)
+{
+    if (ctx->gexec) {
+        hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
+}
+
 sx_status sx_set_tuning(sx_ctx *ctx, int32_t tile_hills, int32_t grid)
 {
     if (!ctx) return SX_EINVAL;
@@ -1673,11 +1682,11 @@ sx_status sx_set_tuning(sx_ctx *ctx, int32_t tile_hills, int32_t grid)
     const int u = tile_hills / kTileUnit;
     if (u != 1 && u != 2 && u != 4 && u != 8) return fail(ctx, SX_EINVAL, "tile must be 1024 * {1,2,4,8}");
     if (grid < 0) return fail(ctx, SX_EINVAL, "grid must be >= 0");
+    if (grid != ctx->grid || u != ctx->tile_units) drop_graph(ctx);
     ctx->grid = grid;
     if (u != ctx->tile_units) {
         ctx->tile_units = u;
         if (ctx->bound && ctx->method == M_METAD && !ctx->shared) {
-            if (ctx->gexec) return fail(ctx, SX_ESTATE, "release the captured graph before retiling");
             build_tiles(ctx);
             return upload_tiles(ctx);
         }
@@ -1698,7 +1707,7 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
     if (sx_status s = require_bound(ctx)) return s;
     SX_GUARD_BEGIN
     if (ctx->method != M_METAD || ctx->shared) return SX_OK;  // only the private hill sum has launch choices
-    if (ctx->gexec) return fail(ctx, SX_ESTATE, "release the captured graph before tuning");
+    drop_graph(ctx);
     const Plan &p = ctx->plan;
     PosView pv{};
     const bool fuse = p.all_dihedral && pos != nullptr;
