@@ -113,6 +113,21 @@ sx_status sx_add_cv_coordination(sx_ctx *ctx, const int32_t *a, int32_t na, cons
 /* Orthorhombic box edges L[3] (nm) for minimum images; 0 = open in that
  * direction.  Default: open.  Before sx_bind. */
 sx_status sx_set_box(sx_ctx *ctx, const double L[3]);
+/* Coordination numbers with a hard cut (rcut > 0) in a periodic box at
+ * least 3 rcut wide can be evaluated through cell lists (cells of edge >=
+ * the largest such cut, 3 to 16 per dimension): each step sorts the groups'
+ * members into cells (stable, so every sum has a fixed order), sums pairs
+ * over the 27 neighbour cells, and computes their forces by recomputing the
+ * pairs (a vector-Jacobian product; their Jacobian is never stored, so it is
+ * absent from sx_eval_cv's jac_out and sx_jac_slots).  mode: -1 never; 0
+ * (default) when |A| |B| >= 2^22; 1 whenever the box allows.  The groups of
+ * all such CVs must be identical or disjoint (mode 1: SX_EINVAL otherwise;
+ * mode 0 then keeps the all-pairs kernels); at most 8 distinct groups, each
+ * used by at most 8 (CV, side) pairs.  Not with ABF (which needs J itself).
+ * Before sx_bind. */
+sx_status sx_set_cell_lists(sx_ctx *ctx, int32_t mode);
+/* Number of CVs the bound plan evaluates through cell lists. */
+int32_t sx_cell_list_cvs(const sx_ctx *ctx);
 
 /* Number of CVs defined so far (D). */
 int32_t sx_num_cvs(const sx_ctx *ctx);

@@ -65,6 +65,8 @@ SIGNATURES = {
     "sx_time_hill": (i32, [P, P, i32, i32, P, i32, P, P]),
     "sx_probe_read": (i32, [P, sz, P, i32, P]),
     "sx_probe_copy": (i32, [P, P, sz, i32, P]),
+    "sx_set_cell_lists": (i32, [P, i32]),
+    "sx_cell_list_cvs": (i32, [P]),
     "sx_surrogate_config": (i32, [P, i32, i64, i32, i32, f64]),
     "sx_surrogate_norm": (i32, [P, P, P]),
     "sx_surrogate_param_count": (i64, [P]),

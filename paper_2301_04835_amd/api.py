@@ -108,6 +108,13 @@ class Sampler:
             else:
                 raise ValueError(c["kind"])
 
+    def set_cell_lists(self, mode):
+        """-1 never, 0 for large groups (default), 1 whenever the box allows."""
+        self._check(self.L.sx_set_cell_lists(self.h, int(mode)))
+
+    def cell_list_cvs(self):
+        return int(self.L.sx_cell_list_cvs(self.h))
+
     def set_box(self, L):
         a, p = _host(L, np.float64)
         self._check(self.L.sx_set_box(self.h, p))
@@ -150,7 +157,8 @@ class Sampler:
     def bind(self):
         sb = int(self.L.sx_state_bytes(self.h))
         wb = int(self.L.sx_workspace_bytes(self.h))
-        if sb == 0 or wb == 0:
+        if sb == 0 or wb == 0:  # the plan failed: sx_bind reports why
+            self._check(self.L.sx_bind(self.h, None, 0, None, 0))
             self._check(_lib.SX_ESTATE)
         # torch's caching allocator returns 512-byte aligned blocks
         self.state = torch.empty(sb, dtype=torch.uint8, device=self.device)

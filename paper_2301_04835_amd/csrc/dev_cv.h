@@ -73,4 +73,35 @@ __device__ __forceinline__ double dihedral_at(const CvDesc &cv, const PosView &p
     return pos.f64 ? dihedral_at_t<double, GRAD>(cv, pos, aoff, g) : dihedral_at_t<float, GRAD>(cv, pos, aoff, g);
 }
 
+// Rational switch s = (1 - x^n)/(1 - x^m), x = r/r0, and f = (1/r) ds/dr.
+// (6, 12): s = 1/(1 + x^6) and f = -6 x^4 s^2 / r0^2, both from r^2 alone.
+// Other (n, m): s = P_n(x)/P_m(x) with P_k(x) = 1 + x + ... + x^(k-1), the
+// same rational function with the factor (1 - x) cancelled, which stays
+// exact around x = 1 where the plain quotient loses all its digits.
+__device__ __forceinline__ void switch_fn(float r2, const CvDesc &c, float &s, float &f)
+{
+    if (c.n == 6 && c.m == 12) {
+        float x2 = r2 * (c.inv_r0 * c.inv_r0);
+        float x4 = x2 * x2;
+        float sv = __builtin_amdgcn_rcpf(1.0f + x4 * x2);
+        s = sv;
+        f = -6.0f * x4 * sv * sv * (c.inv_r0 * c.inv_r0);
+        return;
+    }
+    float r = sqrtf(r2), x = r * c.inv_r0;
+    float pn = 0.f, dpn = 0.f, pm = 0.f, dpm = 0.f;
+    for (int i = c.n - 1; i >= 0; --i) {  // Horner: P and P'
+        dpn = fmaf(dpn, x, pn);
+        pn = fmaf(pn, x, 1.0f);
+    }
+    for (int i = c.m - 1; i >= 0; --i) {
+        dpm = fmaf(dpm, x, pm);
+        pm = fmaf(pm, x, 1.0f);
+    }
+    float ipm = __builtin_amdgcn_rcpf(pm);
+    s = pn * ipm;
+    float dsdx = (dpn * pm - pn * dpm) * ipm * ipm;
+    f = r > 0.f ? dsdx * c.inv_r0 / r : 0.f;
+}
+
 }  // namespace sx

@@ -65,6 +65,10 @@ struct Plan {
     // state sub-buffers
     Sub s_hdr, s_count, s_c[kMaxBiasDim], s_h, s_N, s_Fsum;
     size_t state_bytes = 0;
+    // cell lists of coordination numbers
+    CellArgs cell{};
+    std::vector<int32_t> gatoms;
+    Sub w_gatoms, w_cid, w_cstart, w_sorted, w_cpart;
     // surrogate network (state: FP32 master weights, bf16 copies, Adam
     // moments, certified cells; workspace: samples, training tangents)
     int32_t sgP = 0;
@@ -114,6 +118,8 @@ struct sx_ctx {
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // coordination numbers through cell lists: -1 never, 0 large groups, 1 whenever the box allows
+    int32_t cell_mode = 0;
     // surrogate network of the bias of hill list 0
     int32_t sg_H = 0;  // 0: none
     int64_t sg_max_samples = 0;
@@ -226,12 +232,105 @@ sx_status make_plan(sx_ctx *c)
         cs.box[k] = c->box[k];
         cs.inv_box[k] = c->box[k] > 0 ? 1.0 / c->box[k] : 0.0;
     }
+    // coordination numbers evaluated through cell lists: a hard cut, a
+    // periodic box at least three cutoffs wide, groups identical or
+    // disjoint, and (by default) large enough groups
+    std::vector<int> cellcv(ncv, 0), gid_a(ncv, -1), gid_b(ncv, -1);
+    std::vector<std::vector<int32_t>> groups;
+    CellArgs &cl = p.cell;
+    cl = CellArgs{};
+    {
+        double rmax = 0;
+        bool box = c->box[0] > 0 && c->box[1] > 0 && c->box[2] > 0;
+        for (int d = 0; d < ncv; ++d) {
+            const CvDef &cv = c->cvs[d];
+            if (cv.kind != CV_COORD || !(cv.rcut > 0) || !box || c->cell_mode < 0 || c->method == M_ABF) continue;
+            if (c->cell_mode == 0 && (double)cv.a.size() * (double)cv.b.size() < 4194304.0) continue;
+            bool fits = true;
+            for (int k = 0; k < 3; ++k) fits = fits && c->box[k] >= 3.0 * cv.rcut;
+            if (!fits) continue;
+            cellcv[d] = 1;
+            rmax = std::max(rmax, cv.rcut);
+        }
+        auto group_of = [&](const std::vector<int32_t> &v) {
+            for (size_t g = 0; g < groups.size(); ++g)
+                if (groups[g] == v) return (int)g;
+            groups.push_back(v);
+            return (int)groups.size() - 1;
+        };
+        for (int d = 0; d < ncv; ++d)
+            if (cellcv[d]) {
+                gid_a[d] = group_of(c->cvs[d].a);
+                gid_b[d] = group_of(c->cvs[d].b);
+            }
+        bool ok = groups.size() <= (size_t)kMaxGroups;
+        std::map<int32_t, int> owner;
+        for (size_t g = 0; g < groups.size() && ok; ++g)
+            for (int32_t i : groups[g]) {
+                auto it = owner.find(i);
+                if (it != owner.end() && it->second != (int)g) ok = false;
+                owner[i] = (int)g;
+            }
+        std::vector<int> uses(groups.size(), 0);
+        for (int d = 0; d < ncv && ok; ++d)
+            if (cellcv[d]) ok = ++uses[gid_a[d]] <= kMaxInv && ++uses[gid_b[d]] <= kMaxInv;
+        if (!ok) {
+            if (c->cell_mode > 0)
+                return fail(c, SX_EINVAL, "cell-list coordination numbers need identical or disjoint groups "
+                                          "(at most 8 groups, 8 uses each)");
+            std::fill(cellcv.begin(), cellcv.end(), 0);
+            groups.clear();
+        }
+        if (!groups.empty()) {
+            cl.G = (int32_t)groups.size();
+            cl.ncell = 1;
+            for (int k = 0; k < 3; ++k) {
+                cl.nc[k] = std::min(kCellMax, (int)std::floor(c->box[k] / rmax));
+                cl.L[k] = c->box[k];
+                cl.inv_L[k] = 1.0 / c->box[k];
+                cl.clen[k] = c->box[k] / cl.nc[k];
+                cl.ncell *= cl.nc[k];
+            }
+            cl.goff[0] = 0;
+            for (int g = 0; g < cl.G; ++g) {
+                for (int32_t i : groups[g]) p.gatoms.push_back(i);
+                cl.goff[g + 1] = (int32_t)p.gatoms.size();
+            }
+            cl.gtotal = (int64_t)p.gatoms.size();
+            for (int d = 0; d < ncv; ++d) {
+                if (!cellcv[d]) continue;
+                const int ga = gid_a[d], gb = gid_b[d];
+                cl.inv_cv[ga][cl.ninv[ga]] = d;
+                cl.inv_p[ga][cl.ninv[ga]++] = gb;
+                cl.inv_cv[gb][cl.ninv[gb]] = d;
+                cl.inv_p[gb][cl.ninv[gb]++] = ga;
+            }
+        }
+    }
     int64_t part = 0;
     for (int d = 0; d < ncv; ++d) {
         const CvDef &cv = c->cvs[d];
         CvDesc &ds = cs.cv[d];
         ds = CvDesc{};
         ds.kind = cv.kind;
+        if (cellcv[d]) {  // no Jacobian slots: forces through the VJP kernel
+            ds.kind = CV_COORD_CELL;
+            ds.d = d;
+            ds.slot0 = (int32_t)p.slot_atom.size();
+            ds.na = (int32_t)cv.a.size();
+            ds.nb = (int32_t)cv.b.size();
+            ds.n = cv.n;
+            ds.m = cv.m;
+            ds.r0 = (float)cv.r0;
+            ds.inv_r0 = (float)(1.0 / cv.r0);
+            ds.rcut2 = (float)(cv.rcut * cv.rcut);
+            ds.rcut = cv.rcut;
+            ds.scale = cv.normalize ? (float)(1.0 / cv.a.size()) : 1.f;
+            ds.ga = gid_a[d];
+            ds.gb = gid_b[d];
+            ds.cn = cl.ncn++;
+            continue;
+        }
         ds.d = d;
         ds.slot0 = (int32_t)p.slot_atom.size();
         ds.na = (int32_t)cv.a.size();
@@ -373,6 +472,16 @@ sx_status make_plan(sx_ctx *c)
     p.w_touched = lw.take(sizeof(int32_t) * p.U);
     p.w_inv_ptr = lw.take(sizeof(int32_t) * (p.U + 1));
     p.w_inv_slot = lw.take(sizeof(int32_t) * p.nslots);
+    if (p.cell.ncn) {
+        CellArgs &cl = p.cell;
+        cl.W = p.W;
+        const size_t W = (size_t)p.W, gt = (size_t)cl.gtotal;
+        p.w_gatoms = lw.take(sizeof(int32_t) * gt);
+        p.w_cid = lw.take(sizeof(int32_t) * W * gt);
+        p.w_cstart = lw.take(sizeof(int32_t) * W * cl.G * (cl.ncell + 1));
+        p.w_sorted = lw.take(16 * W * gt);
+        p.w_cpart = lw.take(sizeof(double) * W * cl.ncn * cl.ncell);
+    }
     if (c->sg_H) {
         const size_t N = (size_t)p.sgN, B = (size_t)c->sg_max_batch, H = (size_t)c->sg_H, D = (size_t)p.D;
         p.w_sgX = lw.take(sizeof(double) * N * D);
@@ -569,6 +678,7 @@ MlpArgs mlp_args(sx_ctx *c)
 }
 
 sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J);
+sx_status cell_forces(sx_ctx *c, const PosView &pv, const double *coef, double sign, float *out, int32_t layout);
 
 // the surrogate's step: network for every walker (outputs, certification
 // flags, forces of the walkers it serves), then the exact sum of the shared
@@ -615,14 +725,39 @@ sx_status enqueue_surrogate_step(sx_ctx *c, const PosView &pv, int64_t step, dou
         e = launch_hill_shared(a, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "surrogate step kernels");
-    return SX_OK;
+    return cell_forces(c, pv, dV, -1.0, forces, layout);
+}
+
+CellArgs cell_args(sx_ctx *c)
+{
+    const Plan &p = c->plan;
+    CellArgs a = p.cell;
+    a.atom_off = at<int64_t>(c->ws, p.w_atom_off);
+    a.gatoms = at<int32_t>(c->ws, p.w_gatoms);
+    a.cid = at<int32_t>(c->ws, p.w_cid);
+    a.cstart = at<int32_t>(c->ws, p.w_cstart);
+    a.sorted = at<float4>(c->ws, p.w_sorted);
+    a.part = at<double>(c->ws, p.w_cpart);
+    return a;
 }
 
 sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J)
 {
     const Plan &p = c->plan;
     hipError_t e = launch_cv(p.cs, tabs_of(c), pv, xi, J, at<double>(c->ws, p.w_cnpart), 0, c->stream);
+    if (e == hipSuccess && p.cell.ncn) e = launch_cell_cv(cell_args(c), p.cs, pv, xi, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "CV kernels");
+    return SX_OK;
+}
+
+// forces of the cell-list coordination numbers: out += sign coef . dxi/dr
+// (their cell lists are those of the step's positions)
+sx_status cell_forces(sx_ctx *c, const PosView &pv, const double *coef, double sign, float *out, int32_t layout)
+{
+    const Plan &p = c->plan;
+    if (!p.cell.ncn || !out) return SX_OK;
+    hipError_t e = launch_cell_vjp(cell_args(c), p.cs, pv, coef, sign, force_view(c, out, layout), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "cell-list VJP kernel");
     return SX_OK;
 }
 
@@ -656,6 +791,7 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         set_forces(c, a, J, forces, layout);
         hipError_t e = launch_hill_shared(a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "shared hill-sum kernels");
+        if (sx_status st = cell_forces(c, pv, a.dV_ws, -1.0, forces, layout)) return st;
     } else if (c->method == M_METAD) {
         HillArgs a = hill_args(c, xi);
         a.fuse = fuse;
@@ -670,6 +806,7 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.F = force_view(c, forces, layout);
         hipError_t e = launch_hill_private(a, p.cs, pv, c->grid, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "hill-sum kernels");
+        if (sx_status st = cell_forces(c, pv, a.dV_ws, -1.0, forces, layout)) return st;
     } else {
         if (!sys_forces) return fail(c, SX_EINVAL, "ABF needs the system forces");
         if (!forces) return fail(c, SX_EINVAL, "ABF needs the force buffer");
@@ -863,6 +1000,23 @@ sx_status sx_set_box(sx_ctx *ctx, const double L[3])
     return SX_OK;
 }
 
+sx_status sx_set_cell_lists(sx_ctx *ctx, int32_t mode)
+{
+    if (!ctx) return SX_EINVAL;
+    if (sx_status s = require_unbound(ctx)) return s;
+    if (mode < -1 || mode > 1) return fail(ctx, SX_EINVAL, "mode must be -1, 0 or 1");
+    ctx->cell_mode = mode;
+    invalidate(ctx);
+    return SX_OK;
+}
+
+int32_t sx_cell_list_cvs(const sx_ctx *cctx)
+{
+    sx_ctx *ctx = const_cast<sx_ctx *>(cctx);
+    if (!ctx || ensure_plan(ctx) != SX_OK) return 0;
+    return ctx->plan.cell.ncn;
+}
+
 int32_t sx_num_cvs(const sx_ctx *ctx) { return ctx ? (int32_t)ctx->cvs.size() : 0; }
 
 sx_status sx_set_walkers(sx_ctx *ctx, int32_t n_walkers, const int64_t *atom_off, const int64_t *hill_capacity,
@@ -1008,6 +1162,7 @@ sx_status sx_bind(sx_ctx *ctx, void *dev_state, size_t state_bytes, void *dev_ws
     if (e == hipSuccess) e = up(p.w_touched, p.touched.data(), sizeof(int32_t) * p.U);
     if (e == hipSuccess) e = up(p.w_inv_ptr, p.inv_ptr.data(), sizeof(int32_t) * (p.U + 1));
     if (e == hipSuccess) e = up(p.w_inv_slot, p.inv_slot.data(), sizeof(int32_t) * p.nslots);
+    if (e == hipSuccess && p.cell.ncn) e = up(p.w_gatoms, p.gatoms.data(), sizeof(int32_t) * p.gatoms.size());
     if (e != hipSuccess) return hip_fail(ctx, e, "table upload");
     ctx->bound = true;
     if (ctx->method != M_METAD || ctx->shared)
@@ -1088,7 +1243,7 @@ sx_status sx_cv_vjp(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout,
     hipError_t e = launch_gather(tabs_of(ctx), J, p.nslots, p.D, xi_bar, 1.0, force_view(ctx, pos_bar, layout),
                                  ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "VJP gather");
-    return SX_OK;
+    return cell_forces(ctx, pv, xi_bar, 1.0, pos_bar, layout);
     SX_GUARD_END
 }
 

@@ -14,7 +14,9 @@ constexpr int kHillsPerLoad = 4; // float4 per lane
 constexpr int kTileUnit = kBlock * kHillsPerLoad;  // 1024 hills: smallest tile
 constexpr int kMaxTileUnits = 8;                   // largest tile: 8192 hills
 
-enum CvKind : int32_t { CV_DIHEDRAL = 0, CV_GYRATION = 1, CV_COORD = 2 };
+// CV_COORD_CELL: a coordination number with a hard cut evaluated through
+// cell lists (no Jacobian slots; its forces come from the VJP kernel).
+enum CvKind : int32_t { CV_DIHEDRAL = 0, CV_GYRATION = 1, CV_COORD = 2, CV_COORD_CELL = 3 };
 
 // Device-side flags (bit = sx_status value).
 constexpr uint32_t kFlagCapacity = 1u << 3;
@@ -47,6 +49,9 @@ struct CvDesc {
     int32_t nchunk_a, nchunk_b;  // chunks over B (for side A) and over A (side B)
     int64_t part0;  // coordination: first partial record of this CV (per walker)
     int32_t atom[4];  // dihedral: its four atoms (walker-relative)
+    int32_t ga, gb;   // cell-list coordination: the two atom groups
+    int32_t cn;       // cell-list coordination: index among those CVs
+    double rcut;      // the cut (FP64), for decisions at its edge
 };
 
 struct CvSet {
@@ -200,6 +205,28 @@ struct MlpStep {
     double *xi_ws;
 };
 
+// Cell lists of coordination-number groups (orthorhombic periodic box,
+// cells of edge >= the cutoff, at least 3 per dimension, at most 16).
+constexpr int kCellMax = 16;
+constexpr int kMaxGroups = 8;  // distinct groups of the cell-list CVs
+constexpr int kMaxInv = 8;     // (CV, side) uses of one group
+struct CellArgs {
+    int32_t W, G, ncn;                 // walkers, distinct groups, cell-list CVs
+    int32_t nc[3], ncell;              // cells per dimension, total
+    double L[3], inv_L[3], clen[3];    // box edges, cell edges
+    const int64_t *atom_off;           // W + 1
+    const int32_t *gatoms;             // walker-relative atoms of all groups, group after group
+    int32_t goff[kMaxGroups + 1];      // group g: gatoms[goff[g] .. goff[g + 1])
+    int64_t gtotal;                    // goff[G]
+    int32_t *cid;                      // W x gtotal: cell of each group member
+    int32_t *cstart;                   // W x G x (ncell + 1): members of cell c
+    float4 *sorted;                    // W x gtotal: (x, y, z) relative to the cell origin, atom
+    double *part;                      // W x ncn x ncell: forward partial sums
+    // uses of each group: the CV (index into CvSet::cv) and its partner group
+    int32_t ninv[kMaxGroups];
+    int32_t inv_cv[kMaxGroups][kMaxInv], inv_p[kMaxGroups][kMaxInv];  // CV index in the set, partner group
+};
+
 // Surrogate network (bf16 copies as raw 16-bit words in host code).
 struct MlpArgs {
     int32_t D, H;
@@ -229,6 +256,13 @@ hipError_t launch_abf(const AbfArgs &a, hipStream_t s);
 constexpr int32_t kSharedTarget = 2048;
 void shared_split(int64_t cap, int64_t nq, int32_t &chunk, int32_t &nchunk, int32_t target = kSharedTarget);
 hipError_t launch_hill_shared(const SharedArgs &a, hipStream_t s);
+// cell lists, then every cell-list coordination number's value into xi
+hipError_t launch_cell_cv(const CellArgs &c, const CvSet &cs, const PosView &pos, double *xi, hipStream_t s);
+// out += sign * sum_d coef[w][d] dxi_d/dr for the cell-list coordination
+// numbers (pair recompute, one writer per atom); needs the cell lists of the
+// same positions (launch_cell_cv first)
+hipError_t launch_cell_vjp(const CellArgs &c, const CvSet &cs, const PosView &pos, const double *coef, double sign,
+                           ForceView out, hipStream_t s);
 int32_t mlp_param_count(int32_t H, int32_t D);
 int32_t mlp_bwd_blocks(int32_t H, int64_t n);
 hipError_t launch_mlp_fwd(const MlpArgs &a, const double *xi, int64_t n, double *V, double *dV, float *t_a2,

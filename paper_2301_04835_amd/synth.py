@@ -171,3 +171,37 @@ def chain_walkers(n_walkers, n_atoms=22, seed=4, dtype=np.float32):
     positions (n_walkers * n_atoms, 3) and walker atom offsets."""
     pos = np.concatenate([chain_template(n_atoms, seed * 100003 + w) for w in range(n_walkers)])
     return pos.astype(dtype), np.arange(n_walkers + 1, dtype=np.int64) * n_atoms
+
+
+# ------------------------------------------------------------------------- #
+# Three coordination numbers over 20,000-atom groups: per walker 60,000      #
+# atoms uniform in a 12 nm periodic box, groups A, B, C = consecutive thirds, #
+# CN_AB, CN_BC, CN_CA (r0 0.5 nm, n 6, m 12, hard cut 1.2 nm, divided by     #
+# |A|), one shared list of 10^6 hills of width 0.2 around the expected CN.   #
+# ------------------------------------------------------------------------- #
+CN3 = {"n_group": 20000, "box": 12.0, "r0": 0.5, "rcut": 1.2, "sigma": 0.2,
+       # expected per-atom CN at density 20000 / 12^3 nm^-3 (the integral of
+       # 4 pi r^2 rho s(r) to the cut), the centre of the hill cloud
+       "cn_mean": 9.0817, "hill_sd": 0.3}
+
+
+def cn3_cvs(n_group=20000, r0=0.5, rcut=1.2):
+    g = [list(range(k * n_group, (k + 1) * n_group)) for k in range(3)]
+    mk = lambda a, b: {"kind": "coordination", "a": a, "b": b, "r0": r0, "n": 6, "m": 12, "rcut": rcut,
+                       "normalize": True}
+    return [mk(g[0], g[1]), mk(g[1], g[2]), mk(g[2], g[0])]
+
+
+def cn3_positions(n_walkers, n_group=20000, box=12.0, seed=5):
+    """(n_walkers * 3 n_group, 3) float32 positions uniform in [0, box)^3 and
+    the walker atom offsets."""
+    n = 3 * n_group
+    pos = rng(seed).uniform(0.0, box, size=(n_walkers * n, 3)).astype(np.float32)
+    return pos, np.arange(n_walkers + 1, dtype=np.int64) * n
+
+
+def cn3_hills(K, seed=6, mean=9.0817, sd=0.3):
+    """K hill centres N(mean, sd^2) in each of the three CVs (float32, K x 3)
+    and heights U[0.5, 1.5] kJ/mol."""
+    g = rng(seed)
+    return (mean + sd * g.normal(size=(K, 3))).astype(np.float32), g.uniform(0.5, 1.5, size=K).astype(np.float32)

@@ -1,0 +1,155 @@
+"""Coordination numbers through cell lists against the FP64 oracle (brute
+force over all pairs with the minimum image and the hard cut).
+
+  CN values    <= 1e-6 relative (FP32 pair terms relative to cell origins,
+               FP64 sums)
+  VJP / forces <= 1e-5 relative (inf-norm over a walker's atoms)
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import _clib as oracle
+from oracle import methods
+from paper_2301_04835_amd import synth
+from paper_2301_04835_amd.api import Sampler, SxError
+from gpu_util import dev, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def small_system(W, n, L, seed, self_cn=False):
+    """Three groups of n atoms per walker, some outside [0, L) and some
+    exactly on cell faces (cells of L / 3)."""
+    g = np.random.default_rng(seed)
+    pos = g.uniform(0.0, L, size=(W * 3 * n, 3))
+    pos[::7] += g.choice([-L, L, 2 * L], size=(pos[::7].shape[0], 1))  # outside the box: wrapped
+    pos[3::11, 0] = L / 3.0                                            # on a cell face
+    pos[5::13, 1] = 0.0
+    pos[6::17, 2] = L                                                  # on the far face = 0
+    off = np.arange(W + 1, dtype=np.int64) * 3 * n
+    cvs = synth.cn3_cvs(n, 0.5, 1.2)
+    if self_cn:  # one group with itself: i == j skipped, the gradient counts both sides
+        cvs.append({"kind": "coordination", "a": list(range(n)), "b": list(range(n)), "r0": 0.45, "n": 8,
+                    "m": 14, "rcut": 1.1, "normalize": False})
+    return pos.astype(np.float32), off, cvs
+
+
+def oracle_walker(pos_w, cvs, L):
+    xi, J = methods.cv_eval(pos_w.astype(np.float64), cvs, np.full(3, L))
+    return xi, J
+
+
+def ctx(cvs, L, off, mode, metad=None):
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    s.set_box([L, L, L])
+    s.set_walkers(off, metad["cap"] if metad else None, shared=bool(metad))
+    s.set_cell_lists(mode)
+    if metad:
+        s.metad([metad["sigma"]] * len(cvs), 1.0, 300.0, 6.0, 0, metad["cap"])
+    s.bind()
+    return s
+
+
+@pytest.mark.parametrize("self_cn", [False, True])
+def test_cell_values_and_vjp_against_oracle(gpu, self_cn):
+    W, n, L = 3, 700, 4.0
+    pos, off, cvs = small_system(W, n, L, 21, self_cn)
+    s = ctx(cvs, L, off, 1)
+    assert s.cell_list_cvs() == len(cvs)
+    P = dev(pos)
+    xi = s.eval_cv(P)[0].cpu().numpy()
+    g = np.random.default_rng(3)
+    xb = g.normal(size=(W, len(cvs)))
+    pb = torch.zeros_like(P)
+    s.cv_vjp(P, dev(xb), pb)
+    pb = pb.cpu().numpy()
+    # the all-pairs kernels on the same input
+    a = ctx(cvs, L, off, -1)
+    assert a.cell_list_cvs() == 0
+    xa = a.eval_cv(P)[0].cpu().numpy()
+    for w in range(W):
+        pw = pos[off[w]:off[w + 1]]
+        xr, J = oracle_walker(pw, cvs, L)
+        assert np.max(np.abs(xi[w] - xr) / np.abs(xr)) <= 1e-6
+        assert np.max(np.abs(xa[w] - xr) / np.abs(xr)) <= 1e-6
+        ref = np.tensordot(xb[w], J, axes=1)
+        assert rel_inf(pb[off[w]:off[w + 1]], ref) <= 1e-5
+
+
+def test_cell_mode_rules(gpu):
+    W, n, L = 2, 300, 4.0
+    pos, off, cvs = small_system(W, n, L, 5)
+    # default mode: groups this small stay on the all-pairs kernels
+    assert ctx(cvs, L, off, 0).cell_list_cvs() == 0
+    # a box narrower than three cutoffs cannot use cells
+    assert ctx(cvs, 3.3, off, 1).cell_list_cvs() == 0
+    # groups that overlap without being identical are refused in mode 1
+    bad = [dict(cvs[0]), dict(cvs[1])]
+    bad[1]["a"] = list(range(n // 2, n + n // 2))
+    s = Sampler(0)
+    s.add_cvs(bad)
+    s.set_box([L, L, L])
+    s.set_walkers(off)
+    s.set_cell_lists(1)
+    with pytest.raises(SxError) as e:
+        s.bind()
+    assert e.value.status == 1
+
+
+def test_cell_step_shared_hills_3d(gpu):
+    """Metadynamics step: three cell-list CNs, a shared list of 3-D hills,
+    forces from the VJP kernel, against the oracle's chain rule."""
+    W, n, L, K = 4, 800, 4.0, 5000
+    pos, off, cvs = small_system(W, n, L, 8)
+    P = dev(pos)
+    s = ctx(cvs, L, off, 1, {"sigma": 0.2, "cap": K + 4 * W})
+    xi0 = s.eval_cv(P)[0].cpu().numpy()
+    g = np.random.default_rng(9)
+    C = (xi0.mean(axis=0) + 0.3 * g.normal(size=(K, 3))).astype(np.float32)
+    H = g.uniform(0.5, 1.5, size=K).astype(np.float32)
+    s.hills_set(0, C, H)
+    F = torch.zeros_like(P)
+    xi = torch.zeros((W, 3), dtype=torch.float64, device=P.device)
+    V = torch.zeros(W, dtype=torch.float64, device=P.device)
+    dV = torch.zeros((W, 3), dtype=torch.float64, device=P.device)
+    s.step(P, forces=F, step=1, xi_out=xi, V_out=V, dV_out=dV)
+    s.check()
+    xi, V, dV, F = (t.cpu().numpy() for t in (xi, V, dV, F))
+    Vr, dVr = oracle.hillsum_batch(xi, None, C.astype(np.float64), H.astype(np.float64), [0.2] * 3, [0.0] * 3,
+                                   nthreads=8)
+    assert np.max(np.abs(V - Vr) / Vr) <= 1e-6
+    for w in range(W):
+        assert rel_inf(dV[w], dVr[w]) <= 1e-5
+        xr, J = oracle_walker(pos[off[w]:off[w + 1]], cvs, L)
+        assert np.max(np.abs(xi[w] - xr) / xr) <= 1e-6
+        assert rel_inf(F[off[w]:off[w + 1]], methods.chain_rule(-dV[w], J)) <= 1e-5
+
+
+def test_cn3_full_size_sampled(gpu):
+    """512 walkers of 60,000 atoms in a 12 nm box, groups of 20,000 (default
+    mode picks the cell lists); walker 137 checked against the oracle."""
+    p = synth.CN3
+    W, n = 512, p["n_group"]
+    cvs = synth.cn3_cvs(n, p["r0"], p["rcut"])
+    pos, off = synth.cn3_positions(W, n, p["box"])
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    s.set_box([p["box"]] * 3)
+    s.set_walkers(off)
+    s.bind()
+    assert s.cell_list_cvs() == 3
+    P = dev(pos)
+    xi = s.eval_cv(P)[0].cpu().numpy()
+    assert np.all(np.abs(xi - p["cn_mean"]) < 0.2)
+    w = 137
+    xb = np.zeros((W, 3))
+    xb[w] = [0.7, -1.3, 0.4]
+    pb = torch.zeros_like(P)
+    s.cv_vjp(P, dev(xb), pb)
+    xr, J = oracle_walker(pos[off[w]:off[w + 1]], cvs, p["box"])
+    assert np.max(np.abs(xi[w] - xr) / xr) <= 1e-6
+    pbw = pb.cpu().numpy()
+    assert rel_inf(pbw[off[w]:off[w + 1]], np.tensordot(xb[w], J, axes=1)) <= 1e-5
+    assert np.all(pbw[:off[w]] == 0) and np.all(pbw[off[w + 1]:] == 0)
