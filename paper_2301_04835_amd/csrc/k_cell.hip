@@ -14,7 +14,8 @@
 //                  B members of the 27 neighbour cells are staged in LDS
 //                  relative to the home cell's origin (a neighbour's offset
 //                  is its cell step times the cell edge, periodic wrap
-//                  included), wavefronts take home atoms, lanes take partners;
+//                  included), groups of 16 lanes take home atoms (four per
+//                  wavefront), their lanes take partners, four at a time;
 //                  FP32 pair terms, FP64 sums; one partial per home cell.
 //   k_cn_cell_fin  per (walker, CV): the home-cell partials in cell order.
 //   k_cell_vjp     one workgroup per (walker, group, home cell): for every use
@@ -33,7 +34,7 @@ namespace sx {
 namespace {
 
 constexpr int kBuildBlock = 1024;
-constexpr int kStageMax = 2048;  // partner atoms staged per round
+constexpr int kStageMax = 1024;  // partner atoms staged per round (16 KB of LDS)
 constexpr int kHomeMax = 128;    // home atoms per force round
 
 __device__ __forceinline__ int cell_of(double x, double L, double iL, double clen, int nc, double &rel)
@@ -162,6 +163,64 @@ __device__ __forceinline__ bool within_cut(float r2, const CvDesc &cv, const Cel
     return cut_exact(pos, aoff, ai, aj, c.L[0], c.L[1], c.L[2], cv.rcut);
 }
 
+// switching function: the (6, 12) form as a template choice, else the
+// general form of switch_fn
+template <bool S612>
+__device__ __forceinline__ void sw(float r2, const CvDesc &cv, float &s, float &f)
+{
+    if (S612) {
+        const float ir = cv.inv_r0 * cv.inv_r0;
+        const float x2 = r2 * ir, x4 = x2 * x2;
+        const float sv = __builtin_amdgcn_rcpf(fmaf(x4, x2, 1.0f));
+        s = sv;
+        f = -6.0f * x4 * sv * sv * ir;
+    } else {
+        switch_fn(r2, cv, s, f);
+    }
+}
+
+// Four partners j0 + kLpa q (q < 4) of home atom `me` at pi, the kLpa lanes
+// of a lane group over j0: r^2 in FP32 from cell-relative coordinates, the
+// cut decided by within_cut (its exact path behind one wavefront-uniform
+// vote).  A wavefront works on 64 / kLpa home atoms at a time.
+constexpr int kUnroll = 4;
+constexpr int kLpa = 16;             // lanes per home atom
+constexpr int kApw = 64 / kLpa;      // home atoms per wavefront
+struct PairBatch {
+    float dx[kUnroll], dy[kUnroll], dz[kUnroll], r2[kUnroll];
+    bool in[kUnroll];
+};
+
+__device__ __forceinline__ void pair_batch(const float4 &pi, int32_t me, const float4 *s_p, int j0, int m,
+                                           const CvDesc &cv, const CellArgs &c, const PosView &pos, int64_t aoff,
+                                           PairBatch &b)
+{
+    // s_p is padded with far atoms to a multiple of 64 >= m: j0 + kLpa q < 64 ceil(m / 64)
+    const bool self = cv.ga == cv.gb;  // uniform: a group paired with itself skips i == j
+    const float band = 1e-5f * cv.rcut2;
+    bool near = false;
+    int32_t him[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+        const float4 pj = s_p[j0 + kLpa * q];
+        him[q] = __float_as_int(pj.w);
+        b.dx[q] = pi.x - pj.x;
+        b.dy[q] = pi.y - pj.y;
+        b.dz[q] = pi.z - pj.z;
+        b.r2[q] = fmaf(b.dx[q], b.dx[q], fmaf(b.dy[q], b.dy[q], b.dz[q] * b.dz[q]));
+        const float t = b.r2[q] - cv.rcut2;
+        const bool ok = m > 0 && (!self || him[q] != me);
+        b.in[q] = ok && t < 0.f;
+        near = near || (ok && fabsf(t) <= band);
+    }
+    if (__any(near)) {  // rare: a pair at the edge of the cut somewhere in the wavefront
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q)
+            if (m > 0 && him[q] >= 0 && (!self || him[q] != me) && fabsf(b.r2[q] - cv.rcut2) <= band)
+                b.in[q] = cut_exact(pos, aoff, me, him[q], c.L[0], c.L[1], c.L[2], cv.rcut);
+    }
+}
+
 __device__ __forceinline__ const CvDesc &cell_cv(const CvSet &cs, int k)
 {
     int c = 0;
@@ -197,27 +256,33 @@ __device__ __forceinline__ int stage_partners(const CellArgs &c, int w, int gp, 
     __syncthreads();
     const int total = s_seg[27];
     const int m = min(kStageMax, total - r0);
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        const int e = r0 + j;
-        int t = 0;
-        while (s_seg[t + 1] <= e) ++t;  // at most 26 steps
-        float4 v = srt[s_seg[32 + t] + (e - s_seg[t])];
-        v.x += s_sh[3 * t];
-        v.y += s_sh[3 * t + 1];
-        v.z += s_sh[3 * t + 2];
+    // padded to a multiple of 64 with atoms far outside any cut (index -1)
+    const int mp = min(kStageMax, (m + 63) & ~63);
+    for (int j = threadIdx.x; j < mp; j += blockDim.x) {
+        float4 v = make_float4(1e6f, 1e6f, 1e6f, __int_as_float(-1));
+        if (j < m) {
+            const int e = r0 + j;
+            int t = 0;
+            while (s_seg[t + 1] <= e) ++t;  // at most 26 steps
+            v = srt[s_seg[32 + t] + (e - s_seg[t])];
+            v.x += s_sh[3 * t];
+            v.y += s_sh[3 * t + 1];
+            v.z += s_sh[3 * t + 2];
+        }
         s_p[j] = v;
     }
     __syncthreads();
     return m;
 }
 
-__global__ void __launch_bounds__(kBlock) k_cn_cell(CellArgs c, CvSet cs, PosView pos)
+template <bool S612>
+__global__ void __launch_bounds__(kBlock) k_cn_cell(CellArgs c, CvSet cs, PosView pos, int k)
 {
     __shared__ float4 s_p[kStageMax];
     __shared__ int32_t s_seg[64];
     __shared__ float s_sh[81];
     __shared__ double s_red[kBlock / 64];
-    const int home = blockIdx.x, k = blockIdx.y, w = blockIdx.z;
+    const int home = blockIdx.x, w = blockIdx.z;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const CvDesc cv = cell_cv(cs, k);
     const int32_t *cstA = c.cstart + ((int64_t)w * c.G + cv.ga) * (c.ncell + 1);
@@ -229,26 +294,31 @@ __global__ void __launch_bounds__(kBlock) k_cn_cell(CellArgs c, CvSet cs, PosVie
         return;
     }
     const int64_t aoff = c.atom_off[w];
-    float acc = 0.f;
+    float acc[kUnroll] = {0.f, 0.f, 0.f, 0.f};
     for (int r0 = 0;; r0 += kStageMax) {
         const int m = stage_partners(c, w, cv.gb, home, r0, s_p, s_seg, s_sh);
-        for (int i = a0 + wave; i < a1; i += kBlock / 64) {
-            const float4 pi = sA[i];
+        const int grp = lane / kLpa, gl = lane % kLpa;
+        for (int ib = a0 + wave * kApw; ib < a1; ib += (kBlock / 64) * kApw) {
+            const int i = ib + grp;  // this lane group's home atom
+            const bool live = i < a1;
+            const float4 pi = sA[live ? i : a0];
             const int32_t me = __float_as_int(pi.w);
-            for (int j = lane; j < m; j += 64) {
-                const float4 pj = s_p[j];
-                const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                float s, f;
-                switch_fn(r2, cv, s, f);
-                const int32_t him = __float_as_int(pj.w);
-                acc += (him != me && within_cut(r2, cv, c, pos, aoff, me, him)) ? s : 0.f;
+            const int mm = live ? m : 0;
+            for (int j0 = gl; j0 < m; j0 += kLpa * kUnroll) {
+                PairBatch b;
+                pair_batch(pi, me, s_p, j0, mm, cv, c, pos, aoff, b);
+#pragma unroll
+                for (int q = 0; q < kUnroll; ++q) {
+                    float sv, f;
+                    sw<S612>(b.r2[q], cv, sv, f);
+                    acc[q] += b.in[q] ? sv : 0.f;
+                }
             }
         }
         if (r0 + m >= s_seg[27]) break;  // uniform
         __syncthreads();                 // the next round overwrites s_p
     }
-    double v = (double)acc;
+    double v = ((double)acc[0] + (double)acc[1]) + ((double)acc[2] + (double)acc[3]);
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (lane == 0) s_red[wave] = v;
     __syncthreads();
@@ -277,6 +347,7 @@ __global__ void __launch_bounds__(kBlock) k_cn_cell_fin(CellArgs c, CvSet cs, do
     }
 }
 
+template <bool S612>
 __global__ void __launch_bounds__(kBlock) k_cell_vjp(CellArgs c, CvSet cs, PosView pos, const double *coef,
                                                       double sign, ForceView F)
 {
@@ -300,32 +371,37 @@ __global__ void __launch_bounds__(kBlock) k_cell_vjp(CellArgs c, CvSet cs, PosVi
             const double cf = sign * coef[(int64_t)w * cs.D + cv.d] * (double)cv.scale;
             for (int r0 = 0;; r0 += kStageMax) {
                 const int m = stage_partners(c, w, c.inv_p[g][u], home, r0, s_p, s_seg, s_sh);
-                for (int i = h0 + wave; i < h1; i += kBlock / 64) {
-                    const float4 pi = sg[i];
+                const int grp = lane / kLpa, gl = lane % kLpa;
+                for (int ib = h0 + wave * kApw; ib < h1; ib += (kBlock / 64) * kApw) {
+                    const int i = ib + grp;  // this lane group's home atom
+                    const bool live = i < h1;
+                    const float4 pi = sg[live ? i : h0];
                     const int32_t me = __float_as_int(pi.w);
+                    const int mm = live ? m : 0;
                     float gx = 0.f, gy = 0.f, gz = 0.f;
-                    for (int j = lane; j < m; j += 64) {
-                        const float4 pj = s_p[j];
-                        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        float s, f;
-                        switch_fn(r2, cv, s, f);
-                        const int32_t him = __float_as_int(pj.w);
-                        f = (him != me && within_cut(r2, cv, c, pos, aoff, me, him)) ? f : 0.f;
-                        gx = fmaf(f, dx, gx);
-                        gy = fmaf(f, dy, gy);
-                        gz = fmaf(f, dz, gz);
+                    for (int j0 = gl; j0 < m; j0 += kLpa * kUnroll) {
+                        PairBatch b;
+                        pair_batch(pi, me, s_p, j0, mm, cv, c, pos, aoff, b);
+#pragma unroll
+                        for (int q = 0; q < kUnroll; ++q) {
+                            float sv, f;
+                            sw<S612>(b.r2[q], cv, sv, f);
+                            f = b.in[q] ? f : 0.f;
+                            gx = fmaf(f, b.dx[q], gx);
+                            gy = fmaf(f, b.dy[q], gy);
+                            gz = fmaf(f, b.dz[q], gz);
+                        }
                     }
-                    double vx = gx, vy = gy, vz = gz;
-                    for (int o = 32; o > 0; o >>= 1) {
-                        vx += __shfl_xor(vx, o, 64);
-                        vy += __shfl_xor(vy, o, 64);
-                        vz += __shfl_xor(vz, o, 64);
+                    // butterfly over the lane group (FP32: error ~ log2(16) ulp of the terms)
+                    for (int o = kLpa / 2; o > 0; o >>= 1) {
+                        gx += __shfl_xor(gx, o, 64);
+                        gy += __shfl_xor(gy, o, 64);
+                        gz += __shfl_xor(gz, o, 64);
                     }
-                    if (lane == 0) {  // one wavefront per home atom: the only writer
-                        s_f[i - h0][0] += cf * vx;
-                        s_f[i - h0][1] += cf * vy;
-                        s_f[i - h0][2] += cf * vz;
+                    if (gl == 0 && live) {  // one lane group per home atom: the only writer
+                        s_f[i - h0][0] += cf * (double)gx;
+                        s_f[i - h0][1] += cf * (double)gy;
+                        s_f[i - h0][2] += cf * (double)gz;
                     }
                 }
                 if (r0 + m >= s_seg[27]) break;  // uniform
@@ -355,9 +431,16 @@ hipError_t launch_cell_cv(const CellArgs &c, const CvSet &cs, const PosView &pos
         hipLaunchKernelGGL(k_cell_build<float>, dim3(c.W * c.G), dim3(kBuildBlock), 0, s, c, pos);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cn_cell, dim3(c.ncell, c.ncn, c.W), dim3(kBlock), 0, s, c, cs, pos);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    for (int d = 0; d < cs.ncv; ++d) {  // one launch per CV: its switching form is a template choice
+        const CvDesc &cv = cs.cv[d];
+        if (cv.kind != CV_COORD_CELL) continue;
+        if (cv.n == 6 && cv.m == 12)
+            hipLaunchKernelGGL(k_cn_cell<true>, dim3(c.ncell, 1, c.W), dim3(kBlock), 0, s, c, cs, pos, cv.cn);
+        else
+            hipLaunchKernelGGL(k_cn_cell<false>, dim3(c.ncell, 1, c.W), dim3(kBlock), 0, s, c, cs, pos, cv.cn);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_cn_cell_fin, dim3(c.ncn, c.W), dim3(kBlock), 0, s, c, cs, xi);
     return hipGetLastError();
 }
@@ -366,7 +449,13 @@ hipError_t launch_cell_vjp(const CellArgs &c, const CvSet &cs, const PosView &po
                            ForceView out, hipStream_t s)
 {
     if (c.ncn == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cell_vjp, dim3(c.ncell, c.G, c.W), dim3(kBlock), 0, s, c, cs, pos, coef, sign, out);
+    bool all612 = true;
+    for (int d = 0; d < cs.ncv; ++d)
+        if (cs.cv[d].kind == CV_COORD_CELL) all612 = all612 && cs.cv[d].n == 6 && cs.cv[d].m == 12;
+    if (all612)
+        hipLaunchKernelGGL(k_cell_vjp<true>, dim3(c.ncell, c.G, c.W), dim3(kBlock), 0, s, c, cs, pos, coef, sign, out);
+    else
+        hipLaunchKernelGGL(k_cell_vjp<false>, dim3(c.ncell, c.G, c.W), dim3(kBlock), 0, s, c, cs, pos, coef, sign, out);
     return hipGetLastError();
 }
 
