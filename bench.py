@@ -40,6 +40,8 @@ def parse():
                     help="after the run, copy this many MiB with the plain copy probe (counter calibration)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
     ap.add_argument("--no-bust", action="store_true", help="skip the cache-busting replica of the hill kernel")
+    ap.add_argument("--no-cn3", action="store_true", help="skip the cell-list coordination-number workload")
+    ap.add_argument("--cn3-steps", type=int, default=50, help="timed steps of the coordination-number workload")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2301_04835_amd", "tuning_mi355x.json"),
                     help="autotuner cache (JSON): an entry for this problem shape is reused, else searched and added")
     ap.add_argument("--sg-train-steps", type=int, default=100000, help="Adam steps of the surrogate fit")
@@ -236,6 +238,96 @@ def surrogate_leg(args):
     return res, (C, H, pos_np, off, sg)
 
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
+
+
+def cn3_leg(args):
+    """512 walkers, each 60,000 atoms uniform in a 12 nm periodic box; three
+    coordination numbers between 20,000-atom groups (r0 0.5 nm, (6, 12), hard
+    cut 1.2 nm, divided by |A|) through cell lists; one shared list of 10^6
+    three-dimensional hills (sigma 0.2) around the expected CN.  One step =
+    cell sort, pair sums, hill sum, forces by pair recompute (VJP); replayed
+    graphs.  Then the same with a 6-128-128-1 surrogate."""
+    import torch
+    from paper_2301_04835_amd import Sampler, synth
+
+    p = synth.CN3
+    W, n, K = 512, p["n_group"], 1000000
+    cvs = synth.cn3_cvs(n, p["r0"], p["rcut"])
+    pos_np, off = synth.cn3_positions(W, n, p["box"])
+    C, H = synth.cn3_hills(K, mean=p["cn_mean"], sd=p["hill_sd"])
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    s.set_box([p["box"]] * 3)
+    s.set_walkers(off, [K + 64 * W], shared=True)
+    s.metad([p["sigma"]] * 3, 1.0, 300.0, 6.0, 0, K + 64 * W)
+    s.surrogate(128, max_samples=1 << 17, max_batch=2048, cert_n=48, tol_force=1.0)
+    s.bind()
+    s.hills_set(0, C, H)
+    pos = torch.from_numpy(pos_np).cuda()
+    forces = torch.zeros_like(pos)
+    mk = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+    ex = (mk(W, 3), mk(W), mk(W, 3))
+    rate, nst = timed_graph(s, pos, forces, ex, args.cn3_steps, 10, gsteps=5)
+    ms_cv, ms_vjp = s.time_cell(pos, forces=forces, reps=10)
+    # algorithmic work: expected pairs inside the cut (density x sphere volume)
+    rho = n / p["box"] ** 3
+    pairs = 3 * W * n * rho * 4.0 / 3.0 * np.pi * p["rcut"] ** 3
+    vjp_flops = 2 * pairs * 23   # both sides of each pair: r^2 8, switch and derivative 9, 3 FMAs 6
+    fwd_flops = pairs * 17       # r^2 8, switch 8, sum 1
+    res = {"workload": "cn3-cells-512-walkers-1M-shared-hills", "walkers": W, "atoms_per_walker": 3 * n,
+           "cvs": "CN_AB, CN_BC, CN_CA over 20,000-atom groups, cut 1.2 nm, 10^3 cells", "hills": K,
+           "steps_per_s": rate, "ms_per_step": 1e3 / rate, "steps_timed": nst,
+           "cell_cv_ms": ms_cv, "vjp_kernel_ms": ms_vjp, "pairs_in_cut_per_step": pairs,
+           "roofline": {"bound": "alu", "kernel": "k_cell_vjp<true>", "achieved": vjp_flops / (ms_vjp * 1e-3) / 1e12,
+                        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": vjp_flops / (ms_vjp * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                        "flops_per_launch": vjp_flops, "traffic": None},
+           "cv_kernels_tflops": fwd_flops / (ms_cv * 1e-3) / 1e12}
+    # surrogate: 6-128-128-1 on standardised CNs, certified on a 48^3 grid
+    # over mean +- 1.2; tolerance 1e-3 of the rms gradient of the bias (the
+    # bias of 10^6 hills reaches ~10^5 kJ/mol: an absolute tolerance of the
+    # dihedral workloads' size has no meaning here)
+    g = np.random.default_rng(12)
+    X = torch.from_numpy(p["cn_mean"] + p["hill_sd"] * g.normal(size=(1 << 17, 3))).cuda()
+    s.surrogate_norm([p["cn_mean"]] * 3, [p["hill_sd"]] * 3)
+    P0 = []
+    for fan_in, shape in [(6, (128, 6)), (1, (128,)), (128, (128, 128)), (1, (128,)), (128, (128,)), (1, (1,))]:
+        P0.append((g.uniform(-1, 1, shape) / np.sqrt(fan_in) if fan_in > 1 else np.zeros(shape)).ravel())
+    s.surrogate_params(np.concatenate(P0).astype(np.float32))
+    t0 = time.perf_counter()
+    s.surrogate_train(X, batch=2048, steps=20000, lr=3e-3, lr_final=1e-5)
+    t_train = time.perf_counter() - t0
+    Vx, dVx = s.bias_eval(X[:4096])
+    g_rms = float(torch.sqrt((dVx ** 2).sum(1).mean()).item())
+    lo, hi = [p["cn_mean"] - 1.2] * 3, [p["cn_mean"] + 1.2] * 3
+    tol = 1e-3 * g_rms
+    s.surrogate_tolerance(tol)
+    frac = s.surrogate_certify(lo, hi)
+    s.surrogate_enable(True)
+    sg = (mk(W, 3), mk(W), mk(W, 3))
+    rate_sg, _ = timed_graph(s, pos, forces, sg, args.cn3_steps, 10, gsteps=5)
+    nfb = s.surrogate_fallback_count()
+    s.surrogate_enable(False)
+    res["surrogate"] = {"network": "6-128-128-1 tanh on (u, u^2), bf16 weights", "train_steps": 20000,
+                        "train_s": t_train, "certify_grid": "48^3 over mean +- 1.2", "tol_force": tol,
+                        "rms_bias_gradient": g_rms, "certified_fraction": frac, "fallback_walkers": nfb,
+                        "steps_per_s": rate_sg, "speedup": rate_sg / rate}
+    return res, (pos_np, off, cvs, p)
+
+
+def cn3_oracle(cn_data):
+    """CPU oracle leg: one walker's three coordination numbers and their
+    gradients (brute force over all pairs, FP64, one thread)."""
+    import oracle
+
+    pos_np, off, cvs, p = cn_data
+    t0 = time.perf_counter()
+    oracle.cv_eval(pos_np[off[0]:off[1]].astype(np.float64), cvs, np.full(3, p["box"]))
+    el = time.perf_counter() - t0
+    return {"oracle_s_per_walker_cvs_and_gradients_1_thread": el}
+
+
 def surrogate_oracle_check(sg_data):
     """CPU oracle leg of the surrogate workload: the FP64 hill sum at the
     walkers' CV values, against which the surrogate step's dV/dxi error is
@@ -343,10 +435,15 @@ def main():
     sg_data = None
     if not args.no_surrogate:
         out["surrogate"], sg_data = surrogate_leg(args)
+    cn_data = None
+    if not args.no_cn3:
+        out["cn3"], cn_data = cn3_leg(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, p, args.cpu_seconds)
         if sg_data is not None:
             out["surrogate"].update(surrogate_oracle_check(sg_data))
+        if cn_data is not None:
+            out["cn3"].update(cn3_oracle(cn_data))
     print(json.dumps(out))
 
 

@@ -352,6 +352,9 @@ sx_status sx_surrogate_train(sx_ctx *ctx, const double *xi, int64_t n, int32_t b
  * hills or parameters, depositing, training or an exact step that may
  * deposit drops it.  Synchronous. */
 sx_status sx_surrogate_certify(sx_ctx *ctx, const double *lo, const double *hi, double *certified_fraction);
+/* Change the certification tolerance (kJ/mol per CV unit, > 0); drops the
+ * certification. */
+sx_status sx_surrogate_tolerance(sx_ctx *ctx, double tol_force);
 /* Switch the surrogate into sx_step (needs parameters and a certification;
  * a shared hill list or one walker).  While on, the step evaluates the
  * network for every walker, the exact sum of the shared list for the
@@ -372,6 +375,14 @@ sx_status sx_surrogate_fallback_count(sx_ctx *ctx, int32_t *count);
  * Synchronous.  ms_tiles / ms_finalize: host, milliseconds per launch. */
 sx_status sx_time_hill(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
                        float *ms_tiles, float *ms_finalize);
+/* Average duration of the cell-list kernels on the bound state: `reps`
+ * evaluations of the cell-list CVs (cell sort, pair sums, finalize; positions
+ * as sx_step receives them), then `reps` launches of the VJP kernel adding
+ * -dV/dxi (of the last step) times their Jacobian to forces (device, layout
+ * of pos; may be NULL: no VJP timing), bracketed by hipEvents on the
+ * context's stream.  Synchronous.  ms_cv / ms_vjp: host, ms per launch. */
+sx_status sx_time_cell(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
+                       float *ms_cv, float *ms_vjp);
 /* Plain streaming read of `bytes` (multiple of 16) from device memory src
  * with `grid` workgroups; each workgroup writes one float to sink[grid]
  * (device).  Enqueued on `stream` (hipStream_t).  Used to calibrate the

@@ -334,6 +334,9 @@ class Sampler:
         self._check(self.L.sx_surrogate_certify(self.h, plo[1], phi[1], ctypes.byref(frac)))
         return frac.value
 
+    def surrogate_tolerance(self, tol_force):
+        self._check(self.L.sx_surrogate_tolerance(self.h, float(tol_force)))
+
     def surrogate_enable(self, on=True):
         self._check(self.L.sx_surrogate_enable(self.h, 1 if on else 0))
 
@@ -360,6 +363,13 @@ class Sampler:
         g = ctypes.c_int32()
         self._check(self.L.sx_get_tuning(self.h, ctypes.byref(t), ctypes.byref(g)))
         return t.value, g.value
+
+    def time_cell(self, pos, forces=None, reps=20, layout="aos3"):
+        """ms per launch of the cell-list CV kernels and of the VJP kernel."""
+        a, b = ctypes.c_float(), ctypes.c_float()
+        self._check(self.L.sx_time_cell(self.h, _ptr(pos), _pos_dtype(pos), _LAYOUTS[layout], _ptr(forces), int(reps),
+                                        ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def time_hill(self, pos, forces=None, reps=100, layout="aos3"):
         """(ms per tile-kernel launch, ms per finalize-kernel launch) measured

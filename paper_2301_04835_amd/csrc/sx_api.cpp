@@ -1599,6 +1599,15 @@ sx_status sx_surrogate_certify(sx_ctx *ctx, const double *lo, const double *hi, 
     SX_GUARD_END
 }
 
+sx_status sx_surrogate_tolerance(sx_ctx *ctx, double tol_force)
+{
+    if (!ctx) return SX_EINVAL;
+    if (!(tol_force > 0) || !std::isfinite(tol_force)) return fail(ctx, SX_EINVAL, "tol_force must be > 0");
+    ctx->sg_tol = tol_force;
+    ctx->sg_certified = ctx->sg_on = false;
+    return SX_OK;
+}
+
 sx_status sx_surrogate_enable(sx_ctx *ctx, int32_t on)
 {
     if (sx_status s = require_surrogate(ctx)) return s;
@@ -1947,6 +1956,40 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
                 << (++i < cache.size() ? ",\n" : "\n");
         out << "}\n";
     }
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_time_cell(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
+                       float *ms_cv, float *ms_vjp)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    const Plan &p = ctx->plan;
+    if (!p.cell.ncn) return fail(ctx, SX_ESTATE, "no cell-list coordination numbers in this plan");
+    PosView pv;
+    if (!pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
+    if (reps < 1 || !ms_cv || !ms_vjp) return fail(ctx, SX_EINVAL, "reps must be >= 1, outputs non-NULL");
+    const CellArgs ca = cell_args(ctx);
+    double *xi = at<double>(ctx->ws, p.w_xi), *coef = at<double>(ctx->ws, p.w_dV);
+    hipEvent_t e[3];
+    for (auto &x : e)
+        if (hipEventCreate(&x) != hipSuccess) return fail(ctx, SX_EDEVICE, "events");
+    hipError_t err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream);  // warm, and cells for the VJP
+    if (err == hipSuccess) err = hipEventRecord(e[0], ctx->stream);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream);
+    if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
+    for (int r = 0; r < reps && err == hipSuccess && forces; ++r)
+        err = launch_cell_vjp(ca, p.cs, pv, coef, -1.0, force_view(ctx, forces, layout), ctx->stream);
+    if (err == hipSuccess) err = hipEventRecord(e[2], ctx->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e[2]);
+    float a = 0, b = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&a, e[0], e[1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&b, e[1], e[2]);
+    for (auto &x : e) hipEventDestroy(x);
+    if (err != hipSuccess) return hip_fail(ctx, err, "cell timing");
+    *ms_cv = a / reps;
+    *ms_vjp = forces ? b / reps : 0.f;
     return SX_OK;
     SX_GUARD_END
 }

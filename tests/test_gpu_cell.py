@@ -153,3 +153,62 @@ def test_cn3_full_size_sampled(gpu):
     pbw = pb.cpu().numpy()
     assert rel_inf(pbw[off[w]:off[w + 1]], np.tensordot(xb[w], J, axes=1)) <= 1e-5
     assert np.all(pbw[:off[w]] == 0) and np.all(pbw[off[w + 1]:] == 0)
+
+
+def test_cell_surrogate_step(gpu):
+    """Surrogate on three cell-list CNs (6-128-128-1 on standardised CNs):
+    each walker gets the network's or the exact bias by its cell's
+    certification, and its forces are the VJP of the dV/dxi it got."""
+    W, n, L, K = 6, 800, 4.0, 3000
+    pos, off, cvs = small_system(W, n, L, 30)
+    P = dev(pos)
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    s.set_box([L, L, L])
+    s.set_walkers(off, [K + 64], shared=True)
+    s.set_cell_lists(1)
+    s.metad([0.2] * 3, 1.0, 300.0, 6.0, 0, K + 64)
+    s.surrogate(128, max_samples=1 << 14, max_batch=1024, cert_n=24, tol_force=1.0)
+    s.bind()
+    xi0 = s.eval_cv(P)[0].cpu().numpy()
+    mu, sd = xi0.mean(axis=0), 0.3
+    g = np.random.default_rng(31)
+    C = (mu + sd * g.normal(size=(K, 3))).astype(np.float32)
+    H = g.uniform(0.5, 1.5, size=K).astype(np.float32)
+    s.hills_set(0, C, H)
+    s.surrogate_norm(mu, [sd] * 3)
+    P0 = np.concatenate([np.ravel(v) for v in mlp_init(128, 6)]).astype(np.float32)
+    s.surrogate_params(P0)
+    X = dev(mu + sd * g.normal(size=(1 << 14, 3)))
+    s.surrogate_train(X, batch=1024, steps=3000, lr=3e-3, lr_final=1e-5)
+    _, dVx = s.bias_eval(X[:2048])
+    s.surrogate_tolerance(0.05 * float(torch.sqrt((dVx ** 2).sum(1).mean()).item()))
+    frac = s.surrogate_certify(mu - 1.0, mu + 1.0)
+    assert 0.0 < frac < 1.0
+    s.surrogate_enable(True)
+    F = torch.zeros_like(P)
+    xi = torch.zeros((W, 3), dtype=torch.float64, device=P.device)
+    V = torch.zeros(W, dtype=torch.float64, device=P.device)
+    dV = torch.zeros((W, 3), dtype=torch.float64, device=P.device)
+    s.step(P, forces=F, step=0, xi_out=xi, V_out=V, dV_out=dV)
+    s.check()
+    Vn, dVn, fb = s.surrogate_eval(xi, fallback=True)
+    fb = fb.cpu().numpy().astype(bool)
+    xi, V, dV, F = (t.cpu().numpy() for t in (xi, V, dV, F))
+    assert s.surrogate_fallback_count() == fb.sum()
+    Vr, dVr = oracle.hillsum_batch(xi, None, C.astype(np.float64), H.astype(np.float64), [0.2] * 3, [0.0] * 3,
+                                   nthreads=8)
+    for w in range(W):
+        if fb[w]:
+            assert abs(V[w] - Vr[w]) <= 1e-6 * abs(Vr[w]) and rel_inf(dV[w], dVr[w]) <= 1e-5
+        else:
+            assert V[w] == Vn.cpu().numpy()[w] and np.array_equal(dV[w], dVn.cpu().numpy()[w])
+        xr, J = oracle_walker(pos[off[w]:off[w + 1]], cvs, L)
+        assert np.max(np.abs(xi[w] - xr) / xr) <= 1e-6
+        assert rel_inf(F[off[w]:off[w + 1]], methods.chain_rule(-dV[w], J)) <= 1e-5
+
+
+def mlp_init(H, F):
+    from oracle import mlp
+    P = mlp.init_params(H, F, 2)
+    return [P[k] for k in mlp.PARAM_ORDER]
