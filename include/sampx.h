@@ -375,14 +375,16 @@ sx_status sx_surrogate_fallback_count(sx_ctx *ctx, int32_t *count);
  * Synchronous.  ms_tiles / ms_finalize: host, milliseconds per launch. */
 sx_status sx_time_hill(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
                        float *ms_tiles, float *ms_finalize);
-/* Average duration of the cell-list kernels on the bound state: `reps`
- * evaluations of the cell-list CVs (cell sort, pair sums, finalize; positions
- * as sx_step receives them), then `reps` launches of the VJP kernel adding
- * -dV/dxi (of the last step) times their Jacobian to forces (device, layout
- * of pos; may be NULL: no VJP timing), bracketed by hipEvents on the
- * context's stream.  Synchronous.  ms_cv / ms_vjp: host, ms per launch. */
+/* Average duration of the cell-list kernels on the bound state, `reps`
+ * launches each, bracketed by hipEvents on the context's stream: the cell
+ * sort, the pair pass (CV values and the members' gradients, with its
+ * finalize), and the vector-Jacobian gather adding -dV/dxi (of the last
+ * step) times those gradients to forces (device, layout of pos; may be
+ * NULL: not timed).  Positions as sx_step receives them.  Synchronous.
+ * ms_sort / ms_pairs / ms_vjp: host, ms per launch. */
 sx_status sx_time_cell(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
-                       float *ms_cv, float *ms_vjp);
+                       float *ms_sort, float *ms_pairs, float *ms_vjp);
+
 /* Plain streaming read of `bytes` (multiple of 16) from device memory src
  * with `grid` workgroups; each workgroup writes one float to sink[grid]
  * (device).  Enqueued on `stream` (hipStream_t).  Used to calibrate the

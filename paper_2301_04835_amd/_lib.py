@@ -63,7 +63,7 @@ SIGNATURES = {
     "sx_get_tuning": (i32, [P, P, P]),
     "sx_autotune": (i32, [P, P, i32, i32, ctypes.c_char_p]),
     "sx_time_hill": (i32, [P, P, i32, i32, P, i32, P, P]),
-    "sx_time_cell": (i32, [P, P, i32, i32, P, i32, P, P]),
+    "sx_time_cell": (i32, [P, P, i32, i32, P, i32, P, P, P]),
     "sx_probe_read": (i32, [P, sz, P, i32, P]),
     "sx_probe_copy": (i32, [P, P, sz, i32, P]),
     "sx_set_cell_lists": (i32, [P, i32]),

@@ -365,11 +365,11 @@ class Sampler:
         return t.value, g.value
 
     def time_cell(self, pos, forces=None, reps=20, layout="aos3"):
-        """ms per launch of the cell-list CV kernels and of the VJP kernel."""
-        a, b = ctypes.c_float(), ctypes.c_float()
+        """ms per launch of the cell sort, the pair pass and the VJP gather."""
+        a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
         self._check(self.L.sx_time_cell(self.h, _ptr(pos), _pos_dtype(pos), _LAYOUTS[layout], _ptr(forces), int(reps),
-                                        ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+                                        ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def time_hill(self, pos, forces=None, reps=100, layout="aos3"):
         """(ms per tile-kernel launch, ms per finalize-kernel launch) measured

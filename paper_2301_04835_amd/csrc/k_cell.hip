@@ -10,20 +10,22 @@
 //                  a cell), so every later sum runs in a fixed order; each
 //                  member is stored as (x, y, z) relative to its cell's
 //                  origin (float, ~6e-8 nm) and its atom index.
-//   k_cn_cell      one workgroup per (walker, CV, home cell of group A): the
-//                  B members of the 27 neighbour cells are staged in LDS
-//                  relative to the home cell's origin (a neighbour's offset
-//                  is its cell step times the cell edge, periodic wrap
-//                  included), groups of 16 lanes take home atoms (four per
-//                  wavefront), their lanes take partners, four at a time;
-//                  FP32 pair terms, FP64 sums; one partial per home cell.
-//   k_cn_cell_fin  per (walker, CV): the home-cell partials in cell order.
-//   k_cell_vjp     one workgroup per (walker, group, home cell): for every use
-//                  of the group (CV, side, partner group) the partners of each
-//                  home atom are recomputed and its gradient accumulated in
-//                  FP64; the workgroup alone writes its atoms' forces (no
-//                  atomics; needs groups that are identical or disjoint).
-//
+//   k_cell_jac     one wavefront per (walker, group, column block of 3
+//                  cells in z): the partner group's members in the 3 x 3 x 5
+//                  cells around the block are staged in LDS relative to the
+//                  block's origin (a cell's offset is its cell step times the
+//                  cell edge, periodic wrap included), slice by slice, so each
+//                  home cell's 27 neighbours form one contiguous range; each
+//                  lane owns one home atom and walks that range four partners
+//                  at a time: FP32 pair terms, the switch sum (the CV value,
+//                  on the A side) and the gradient sum_j f(r_ij)(r_i - r_j)
+//                  of each (CV, side) use, stored per member (no atomics,
+//                  fixed order).
+//   k_cn_cell_fin  per (walker, CV): the column-block partials in order.
+//   k_cell_gather  the vector-Jacobian product from the stored gradients,
+//                  one lane per member (groups identical or disjoint: one
+//                  writer per atom).
+
 // Cells have edge >= the cutoff and there are >= 3 per dimension, so the 27
 // neighbour cells are distinct and hold exactly the one image of every
 // partner within the cutoff.
@@ -34,8 +36,6 @@ namespace sx {
 namespace {
 
 constexpr int kBuildBlock = 1024;
-constexpr int kStageMax = 1024;  // partner atoms staged per round (16 KB of LDS)
-constexpr int kHomeMax = 128;    // home atoms per force round
 
 __device__ __forceinline__ int cell_of(double x, double L, double iL, double clen, int nc, double &rel)
 {
@@ -163,64 +163,6 @@ __device__ __forceinline__ bool within_cut(float r2, const CvDesc &cv, const Cel
     return cut_exact(pos, aoff, ai, aj, c.L[0], c.L[1], c.L[2], cv.rcut);
 }
 
-// switching function: the (6, 12) form as a template choice, else the
-// general form of switch_fn
-template <bool S612>
-__device__ __forceinline__ void sw(float r2, const CvDesc &cv, float &s, float &f)
-{
-    if (S612) {
-        const float ir = cv.inv_r0 * cv.inv_r0;
-        const float x2 = r2 * ir, x4 = x2 * x2;
-        const float sv = __builtin_amdgcn_rcpf(fmaf(x4, x2, 1.0f));
-        s = sv;
-        f = -6.0f * x4 * sv * sv * ir;
-    } else {
-        switch_fn(r2, cv, s, f);
-    }
-}
-
-// Four partners j0 + kLpa q (q < 4) of home atom `me` at pi, the kLpa lanes
-// of a lane group over j0: r^2 in FP32 from cell-relative coordinates, the
-// cut decided by within_cut (its exact path behind one wavefront-uniform
-// vote).  A wavefront works on 64 / kLpa home atoms at a time.
-constexpr int kUnroll = 4;
-constexpr int kLpa = 16;             // lanes per home atom
-constexpr int kApw = 64 / kLpa;      // home atoms per wavefront
-struct PairBatch {
-    float dx[kUnroll], dy[kUnroll], dz[kUnroll], r2[kUnroll];
-    bool in[kUnroll];
-};
-
-__device__ __forceinline__ void pair_batch(const float4 &pi, int32_t me, const float4 *s_p, int j0, int m,
-                                           const CvDesc &cv, const CellArgs &c, const PosView &pos, int64_t aoff,
-                                           PairBatch &b)
-{
-    // s_p is padded with far atoms to a multiple of 64 >= m: j0 + kLpa q < 64 ceil(m / 64)
-    const bool self = cv.ga == cv.gb;  // uniform: a group paired with itself skips i == j
-    const float band = 1e-5f * cv.rcut2;
-    bool near = false;
-    int32_t him[kUnroll];
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-        const float4 pj = s_p[j0 + kLpa * q];
-        him[q] = __float_as_int(pj.w);
-        b.dx[q] = pi.x - pj.x;
-        b.dy[q] = pi.y - pj.y;
-        b.dz[q] = pi.z - pj.z;
-        b.r2[q] = fmaf(b.dx[q], b.dx[q], fmaf(b.dy[q], b.dy[q], b.dz[q] * b.dz[q]));
-        const float t = b.r2[q] - cv.rcut2;
-        const bool ok = m > 0 && (!self || him[q] != me);
-        b.in[q] = ok && t < 0.f;
-        near = near || (ok && fabsf(t) <= band);
-    }
-    if (__any(near)) {  // rare: a pair at the edge of the cut somewhere in the wavefront
-#pragma unroll
-        for (int q = 0; q < kUnroll; ++q)
-            if (m > 0 && him[q] >= 0 && (!self || him[q] != me) && fabsf(b.r2[q] - cv.rcut2) <= band)
-                b.in[q] = cut_exact(pos, aoff, me, him[q], c.L[0], c.L[1], c.L[2], cv.rcut);
-    }
-}
-
 __device__ __forceinline__ const CvDesc &cell_cv(const CvSet &cs, int k)
 {
     int c = 0;
@@ -229,22 +171,32 @@ __device__ __forceinline__ const CvDesc &cell_cv(const CvSet &cs, int k)
     return cs.cv[c];
 }
 
-// stage the members of group gp in the 27 cells around `home` into s_p,
-// relative to home's origin: entries [r0, r0 + kStageMax) of the
-// concatenation in neighbour order; returns how many were staged
-__device__ __forceinline__ int stage_partners(const CellArgs &c, int w, int gp, int home, int r0, float4 *s_p,
-                                              int32_t *s_seg, float *s_sh)
+// Stage the members of group gp in the region of column block (cx, cy, z0):
+// the 3 x 3 x (czb + 2) cells around it, slice by slice (z offset -1 .. czb),
+// each slice in (x, y) order, so that the 27 neighbour cells of the block's
+// k-th home cell are the contiguous range s_seg[9 k] .. s_seg[9 (k + 3)].
+// Positions relative to the origin of cell (cx, cy, z0), times sc; entries
+// [r0, r0 + kColStage) of the region, followed by 16 atoms far outside any
+// cut (index -1), so a lane reading four partners 4 apart from any start
+// below the count stays inside.  Returns how many are real.
+constexpr int kCz = 3;            // home cells per column block
+constexpr int kColStage = 1280;   // partner atoms staged per round (20 KB)
+constexpr int kRegMax = 9 * (kCz + 2);
+
+__device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, int cx, int cy, int z0, int czb, int r0,
+                                            float sc, float4 *s_p, int32_t *s_seg, int32_t *s_first, float *s_sh)
 {
     const int32_t *cst = c.cstart + ((int64_t)w * c.G + gp) * (c.ncell + 1);
     const float4 *srt = c.sorted + (int64_t)w * c.gtotal + c.goff[gp];
-    const int hz = home % c.nc[2], hy = (home / c.nc[2]) % c.nc[1], hx = home / (c.nc[1] * c.nc[2]);
-    if (threadIdx.x < 27) {
-        const int t = threadIdx.x;
-        const int ox = t / 9 - 1, oy = (t / 3) % 3 - 1, oz = t % 3 - 1;
-        const int nx = (hx + ox + c.nc[0]) % c.nc[0], ny = (hy + oy + c.nc[1]) % c.nc[1], nz = (hz + oz + c.nc[2]) % c.nc[2];
+    const int nreg = 9 * (czb + 2);
+    for (int t = threadIdx.x; t < nreg; t += blockDim.x) {
+        const int sl = t / 9, xy = t % 9;
+        const int ox = xy / 3 - 1, oy = xy % 3 - 1, oz = sl - 1;
+        const int nx = (cx + ox + c.nc[0]) % c.nc[0], ny = (cy + oy + c.nc[1]) % c.nc[1];
+        const int nz = (z0 + oz + c.nc[2]) % c.nc[2];
         const int nb = (nx * c.nc[1] + ny) * c.nc[2] + nz;
-        s_seg[32 + t] = cst[nb];                   // first member of the neighbour
-        s_seg[t + 1] = cst[nb + 1] - cst[nb];      // its count (prefix below)
+        s_first[t] = cst[nb];
+        s_seg[t + 1] = cst[nb + 1] - cst[nb];
         s_sh[3 * t] = (float)(ox * c.clen[0]);
         s_sh[3 * t + 1] = (float)(oy * c.clen[1]);
         s_sh[3 * t + 2] = (float)(oz * c.clen[2]);
@@ -252,22 +204,23 @@ __device__ __forceinline__ int stage_partners(const CellArgs &c, int w, int gp, 
     if (threadIdx.x == 0) s_seg[0] = 0;
     __syncthreads();
     if (threadIdx.x == 0)
-        for (int t = 1; t <= 27; ++t) s_seg[t] += s_seg[t - 1];
+        for (int t = 1; t <= nreg; ++t) s_seg[t] += s_seg[t - 1];
     __syncthreads();
-    const int total = s_seg[27];
-    const int m = min(kStageMax, total - r0);
-    // padded to a multiple of 64 with atoms far outside any cut (index -1)
-    const int mp = min(kStageMax, (m + 63) & ~63);
+    const int m = min(kColStage, s_seg[nreg] - r0);
+    const int mp = m + 16;  // s_p holds kColStage + 16 entries
     for (int j = threadIdx.x; j < mp; j += blockDim.x) {
         float4 v = make_float4(1e6f, 1e6f, 1e6f, __int_as_float(-1));
         if (j < m) {
             const int e = r0 + j;
-            int t = 0;
-            while (s_seg[t + 1] <= e) ++t;  // at most 26 steps
-            v = srt[s_seg[32 + t] + (e - s_seg[t])];
-            v.x += s_sh[3 * t];
-            v.y += s_sh[3 * t + 1];
-            v.z += s_sh[3 * t + 2];
+            int lo = 0, hi = nreg - 1;  // the cell t with s_seg[t] <= e < s_seg[t + 1]
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_seg[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            v = srt[s_first[lo] + (e - s_seg[lo])];
+            v.x = (v.x + s_sh[3 * lo]) * sc;
+            v.y = (v.y + s_sh[3 * lo + 1]) * sc;
+            v.z = (v.z + s_sh[3 * lo + 2]) * sc;
         }
         s_p[j] = v;
     }
@@ -275,68 +228,166 @@ __device__ __forceinline__ int stage_partners(const CellArgs &c, int w, int gp, 
     return m;
 }
 
-template <bool S612>
-__global__ void __launch_bounds__(kBlock) k_cn_cell(CellArgs c, CvSet cs, PosView pos, int k)
+// One workgroup of 256 threads per (column block, group, walker); four
+// lanes per home atom (the members of the block's cells, contiguous in the
+// sorted order), 64 home atoms per pass.  For every use (CV, partner group)
+// of the group each lane walks every fourth partner of its home cell's
+// contiguous range, four at a time, accumulating in FP32 the switch sum (A
+// side of the CV: the CV value) and the gradient sum_j f(r_ij) (r_i - r_j);
+// the four lanes combine in a fixed butterfly and the gradient is stored per
+// member and use (the VJP reads it).  A group's own CV counts its self pair
+// (r = 0: s = 1 exactly, zero gradient), so the A-side sum drops 1 per atom
+// instead of testing every pair.
+constexpr int kJacBlock = 256;
+constexpr int kLpa = 4;                     // lanes per home atom
+constexpr int kApp = kJacBlock / kLpa;      // home atoms per pass
+constexpr int kStride = 4 * kLpa;           // partners per lane step
+
+// Four partners s_p[j], s_p[j + kLpa], ... of one home atom (o): the cut
+// decision, the switch sum and the gradient sum.  In the (6, 12) form the
+// coordinates are in units of r0 (x^2 = r^2 / r0^2 directly) and the
+// gradient term is x^4 s^2 (r_i - r_j) / r0, the factor -6 / r0 applied
+// once per atom; otherwise plain units and f of switch_fn.  TAIL: partners
+// at or past b1 do not count.
+template <bool S612, bool TAIL>
+__device__ __forceinline__ void pair4(const float4 *s_p, int j, int b1, float3 o, float rc2, float bandc,
+                                      const CvDesc &cv, const CellArgs &c, const PosView &pos, int64_t aoff,
+                                      int32_t me, float &sA, float &gx, float &gy, float &gz)
 {
-    __shared__ float4 s_p[kStageMax];
-    __shared__ int32_t s_seg[64];
-    __shared__ float s_sh[81];
-    __shared__ double s_red[kBlock / 64];
-    const int home = blockIdx.x, w = blockIdx.z;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const CvDesc cv = cell_cv(cs, k);
-    const int32_t *cstA = c.cstart + ((int64_t)w * c.G + cv.ga) * (c.ncell + 1);
-    const float4 *sA = c.sorted + (int64_t)w * c.gtotal + c.goff[cv.ga];
-    const int a0 = cstA[home], a1 = cstA[home + 1];
-    double *out = c.part + ((int64_t)w * c.ncn + k) * c.ncell + home;
-    if (a0 == a1) {  // uniform: an empty home cell
-        if (threadIdx.x == 0) *out = 0.0;
-        return;
-    }
-    const int64_t aoff = c.atom_off[w];
-    float acc[kUnroll] = {0.f, 0.f, 0.f, 0.f};
-    for (int r0 = 0;; r0 += kStageMax) {
-        const int m = stage_partners(c, w, cv.gb, home, r0, s_p, s_seg, s_sh);
-        const int grp = lane / kLpa, gl = lane % kLpa;
-        for (int ib = a0 + wave * kApw; ib < a1; ib += (kBlock / 64) * kApw) {
-            const int i = ib + grp;  // this lane group's home atom
-            const bool live = i < a1;
-            const float4 pi = sA[live ? i : a0];
-            const int32_t me = __float_as_int(pi.w);
-            const int mm = live ? m : 0;
-            for (int j0 = gl; j0 < m; j0 += kLpa * kUnroll) {
-                PairBatch b;
-                pair_batch(pi, me, s_p, j0, mm, cv, c, pos, aoff, b);
+    // t = r^2 - rc^2 decides (inside iff t < 0); partners that do not count
+    // get t = +inf, and within the band the exact decision overwrites t
+    float dx[4], dy[4], dz[4], r2[4], t[4];
 #pragma unroll
-                for (int q = 0; q < kUnroll; ++q) {
-                    float sv, f;
-                    sw<S612>(b.r2[q], cv, sv, f);
-                    acc[q] += b.in[q] ? sv : 0.f;
-                }
-            }
-        }
-        if (r0 + m >= s_seg[27]) break;  // uniform
-        __syncthreads();                 // the next round overwrites s_p
+    for (int q = 0; q < 4; ++q) {
+        const float4 pj = s_p[j + q * kLpa];  // < b1 + kStride <= m + kStride: padded
+        dx[q] = o.x - pj.x;
+        dy[q] = o.y - pj.y;
+        dz[q] = o.z - pj.z;
+        r2[q] = fmaf(dx[q], dx[q], fmaf(dy[q], dy[q], dz[q] * dz[q]));
+        t[q] = r2[q] - rc2;
+        if (TAIL && j + q * kLpa >= b1) t[q] = __builtin_inff();
     }
-    double v = ((double)acc[0] + (double)acc[1]) + ((double)acc[2] + (double)acc[3]);
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) s_red[wave] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = s_red[0];
-        for (int q = 1; q < kBlock / 64; ++q) t += s_red[q];
-        *out = t;
+    const float tmin = fminf(fminf(fabsf(t[0]), fabsf(t[1])), fminf(fabsf(t[2]), fabsf(t[3])));
+    if (tmin <= bandc) {  // rare: the edge of the cut
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (fabsf(t[q]) <= bandc)
+                t[q] = cut_exact(pos, aoff, me, __float_as_int(s_p[j + q * kLpa].w), c.L[0], c.L[1], c.L[2], cv.rcut)
+                           ? -1.0f
+                           : 1.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool in = t[q] < 0.f;
+        float f;
+        if (S612) {
+            const float x4 = r2[q] * r2[q];
+            const float sv = in ? __builtin_amdgcn_rcpf(fmaf(x4, r2[q], 1.0f)) : 0.f;
+            sA += sv;
+            f = x4 * sv * sv;
+        } else {
+            float sv;
+            switch_fn(r2[q], cv, sv, f);
+            sA += in ? sv : 0.f;
+            f = in ? f : 0.f;
+        }
+        gx = fmaf(f, dx[q], gx);
+        gy = fmaf(f, dy[q], gy);
+        gz = fmaf(f, dz[q], gz);
     }
 }
 
+template <bool S612>
+__global__ void __launch_bounds__(kJacBlock) k_cell_jac(CellArgs c, CvSet cs, PosView pos)
+{
+    __shared__ float4 s_p[kColStage + kStride];
+    __shared__ int32_t s_seg[kRegMax + 1], s_first[kRegMax];
+    __shared__ float s_sh[3 * kRegMax];
+    __shared__ double s_red[kJacBlock / 64];
+    const int blk = blockIdx.x, g = blockIdx.y, w = blockIdx.z;
+    const int tid = threadIdx.x, sub = tid & (kLpa - 1), wave = tid >> 6;
+    const int zb = blk % c.nzb, cy = (blk / c.nzb) % c.nc[1], cx = blk / (c.nzb * c.nc[1]);
+    // blocks split the column evenly: nzb blocks of at most kCz cells
+    const int z0 = zb * c.nc[2] / c.nzb, czb = (zb + 1) * c.nc[2] / c.nzb - z0;
+    const int32_t *cst = c.cstart + ((int64_t)w * c.G + g) * (c.ncell + 1);
+    const float4 *sg = c.sorted + (int64_t)w * c.gtotal + c.goff[g];
+    const int cell0 = (cx * c.nc[1] + cy) * c.nc[2] + z0;
+    const int a0 = cst[cell0], a1 = cst[cell0 + czb];
+    const int64_t aoff = c.atom_off[w];
+    const int nreg = 9 * (czb + 2);
+    for (int u = 0; u < c.ninv[g]; ++u) {
+        const CvDesc &cv = cs.cv[c.inv_cv[g][u]];
+        const bool sideA = c.inv_side[g][u] == 0;
+        const float self1 = cv.ga == cv.gb ? 1.0f : 0.0f;
+        float4 *J = c.jac + (int64_t)w * c.jtotal + c.joff[g][u];
+        // coordinate scale, squared cut, its band, and the gradient factor
+        const float sc = S612 ? cv.inv_r0 : 1.0f;
+        const float rc2 = cv.rcut2 * sc * sc, bandc = 1e-5f * rc2, gsc = S612 ? -6.0f * cv.inv_r0 : 1.0f;
+        double ssum = 0.0;  // this lane's switch sums (A side), over its home atoms
+        for (int r0 = 0;; r0 += kColStage) {
+            const int m = stage_column(c, w, c.inv_p[g][u], cx, cy, z0, czb, r0, sc, s_p, s_seg, s_first, s_sh);
+            for (int h0 = a0; h0 + 16 * wave < a1; h0 += kApp) {  // uniform per wavefront
+                const int i = h0 + tid / kLpa;
+                const bool live = i < a1;
+                const float4 pi = sg[live ? i : a0];
+                int k = 0;  // this atom's home cell within the block
+                while (k + 1 < czb && i >= cst[cell0 + k + 1]) ++k;
+                // this atom's partners in the staged window
+                const int b0 = max(0, s_seg[9 * k] - r0), b1 = live ? min(m, s_seg[9 * (k + 3)] - r0) : 0;
+                // home atoms are stored relative to their own cell: the k-th
+                // cell of the block sits k cell edges above the block origin
+                const float3 o = make_float3(pi.x * sc, pi.y * sc, (pi.z + (float)(k * c.clen[2])) * sc);
+                const int32_t me = __float_as_int(pi.w);
+                float sA = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+                int j = b0 + sub;
+                for (; j + 3 * kLpa < b1; j += kStride)
+                    pair4<S612, false>(s_p, j, b1, o, rc2, bandc, cv, c, pos, aoff, me, sA, gx, gy, gz);
+                if (j < b1) pair4<S612, true>(s_p, j, b1, o, rc2, bandc, cv, c, pos, aoff, me, sA, gx, gy, gz);
+#pragma unroll
+                for (int o = 1; o < kLpa; o <<= 1) {
+                    sA += __shfl_xor(sA, o, 64);
+                    gx += __shfl_xor(gx, o, 64);
+                    gy += __shfl_xor(gy, o, 64);
+                    gz += __shfl_xor(gz, o, 64);
+                }
+                if (sub == 0 && live) {
+                    float4 gv = make_float4(gx * gsc, gy * gsc, gz * gsc, 0.f);
+                    if (r0 > 0) {  // later windows add to the earlier ones (same thread)
+                        const float4 pv = J[i];
+                        gv.x += pv.x;
+                        gv.y += pv.y;
+                        gv.z += pv.z;
+                    }
+                    J[i] = gv;
+                    if (sideA) ssum += (double)sA - (r0 == 0 ? (double)self1 : 0.0);
+                }
+            }
+            const bool last = r0 + m >= s_seg[nreg];  // uniform
+            __syncthreads();  // the next window or use restages
+            if (last) break;
+        }
+        if (sideA) {  // the CV's partial over this block: fixed butterfly, then waves in order
+            for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o, 64);
+            if ((tid & 63) == 0) s_red[wave] = ssum;
+            __syncthreads();
+            if (tid == 0) {
+                double t = s_red[0];
+                for (int q = 1; q < kJacBlock / 64; ++q) t += s_red[q];
+                c.part[((int64_t)w * c.ncn + cv.cn) * c.nblk + blk] = t;
+            }
+        }
+    }
+}
+
+// per (walker, CV): the column-block partials of its A side in block order
 __global__ void __launch_bounds__(kBlock) k_cn_cell_fin(CellArgs c, CvSet cs, double *xi)
 {
     __shared__ double s_red[kBlock / 64];
     const int k = blockIdx.x, w = blockIdx.y;
     const CvDesc cv = cell_cv(cs, k);
-    const double *p = c.part + ((int64_t)w * c.ncn + k) * c.ncell;
+    const double *p = c.part + ((int64_t)w * c.ncn + k) * c.nblk;
     double v = 0.0;
-    for (int i = threadIdx.x; i < c.ncell; i += kBlock) v += p[i];
+    for (int i = threadIdx.x; i < c.nblk; i += kBlock) v += p[i];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -347,115 +398,68 @@ __global__ void __launch_bounds__(kBlock) k_cn_cell_fin(CellArgs c, CvSet cs, do
     }
 }
 
-template <bool S612>
-__global__ void __launch_bounds__(kBlock) k_cell_vjp(CellArgs c, CvSet cs, PosView pos, const double *coef,
-                                                      double sign, ForceView F)
+// VJP from the stored gradients: one lane per member of each group (sorted
+// order), out += sign sum over the group's uses of coef[cv] scale_cv J; the
+// groups are identical or disjoint, so every atom has one writer.
+__global__ void __launch_bounds__(kBlock) k_cell_gather(CellArgs c, CvSet cs, const double *coef, double sign,
+                                                         ForceView F)
 {
-    __shared__ float4 s_p[kStageMax];
-    __shared__ int32_t s_seg[64];
-    __shared__ float s_sh[81];
-    __shared__ double s_f[kHomeMax][3];
-    const int home = blockIdx.x, g = blockIdx.y, w = blockIdx.z;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int32_t *cst = c.cstart + ((int64_t)w * c.G + g) * (c.ncell + 1);
-    const float4 *sg = c.sorted + (int64_t)w * c.gtotal + c.goff[g];
-    const int a0 = cst[home], a1 = cst[home + 1];
-    if (a0 == a1) return;  // uniform
-    const int64_t aoff = c.atom_off[w];
-    for (int h0 = a0; h0 < a1; h0 += kHomeMax) {
-        const int h1 = min(a1, h0 + kHomeMax);
-        for (int i = threadIdx.x; i < kHomeMax; i += kBlock) s_f[i][0] = s_f[i][1] = s_f[i][2] = 0.0;
-        __syncthreads();
-        for (int u = 0; u < c.ninv[g]; ++u) {
-            const CvDesc &cv = cs.cv[c.inv_cv[g][u]];
-            const double cf = sign * coef[(int64_t)w * cs.D + cv.d] * (double)cv.scale;
-            for (int r0 = 0;; r0 += kStageMax) {
-                const int m = stage_partners(c, w, c.inv_p[g][u], home, r0, s_p, s_seg, s_sh);
-                const int grp = lane / kLpa, gl = lane % kLpa;
-                for (int ib = h0 + wave * kApw; ib < h1; ib += (kBlock / 64) * kApw) {
-                    const int i = ib + grp;  // this lane group's home atom
-                    const bool live = i < h1;
-                    const float4 pi = sg[live ? i : h0];
-                    const int32_t me = __float_as_int(pi.w);
-                    const int mm = live ? m : 0;
-                    float gx = 0.f, gy = 0.f, gz = 0.f;
-                    for (int j0 = gl; j0 < m; j0 += kLpa * kUnroll) {
-                        PairBatch b;
-                        pair_batch(pi, me, s_p, j0, mm, cv, c, pos, aoff, b);
-#pragma unroll
-                        for (int q = 0; q < kUnroll; ++q) {
-                            float sv, f;
-                            sw<S612>(b.r2[q], cv, sv, f);
-                            f = b.in[q] ? f : 0.f;
-                            gx = fmaf(f, b.dx[q], gx);
-                            gy = fmaf(f, b.dy[q], gy);
-                            gz = fmaf(f, b.dz[q], gz);
-                        }
-                    }
-                    // butterfly over the lane group (FP32: error ~ log2(16) ulp of the terms)
-                    for (int o = kLpa / 2; o > 0; o >>= 1) {
-                        gx += __shfl_xor(gx, o, 64);
-                        gy += __shfl_xor(gy, o, 64);
-                        gz += __shfl_xor(gz, o, 64);
-                    }
-                    if (gl == 0 && live) {  // one lane group per home atom: the only writer
-                        s_f[i - h0][0] += cf * (double)gx;
-                        s_f[i - h0][1] += cf * (double)gy;
-                        s_f[i - h0][2] += cf * (double)gz;
-                    }
-                }
-                if (r0 + m >= s_seg[27]) break;  // uniform
-                __syncthreads();
-            }
-            __syncthreads();  // the next use restages s_p and its segments
-        }
-        for (int i = h0 + (int)threadIdx.x; i < h1; i += kBlock) {
-            const int32_t atom = __float_as_int(sg[i].w);
-            float *f = F.ptr + (aoff + atom) * F.sa;
-            f[0] += (float)s_f[i - h0][0];
-            f[F.sk] += (float)s_f[i - h0][1];
-            f[2 * F.sk] += (float)s_f[i - h0][2];
-        }
-        __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = blockIdx.y;
+    if (e >= c.gtotal) return;
+    int g = 0;
+    while (g + 1 < c.G && e >= c.goff[g + 1]) ++g;
+    const int64_t i = e - c.goff[g];
+    const float4 me = c.sorted[(int64_t)w * c.gtotal + e];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int u = 0; u < c.ninv[g]; ++u) {
+        const CvDesc &cv = cs.cv[c.inv_cv[g][u]];
+        const double cf = sign * coef[(int64_t)w * cs.D + cv.d] * (double)cv.scale;
+        const float4 j = c.jac[(int64_t)w * c.jtotal + c.joff[g][u] + i];
+        fx += cf * (double)j.x;
+        fy += cf * (double)j.y;
+        fz += cf * (double)j.z;
     }
+    float *f = F.ptr + (c.atom_off[w] + __float_as_int(me.w)) * F.sa;
+    f[0] += (float)fx;
+    f[F.sk] += (float)fy;
+    f[2 * F.sk] += (float)fz;
 }
 
 }  // namespace
 
-hipError_t launch_cell_cv(const CellArgs &c, const CvSet &cs, const PosView &pos, double *xi, hipStream_t s)
+hipError_t launch_cell_cv(const CellArgs &c, const CvSet &cs, const PosView &pos, double *xi, hipStream_t s, int which)
 {
     if (c.ncn == 0) return hipSuccess;
-    if (pos.f64)
-        hipLaunchKernelGGL(k_cell_build<double>, dim3(c.W * c.G), dim3(kBuildBlock), 0, s, c, pos);
-    else
-        hipLaunchKernelGGL(k_cell_build<float>, dim3(c.W * c.G), dim3(kBuildBlock), 0, s, c, pos);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    for (int d = 0; d < cs.ncv; ++d) {  // one launch per CV: its switching form is a template choice
-        const CvDesc &cv = cs.cv[d];
-        if (cv.kind != CV_COORD_CELL) continue;
-        if (cv.n == 6 && cv.m == 12)
-            hipLaunchKernelGGL(k_cn_cell<true>, dim3(c.ncell, 1, c.W), dim3(kBlock), 0, s, c, cs, pos, cv.cn);
+    hipError_t e = hipSuccess;
+    if (which & 1) {
+        if (pos.f64)
+            hipLaunchKernelGGL(k_cell_build<double>, dim3(c.W * c.G), dim3(kBuildBlock), 0, s, c, pos);
         else
-            hipLaunchKernelGGL(k_cn_cell<false>, dim3(c.ncell, 1, c.W), dim3(kBlock), 0, s, c, cs, pos, cv.cn);
+            hipLaunchKernelGGL(k_cell_build<float>, dim3(c.W * c.G), dim3(kBuildBlock), 0, s, c, pos);
         e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess || !(which & 2)) return e;
     }
+    bool all612 = true;
+    for (int d = 0; d < cs.ncv; ++d)
+        if (cs.cv[d].kind == CV_COORD_CELL) all612 = all612 && cs.cv[d].n == 6 && cs.cv[d].m == 12;
+    const dim3 grid(c.nblk, c.G, c.W);
+    if (all612)
+        hipLaunchKernelGGL(k_cell_jac<true>, grid, dim3(kJacBlock), 0, s, c, cs, pos);
+    else
+        hipLaunchKernelGGL(k_cell_jac<false>, grid, dim3(kJacBlock), 0, s, c, cs, pos);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cn_cell_fin, dim3(c.ncn, c.W), dim3(kBlock), 0, s, c, cs, xi);
     return hipGetLastError();
 }
 
-hipError_t launch_cell_vjp(const CellArgs &c, const CvSet &cs, const PosView &pos, const double *coef, double sign,
+hipError_t launch_cell_vjp(const CellArgs &c, const CvSet &cs, const PosView &, const double *coef, double sign,
                            ForceView out, hipStream_t s)
 {
     if (c.ncn == 0) return hipSuccess;
-    bool all612 = true;
-    for (int d = 0; d < cs.ncv; ++d)
-        if (cs.cv[d].kind == CV_COORD_CELL) all612 = all612 && cs.cv[d].n == 6 && cs.cv[d].m == 12;
-    if (all612)
-        hipLaunchKernelGGL(k_cell_vjp<true>, dim3(c.ncell, c.G, c.W), dim3(kBlock), 0, s, c, cs, pos, coef, sign, out);
-    else
-        hipLaunchKernelGGL(k_cell_vjp<false>, dim3(c.ncell, c.G, c.W), dim3(kBlock), 0, s, c, cs, pos, coef, sign, out);
+    hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((c.gtotal + kBlock - 1) / kBlock), c.W), dim3(kBlock), 0, s, c,
+                       cs, coef, sign, out);
     return hipGetLastError();
 }
 

@@ -68,7 +68,7 @@ struct Plan {
     // cell lists of coordination numbers
     CellArgs cell{};
     std::vector<int32_t> gatoms;
-    Sub w_gatoms, w_cid, w_cstart, w_sorted, w_cpart;
+    Sub w_gatoms, w_cid, w_cstart, w_sorted, w_cpart, w_jac;
     // surrogate network (state: FP32 master weights, bf16 copies, Adam
     // moments, certified cells; workspace: samples, training tangents)
     int32_t sgP = 0;
@@ -301,10 +301,22 @@ sx_status make_plan(sx_ctx *c)
                 if (!cellcv[d]) continue;
                 const int ga = gid_a[d], gb = gid_b[d];
                 cl.inv_cv[ga][cl.ninv[ga]] = d;
+                cl.inv_side[ga][cl.ninv[ga]] = 0;
                 cl.inv_p[ga][cl.ninv[ga]++] = gb;
                 cl.inv_cv[gb][cl.ninv[gb]] = d;
+                cl.inv_side[gb][cl.ninv[gb]] = 1;
                 cl.inv_p[gb][cl.ninv[gb]++] = ga;
             }
+            // column blocks of 3 cells in z; one gradient per (member, use)
+            cl.cz = 3;
+            cl.nzb = (cl.nc[2] + cl.cz - 1) / cl.cz;
+            cl.nblk = cl.nc[0] * cl.nc[1] * cl.nzb;
+            cl.jtotal = 0;
+            for (int g = 0; g < cl.G; ++g)
+                for (int u = 0; u < cl.ninv[g]; ++u) {
+                    cl.joff[g][u] = cl.jtotal;
+                    cl.jtotal += cl.goff[g + 1] - cl.goff[g];
+                }
         }
     }
     int64_t part = 0;
@@ -480,7 +492,8 @@ sx_status make_plan(sx_ctx *c)
         p.w_cid = lw.take(sizeof(int32_t) * W * gt);
         p.w_cstart = lw.take(sizeof(int32_t) * W * cl.G * (cl.ncell + 1));
         p.w_sorted = lw.take(16 * W * gt);
-        p.w_cpart = lw.take(sizeof(double) * W * cl.ncn * cl.ncell);
+        p.w_cpart = lw.take(sizeof(double) * W * cl.ncn * cl.nblk);
+        p.w_jac = lw.take(16 * W * (size_t)cl.jtotal);
     }
     if (c->sg_H) {
         const size_t N = (size_t)p.sgN, B = (size_t)c->sg_max_batch, H = (size_t)c->sg_H, D = (size_t)p.D;
@@ -738,6 +751,7 @@ CellArgs cell_args(sx_ctx *c)
     a.cstart = at<int32_t>(c->ws, p.w_cstart);
     a.sorted = at<float4>(c->ws, p.w_sorted);
     a.part = at<double>(c->ws, p.w_cpart);
+    a.jac = at<float4>(c->ws, p.w_jac);
     return a;
 }
 
@@ -1961,7 +1975,7 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
 }
 
 sx_status sx_time_cell(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
-                       float *ms_cv, float *ms_vjp)
+                       float *ms_sort, float *ms_pairs, float *ms_vjp)
 {
     if (sx_status s = require_bound(ctx)) return s;
     SX_GUARD_BEGIN
@@ -1969,27 +1983,29 @@ sx_status sx_time_cell(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layo
     if (!p.cell.ncn) return fail(ctx, SX_ESTATE, "no cell-list coordination numbers in this plan");
     PosView pv;
     if (!pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
-    if (reps < 1 || !ms_cv || !ms_vjp) return fail(ctx, SX_EINVAL, "reps must be >= 1, outputs non-NULL");
+    if (reps < 1 || !ms_sort || !ms_pairs || !ms_vjp) return fail(ctx, SX_EINVAL, "reps must be >= 1, outputs non-NULL");
     const CellArgs ca = cell_args(ctx);
     double *xi = at<double>(ctx->ws, p.w_xi), *coef = at<double>(ctx->ws, p.w_dV);
-    hipEvent_t e[3];
+    hipEvent_t e[4];
     for (auto &x : e)
         if (hipEventCreate(&x) != hipSuccess) return fail(ctx, SX_EDEVICE, "events");
-    hipError_t err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream);  // warm, and cells for the VJP
+    hipError_t err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream);  // warm
     if (err == hipSuccess) err = hipEventRecord(e[0], ctx->stream);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream, 1);
     if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream, 2);
+    if (err == hipSuccess) err = hipEventRecord(e[2], ctx->stream);
     for (int r = 0; r < reps && err == hipSuccess && forces; ++r)
         err = launch_cell_vjp(ca, p.cs, pv, coef, -1.0, force_view(ctx, forces, layout), ctx->stream);
-    if (err == hipSuccess) err = hipEventRecord(e[2], ctx->stream);
-    if (err == hipSuccess) err = hipEventSynchronize(e[2]);
-    float a = 0, b = 0;
-    if (err == hipSuccess) err = hipEventElapsedTime(&a, e[0], e[1]);
-    if (err == hipSuccess) err = hipEventElapsedTime(&b, e[1], e[2]);
+    if (err == hipSuccess) err = hipEventRecord(e[3], ctx->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e[3]);
+    float t[3] = {0, 0, 0};
+    for (int k = 0; k < 3 && err == hipSuccess; ++k) err = hipEventElapsedTime(&t[k], e[k], e[k + 1]);
     for (auto &x : e) hipEventDestroy(x);
     if (err != hipSuccess) return hip_fail(ctx, err, "cell timing");
-    *ms_cv = a / reps;
-    *ms_vjp = forces ? b / reps : 0.f;
+    *ms_sort = t[0] / reps;
+    *ms_pairs = t[1] / reps;
+    *ms_vjp = forces ? t[2] / reps : 0.f;
     return SX_OK;
     SX_GUARD_END
 }

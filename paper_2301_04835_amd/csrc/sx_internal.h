@@ -221,10 +221,15 @@ struct CellArgs {
     int32_t *cid;                      // W x gtotal: cell of each group member
     int32_t *cstart;                   // W x G x (ncell + 1): members of cell c
     float4 *sorted;                    // W x gtotal: (x, y, z) relative to the cell origin, atom
-    double *part;                      // W x ncn x ncell: forward partial sums
+    double *part;                      // W x ncn x nblk: coordination partial sums per column block
+    float4 *jac;                       // W x jtotal: per (group, use) gradient of each member, sorted order
+    int64_t jtotal;                    // sum over groups of members x uses
+    int64_t joff[kMaxGroups][kMaxInv]; // first entry of (group, use) within a walker's jac
+    int32_t cz, nzb, nblk;             // column blocks: cz cells in z, nzb per column, nblk in all
     // uses of each group: the CV (index into CvSet::cv) and its partner group
     int32_t ninv[kMaxGroups];
     int32_t inv_cv[kMaxGroups][kMaxInv], inv_p[kMaxGroups][kMaxInv];  // CV index in the set, partner group
+    int32_t inv_side[kMaxGroups][kMaxInv];                              // 0: the group is the CV's A side
 };
 
 // Surrogate network (bf16 copies as raw 16-bit words in host code).
@@ -256,8 +261,10 @@ hipError_t launch_abf(const AbfArgs &a, hipStream_t s);
 constexpr int32_t kSharedTarget = 2048;
 void shared_split(int64_t cap, int64_t nq, int32_t &chunk, int32_t &nchunk, int32_t target = kSharedTarget);
 hipError_t launch_hill_shared(const SharedArgs &a, hipStream_t s);
-// cell lists, then every cell-list coordination number's value into xi
-hipError_t launch_cell_cv(const CellArgs &c, const CvSet &cs, const PosView &pos, double *xi, hipStream_t s);
+// cell lists (which & 1), then every cell-list coordination number's value
+// into xi and the gradients of its members (which & 2)
+hipError_t launch_cell_cv(const CellArgs &c, const CvSet &cs, const PosView &pos, double *xi, hipStream_t s,
+                          int which = 3);
 // out += sign * sum_d coef[w][d] dxi_d/dr for the cell-list coordination
 // numbers (pair recompute, one writer per atom); needs the cell lists of the
 // same positions (launch_cell_cv first)
