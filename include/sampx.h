@@ -114,11 +114,13 @@ sx_status sx_add_cv_coordination(sx_ctx *ctx, const int32_t *a, int32_t na, cons
  * direction.  Default: open.  Before sx_bind. */
 sx_status sx_set_box(sx_ctx *ctx, const double L[3]);
 /* Coordination numbers with a hard cut (rcut > 0) in a periodic box at
- * least 3 rcut wide can be evaluated through cell lists (cells of edge >=
- * the largest such cut, 3 to 16 per dimension): each step sorts the groups'
- * members into cells (stable, so every sum has a fixed order), sums pairs
- * over the 27 neighbour cells, and computes their forces by recomputing the
- * pairs (a vector-Jacobian product; their Jacobian is never stored, so it is
+ * least 3 rcut wide can be evaluated through cell lists (in x and y cells of
+ * edge >= the largest such cut, 3 to 16 per dimension; in z such cells cut
+ * into 4, 2 or 1 sub-cells, at most 4096 cells in all): each step sorts the
+ * groups' members into cells (stable, so every sum has a fixed order), sums
+ * pairs over the neighbour cells in one pass that also keeps each member's
+ * gradient per (CV, side), and computes forces as a vector-Jacobian product
+ * from those gradients (the per-pair Jacobian is never stored, so it is
  * absent from sx_eval_cv's jac_out and sx_jac_slots).  mode: -1 never; 0
  * (default) when |A| |B| >= 2^22; 1 whenever the box allows.  The groups of
  * all such CVs must be identical or disjoint (mode 1: SX_EINVAL otherwise;

@@ -10,25 +10,26 @@
 //                  a cell), so every later sum runs in a fixed order; each
 //                  member is stored as (x, y, z) relative to its cell's
 //                  origin (float, ~6e-8 nm) and its atom index.
-//   k_cell_jac     one wavefront per (walker, group, column block of 3
-//                  cells in z): the partner group's members in the 3 x 3 x 5
-//                  cells around the block are staged in LDS relative to the
-//                  block's origin (a cell's offset is its cell step times the
-//                  cell edge, periodic wrap included), slice by slice, so each
-//                  home cell's 27 neighbours form one contiguous range; each
-//                  lane owns one home atom and walks that range four partners
-//                  at a time: FP32 pair terms, the switch sum (the CV value,
-//                  on the A side) and the gradient sum_j f(r_ij)(r_i - r_j)
-//                  of each (CV, side) use, stored per member (no atomics,
-//                  fixed order).
+//   k_cell_jac     one workgroup per (walker, group, column block of cells
+//                  in z): the partner group's members in the cells around
+//                  the block are staged in LDS relative to the block's
+//                  origin (a cell's offset is its cell step times the cell
+//                  edge, periodic wrap included), slice by slice, so each
+//                  home cell's neighbours form one contiguous range; four
+//                  lanes own one home atom and walk that range: FP32 pair
+//                  terms, the switch sum (the CV value, on the A side) and
+//                  the gradient sum_j f(r_ij)(r_i - r_j) of each (CV, side)
+//                  use, stored per member (no atomics, fixed order).
 //   k_cn_cell_fin  per (walker, CV): the column-block partials in order.
 //   k_cell_gather  the vector-Jacobian product from the stored gradients,
 //                  one lane per member (groups identical or disjoint: one
 //                  writer per atom).
 
-// Cells have edge >= the cutoff and there are >= 3 per dimension, so the 27
-// neighbour cells are distinct and hold exactly the one image of every
-// partner within the cutoff.
+// In x and y cells have edge >= the cutoff and there are >= 3 of them; in z
+// there are rz sub-cells per such cell (>= 3 rz in all), so the 3 x 3 x
+// (2 rz + 1) neighbour cells of a cell are distinct and hold exactly the one
+// image of every partner within the cutoff.  The sub-cells shrink the
+// partners a home atom visits from 27 cut-length cubes to 9 (2 rz + 1) / rz.
 #include "sx_internal.h"
 #include "dev_cv.h"
 
@@ -49,7 +50,7 @@ __device__ __forceinline__ int cell_of(double x, double L, double iL, double cle
 template <typename T>
 __global__ void __launch_bounds__(kBuildBlock) k_cell_build(CellArgs c, PosView pos)
 {
-    __shared__ int32_t s_off[kCellMax * kCellMax * kCellMax];
+    __shared__ int32_t s_off[kCellTotal];
     __shared__ int32_t s_tot[kBuildBlock];
     const int w = blockIdx.x / c.G, g = blockIdx.x % c.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -172,26 +173,30 @@ __device__ __forceinline__ const CvDesc &cell_cv(const CvSet &cs, int k)
 }
 
 // Stage the members of group gp in the region of column block (cx, cy, z0):
-// the 3 x 3 x (czb + 2) cells around it, slice by slice (z offset -1 .. czb),
-// each slice in (x, y) order, so that the 27 neighbour cells of the block's
-// k-th home cell are the contiguous range s_seg[9 k] .. s_seg[9 (k + 3)].
-// Positions relative to the origin of cell (cx, cy, z0), times sc; entries
-// [r0, r0 + kColStage) of the region, followed by 16 atoms far outside any
-// cut (index -1), so a lane reading four partners 4 apart from any start
-// below the count stays inside.  Returns how many are real.
-constexpr int kCz = 3;            // home cells per column block
-constexpr int kColStage = 1280;   // partner atoms staged per round (20 KB)
-constexpr int kRegMax = 9 * (kCz + 2);
+// the 3 x 3 x (czb + 2 rz) cells around it, slice by slice (z offset -rz ..
+// czb + rz - 1), each slice in (x, y) order, so that the neighbour cells of
+// the block's k-th home cell (z offsets -rz .. rz around it) are the
+// contiguous range s_seg[9 k] .. s_seg[9 (k + 2 rz + 1)].  Positions
+// relative to the origin of cell (cx, cy, z0), times sc; entries
+// [r0, r0 + kColStage) of the region, followed by kStride atoms far outside
+// any cut (index -1), so a lane reading four partners kLpa apart from any
+// start below the count stays inside.  Returns how many are real.
+constexpr int kJacBlock = 256;
+constexpr int kLpa = 8;                     // lanes per home atom
+constexpr int kApp = kJacBlock / kLpa;      // home atoms per pass
+constexpr int kStride = 4 * kLpa;           // partners per lane step
+constexpr int kColStage = 1280;             // partner atoms staged per round (20 KB)
+constexpr int kRegMax = 9 * (kCzMax + 2 * kZReach);
 
 __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, int cx, int cy, int z0, int czb, int r0,
                                             float sc, float4 *s_p, int32_t *s_seg, int32_t *s_first, float *s_sh)
 {
     const int32_t *cst = c.cstart + ((int64_t)w * c.G + gp) * (c.ncell + 1);
     const float4 *srt = c.sorted + (int64_t)w * c.gtotal + c.goff[gp];
-    const int nreg = 9 * (czb + 2);
+    const int nreg = 9 * (czb + 2 * c.rz);
     for (int t = threadIdx.x; t < nreg; t += blockDim.x) {
         const int sl = t / 9, xy = t % 9;
-        const int ox = xy / 3 - 1, oy = xy % 3 - 1, oz = sl - 1;
+        const int ox = xy / 3 - 1, oy = xy % 3 - 1, oz = sl - c.rz;
         const int nx = (cx + ox + c.nc[0]) % c.nc[0], ny = (cy + oy + c.nc[1]) % c.nc[1];
         const int nz = (z0 + oz + c.nc[2]) % c.nc[2];
         const int nb = (nx * c.nc[1] + ny) * c.nc[2] + nz;
@@ -207,7 +212,7 @@ __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, in
         for (int t = 1; t <= nreg; ++t) s_seg[t] += s_seg[t - 1];
     __syncthreads();
     const int m = min(kColStage, s_seg[nreg] - r0);
-    const int mp = m + 16;  // s_p holds kColStage + 16 entries
+    const int mp = m + kStride;  // s_p holds kColStage + kStride entries
     for (int j = threadIdx.x; j < mp; j += blockDim.x) {
         float4 v = make_float4(1e6f, 1e6f, 1e6f, __int_as_float(-1));
         if (j < m) {
@@ -228,21 +233,16 @@ __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, in
     return m;
 }
 
-// One workgroup of 256 threads per (column block, group, walker); four
+// One workgroup of 256 threads per (column block, group, walker); kLpa
 // lanes per home atom (the members of the block's cells, contiguous in the
-// sorted order), 64 home atoms per pass.  For every use (CV, partner group)
-// of the group each lane walks every fourth partner of its home cell's
-// contiguous range, four at a time, accumulating in FP32 the switch sum (A
+// sorted order), kApp home atoms per pass.  For every use (CV, partner
+// group) of the group each lane walks every kLpa-th partner of its home
+// cell's contiguous range, four at a time, accumulating in FP32 the switch sum (A
 // side of the CV: the CV value) and the gradient sum_j f(r_ij) (r_i - r_j);
-// the four lanes combine in a fixed butterfly and the gradient is stored per
+// the atom's lanes combine in a fixed butterfly and the gradient is stored per
 // member and use (the VJP reads it).  A group's own CV counts its self pair
 // (r = 0: s = 1 exactly, zero gradient), so the A-side sum drops 1 per atom
 // instead of testing every pair.
-constexpr int kJacBlock = 256;
-constexpr int kLpa = 4;                     // lanes per home atom
-constexpr int kApp = kJacBlock / kLpa;      // home atoms per pass
-constexpr int kStride = 4 * kLpa;           // partners per lane step
-
 // Four partners s_p[j], s_p[j + kLpa], ... of one home atom (o): the cut
 // decision, the switch sum and the gradient sum.  In the (6, 12) form the
 // coordinates are in units of r0 (x^2 = r^2 / r0^2 directly) and the
@@ -298,23 +298,26 @@ __device__ __forceinline__ void pair4(const float4 *s_p, int j, int b1, float3 o
 }
 
 template <bool S612>
-__global__ void __launch_bounds__(kJacBlock) k_cell_jac(CellArgs c, CvSet cs, PosView pos)
+__global__ void __launch_bounds__(kJacBlock, 5) k_cell_jac(CellArgs c, CvSet cs, PosView pos)
 {
     __shared__ float4 s_p[kColStage + kStride];
     __shared__ int32_t s_seg[kRegMax + 1], s_first[kRegMax];
     __shared__ float s_sh[3 * kRegMax];
     __shared__ double s_red[kJacBlock / 64];
+    __shared__ int32_t s_home[kCzMax + 1];  // sorted position of the block's home cells
     const int blk = blockIdx.x, g = blockIdx.y, w = blockIdx.z;
     const int tid = threadIdx.x, sub = tid & (kLpa - 1), wave = tid >> 6;
     const int zb = blk % c.nzb, cy = (blk / c.nzb) % c.nc[1], cx = blk / (c.nzb * c.nc[1]);
-    // blocks split the column evenly: nzb blocks of at most kCz cells
+    // blocks split the column evenly: nzb blocks of at most kCzMax cells
     const int z0 = zb * c.nc[2] / c.nzb, czb = (zb + 1) * c.nc[2] / c.nzb - z0;
     const int32_t *cst = c.cstart + ((int64_t)w * c.G + g) * (c.ncell + 1);
     const float4 *sg = c.sorted + (int64_t)w * c.gtotal + c.goff[g];
     const int cell0 = (cx * c.nc[1] + cy) * c.nc[2] + z0;
-    const int a0 = cst[cell0], a1 = cst[cell0 + czb];
+    if (tid <= czb) s_home[tid] = cst[cell0 + tid];
+    __syncthreads();
+    const int a0 = s_home[0], a1 = s_home[czb];
     const int64_t aoff = c.atom_off[w];
-    const int nreg = 9 * (czb + 2);
+    const int nreg = 9 * (czb + 2 * c.rz), span = 9 * (2 * c.rz + 1);
     for (int u = 0; u < c.ninv[g]; ++u) {
         const CvDesc &cv = cs.cv[c.inv_cv[g][u]];
         const bool sideA = c.inv_side[g][u] == 0;
@@ -326,14 +329,14 @@ __global__ void __launch_bounds__(kJacBlock) k_cell_jac(CellArgs c, CvSet cs, Po
         double ssum = 0.0;  // this lane's switch sums (A side), over its home atoms
         for (int r0 = 0;; r0 += kColStage) {
             const int m = stage_column(c, w, c.inv_p[g][u], cx, cy, z0, czb, r0, sc, s_p, s_seg, s_first, s_sh);
-            for (int h0 = a0; h0 + 16 * wave < a1; h0 += kApp) {  // uniform per wavefront
+            for (int h0 = a0; h0 + (64 / kLpa) * wave < a1; h0 += kApp) {  // uniform per wavefront
                 const int i = h0 + tid / kLpa;
                 const bool live = i < a1;
                 const float4 pi = sg[live ? i : a0];
                 int k = 0;  // this atom's home cell within the block
-                while (k + 1 < czb && i >= cst[cell0 + k + 1]) ++k;
+                while (k + 1 < czb && i >= s_home[k + 1]) ++k;
                 // this atom's partners in the staged window
-                const int b0 = max(0, s_seg[9 * k] - r0), b1 = live ? min(m, s_seg[9 * (k + 3)] - r0) : 0;
+                const int b0 = max(0, s_seg[9 * k] - r0), b1 = live ? min(m, s_seg[9 * k + span] - r0) : 0;
                 // home atoms are stored relative to their own cell: the k-th
                 // cell of the block sits k cell edges above the block origin
                 const float3 o = make_float3(pi.x * sc, pi.y * sc, (pi.z + (float)(k * c.clen[2])) * sc);
@@ -400,13 +403,18 @@ __global__ void __launch_bounds__(kBlock) k_cn_cell_fin(CellArgs c, CvSet cs, do
 
 // VJP from the stored gradients: one lane per member of each group (sorted
 // order), out += sign sum over the group's uses of coef[cv] scale_cv J; the
-// groups are identical or disjoint, so every atom has one writer.
+// groups are identical or disjoint, so every atom has one writer.  The force
+// writes of a walker go to its atoms in cell order, so all blocks of one
+// walker run on one XCD (blocks are dealt to the 8 XCDs in turn): block b
+// serves walker 8 (k / nch) + b % 8, chunk k % nch, k = b / 8, and each force
+// line passes through one L2.
 __global__ void __launch_bounds__(kBlock) k_cell_gather(CellArgs c, CvSet cs, const double *coef, double sign,
-                                                         ForceView F)
+                                                         ForceView F, int32_t nch)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int w = blockIdx.y;
-    if (e >= c.gtotal) return;
+    const int k = blockIdx.x / 8;
+    const int w = (k / nch) * 8 + (int)(blockIdx.x % 8);
+    const int64_t e = (int64_t)(k % nch) * blockDim.x + threadIdx.x;
+    if (w >= c.W || e >= c.gtotal) return;
     int g = 0;
     while (g + 1 < c.G && e >= c.goff[g + 1]) ++g;
     const int64_t i = e - c.goff[g];
@@ -458,8 +466,10 @@ hipError_t launch_cell_vjp(const CellArgs &c, const CvSet &cs, const PosView &, 
                            ForceView out, hipStream_t s)
 {
     if (c.ncn == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((c.gtotal + kBlock - 1) / kBlock), c.W), dim3(kBlock), 0, s, c,
-                       cs, coef, sign, out);
+    const int32_t nch = (int32_t)((c.gtotal + kBlock - 1) / kBlock);
+    const int64_t nb = (int64_t)nch * ((c.W + 7) / 8) * 8;
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)nb), dim3(kBlock), 0, s, c, cs, coef, sign, out, nch);
     return hipGetLastError();
 }
 

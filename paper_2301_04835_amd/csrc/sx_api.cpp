@@ -283,14 +283,18 @@ sx_status make_plan(sx_ctx *c)
         }
         if (!groups.empty()) {
             cl.G = (int32_t)groups.size();
-            cl.ncell = 1;
             for (int k = 0; k < 3; ++k) {
                 cl.nc[k] = std::min(kCellMax, (int)std::floor(c->box[k] / rmax));
                 cl.L[k] = c->box[k];
                 cl.inv_L[k] = 1.0 / c->box[k];
-                cl.clen[k] = c->box[k] / cl.nc[k];
-                cl.ncell *= cl.nc[k];
             }
+            // z sub-cells: a home cell's partners span (2 rz + 1) / rz cut
+            // lengths in z instead of 3
+            cl.rz = kZReach;
+            while (cl.rz > 1 && cl.nc[0] * cl.nc[1] * cl.nc[2] * cl.rz > kCellTotal) cl.rz /= 2;
+            cl.nc[2] *= cl.rz;
+            cl.ncell = cl.nc[0] * cl.nc[1] * cl.nc[2];
+            for (int k = 0; k < 3; ++k) cl.clen[k] = c->box[k] / cl.nc[k];
             cl.goff[0] = 0;
             for (int g = 0; g < cl.G; ++g) {
                 for (int32_t i : groups[g]) p.gatoms.push_back(i);
@@ -307,9 +311,10 @@ sx_status make_plan(sx_ctx *c)
                 cl.inv_side[gb][cl.ninv[gb]] = 1;
                 cl.inv_p[gb][cl.ninv[gb]++] = ga;
             }
-            // column blocks of 3 cells in z; one gradient per (member, use)
-            cl.cz = 3;
-            cl.nzb = (cl.nc[2] + cl.cz - 1) / cl.cz;
+            // column blocks of about 3 rz cells in z (at most 3 rz * 3 / 2);
+            // one gradient per (member, use)
+            cl.nzb = std::max(1, (2 * cl.nc[2] + 3 * cl.rz) / (6 * cl.rz));
+            if ((cl.nc[2] + cl.nzb - 1) / cl.nzb > kCzMax) return fail(c, SX_EINVAL, "cell column block too tall");
             cl.nblk = cl.nc[0] * cl.nc[1] * cl.nzb;
             cl.jtotal = 0;
             for (int g = 0; g < cl.G; ++g)

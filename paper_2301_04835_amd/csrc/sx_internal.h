@@ -205,14 +205,20 @@ struct MlpStep {
     double *xi_ws;
 };
 
-// Cell lists of coordination-number groups (orthorhombic periodic box,
-// cells of edge >= the cutoff, at least 3 per dimension, at most 16).
+// Cell lists of coordination-number groups (orthorhombic periodic box): in x
+// and y cells of edge >= the cutoff, 3 to 16 of them; in z each such cell is
+// cut into rz = 4, 2 or 1 sub-cells (the largest that keeps the total within
+// kCellTotal), so partners within the cut lie within rz cells in z.
 constexpr int kCellMax = 16;
+constexpr int kCellTotal = 4096;
+constexpr int kZReach = 4;     // largest rz
+constexpr int kCzMax = 18;     // home cells (in z) of one column block
 constexpr int kMaxGroups = 8;  // distinct groups of the cell-list CVs
 constexpr int kMaxInv = 8;     // (CV, side) uses of one group
 struct CellArgs {
     int32_t W, G, ncn;                 // walkers, distinct groups, cell-list CVs
     int32_t nc[3], ncell;              // cells per dimension, total
+    int32_t rz;                        // reach in z, in cells
     double L[3], inv_L[3], clen[3];    // box edges, cell edges
     const int64_t *atom_off;           // W + 1
     const int32_t *gatoms;             // walker-relative atoms of all groups, group after group
@@ -225,7 +231,7 @@ struct CellArgs {
     float4 *jac;                       // W x jtotal: per (group, use) gradient of each member, sorted order
     int64_t jtotal;                    // sum over groups of members x uses
     int64_t joff[kMaxGroups][kMaxInv]; // first entry of (group, use) within a walker's jac
-    int32_t cz, nzb, nblk;             // column blocks: cz cells in z, nzb per column, nblk in all
+    int32_t nzb, nblk;                 // column blocks: nzb per column (even split), nblk in all
     // uses of each group: the CV (index into CvSet::cv) and its partner group
     int32_t ninv[kMaxGroups];
     int32_t inv_cv[kMaxGroups][kMaxInv], inv_p[kMaxGroups][kMaxInv];  // CV index in the set, partner group
