@@ -241,13 +241,23 @@ def surrogate_leg(args):
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
 
 
+def rho_cand(p):
+    """Candidate partners per home atom of the cell-list pair pass: the
+    partner group's density times the 3 x 3 x (2 rz + 1) sub-cells around the
+    home sub-cell (rz = 4 z sub-cells per cut length, 10 cells per edge)."""
+    nc = int(np.floor(p["box"] / p["rcut"]))
+    clen = p["box"] / nc
+    return p["n_group"] / p["box"] ** 3 * (3 * clen) ** 2 * (9 * clen / 4)
+
+
 def cn3_leg(args):
     """512 walkers, each 60,000 atoms uniform in a 12 nm periodic box; three
     coordination numbers between 20,000-atom groups (r0 0.5 nm, (6, 12), hard
     cut 1.2 nm, divided by |A|) through cell lists; one shared list of 10^6
     three-dimensional hills (sigma 0.2) around the expected CN.  One step =
-    cell sort, pair sums, hill sum, forces by pair recompute (VJP); replayed
-    graphs.  Then the same with a 6-128-128-1 surrogate."""
+    cell sort, one pair pass (CN values and each member's gradients), hill
+    sum, forces gathered from the stored gradients (VJP); replayed graphs.
+    Then the same with a 6-128-128-1 surrogate."""
     import torch
     from paper_2301_04835_amd import Sampler, synth
 
@@ -272,15 +282,20 @@ def cn3_leg(args):
     ms_sort, ms_pairs, ms_vjp = s.time_cell(pos, forces=forces, reps=10)
     # algorithmic work: expected pairs inside the cut (density x sphere volume);
     # the pair pass evaluates each from both sides (each side: r^2 8 flops,
-    # switch and its derivative 9, switch sum 1, 3 FMAs 6)
+    # switch and its derivative 9, switch sum 1, 3 FMAs 6).  The cells make it
+    # visit 9 x 2.25 cut-length cubes per atom, 4.8x the cut sphere: the
+    # candidate rate is reported beside it
+    cand = 2 * 3 * W * n * rho_cand(p)
     rho = n / p["box"] ** 3
     pairs = 3 * W * n * rho * 4.0 / 3.0 * np.pi * p["rcut"] ** 3
     pass_flops = 2 * pairs * 24
     res = {"workload": "cn3-cells-512-walkers-1M-shared-hills", "walkers": W, "atoms_per_walker": 3 * n,
-           "cvs": "CN_AB, CN_BC, CN_CA over 20,000-atom groups, cut 1.2 nm, 10^3 cells", "hills": K,
+           "cvs": "CN_AB, CN_BC, CN_CA over 20,000-atom groups, cut 1.2 nm",
+           "cells": "10 x 10 x 40 (z cut into 4 sub-cells per cut length)", "hills": K,
            "steps_per_s": rate, "ms_per_step": 1e3 / rate, "steps_timed": nst,
            "cell_sort_ms": ms_sort, "pair_pass_ms": ms_pairs, "vjp_gather_ms": ms_vjp,
-           "pairs_in_cut_per_step": pairs,
+           "pairs_in_cut_per_step": pairs, "candidate_pairs_per_step": cand,
+           "candidate_pairs_per_s": cand / (ms_pairs * 1e-3),
            "roofline": {"bound": "alu", "kernel": "k_cell_jac<true> (+ k_cn_cell_fin)",
                         "achieved": pass_flops / (ms_pairs * 1e-3) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": pass_flops / (ms_pairs * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
