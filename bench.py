@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
     ap.add_argument("--no-bust", action="store_true", help="skip the cache-busting replica of the hill kernel")
     ap.add_argument("--no-cn3", action="store_true", help="skip the cell-list coordination-number workload")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the one-walker hill-count sweep")
     ap.add_argument("--cn3-steps", type=int, default=50, help="timed steps of the coordination-number workload")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2301_04835_amd", "tuning_mi355x.json"),
                     help="autotuner cache (JSON): an entry for this problem shape is reused, else searched and added")
@@ -99,7 +100,9 @@ def measured_traffic(tile):
 
 def cpu_baseline(d, p, target_s):
     """The FP64 oracle on the host: whole steps (CVs, hill sums, chain rule)
-    over all 256 walkers, single thread, repeated until ~target_s seconds."""
+    over all 256 walkers, single thread, repeated until ~target_s seconds;
+    then the same with the hill sums spread over the host's cores (OpenMP,
+    walkers in parallel; a third of the time)."""
     import oracle
 
     W = p["n_walkers"]
@@ -108,27 +111,42 @@ def cpu_baseline(d, p, target_s):
     H = d["heights"].astype(np.float64)
     per = [2 * np.pi, 2 * np.pi]
 
-    def one_step():
+    def one_step(nthreads):
         xi = np.zeros((W, 2))
         Js = []
         for w in range(W):
             xi[w], J = oracle.cv_eval(d["pos"][off[w]:off[w] + 8].astype(np.float64), d["cvs"])
             Js.append(J)
-        V, dV = oracle.hillsum_batch(xi, hoff, C, H, p["sigma"], per, nthreads=1)
+        V, dV = oracle.hillsum_batch(xi, hoff, C, H, p["sigma"], per, nthreads=nthreads)
         for w in range(W):
             oracle.chain_rule(-dV[w], Js[w])
 
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        one_step()
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= target_s:
-            break
+    def rate(nthreads, seconds):
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            one_step(nthreads)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return n, el
+
+    n, el = rate(1, target_s)
+    nt = host_cores()
+    n_all, el_all = rate(nt, target_s / 3.0)
     return {"value": n / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": "%d full steps of the same 256-walker workload (%d hills per step), FP64, 1 thread, %.1f s"
-                      % (n, int(hoff[-1]), el)}
+                      % (n, int(hoff[-1]), el),
+            "all_cores": {"value": n_all / el_all, "unit": "steps/s", "cores": nt,
+                          "sample": "%d full steps, hill sums over %d OpenMP threads, %.1f s" % (n_all, nt, el_all)}}
+
+
+def host_cores():
+    """Threads the host gives this process: the CPU affinity set, capped by
+    OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(env))) if env.isdigit() else n
 
 
 def bust_leg(d, p, tile, grid, reps):
@@ -176,6 +194,38 @@ def timed_graph(s, pos, forces, outs, steps, warmup, gsteps=10):
         s.graph_launch()
     torch.cuda.synchronize()
     return n * gsteps / (time.perf_counter() - t0), n * gsteps
+
+
+def sweep_leg(reps):
+    """One walker of the 22-atom system (phi/psi dihedrals) with K = 2^11 ...
+    2^26 private hills (24 KB ... 805 MB): the hill kernel's algorithmic read
+    rate as the list grows from cache-resident past the 256 MB Infinity
+    Cache.  Tile 4096, one workgroup per tile; the CVs are fused."""
+    import torch
+    from paper_2301_04835_amd import Sampler, synth
+
+    p = synth.WTMD22
+    Ks = [1 << e for e in (11, 14, 17, 20, 23, 26)]
+    C = synth.uniform_centers(Ks[-1], 2, 7)
+    H = synth.uniform_heights(Ks[-1], 8)
+    pos = torch.from_numpy(synth.chain_template(p["n_atoms"], 1).astype(np.float32)).cuda()
+    forces = torch.zeros_like(pos)
+    rows = []
+    for K in Ks:
+        s = Sampler(0)
+        s.add_cvs(synth.backbone_cvs(4))
+        s.set_walkers(np.array([0, p["n_atoms"]]), [K + 64])
+        s.metad(list(p["sigma"]), p["w"], p["T"], p["bias_factor"], p["stride"], K + 64)
+        s.bind()
+        s.hills_set(0, C[:K], H[:K])
+        s.set_tuning(4096, 0)
+        ms_a, ms_b = s.time_hill(pos, forces=forces, reps=reps if K < (1 << 23) else max(10, reps // 10))
+        gbs = 12.0 * K / (ms_a * 1e-3) / 1e9
+        rows.append({"hills": K, "hill_bytes": 12 * K, "kernel_ms": ms_a, "finalize_kernel_ms": ms_b,
+                     "hill_evals_per_s": K / (ms_a * 1e-3), "achieved": gbs, "frac": gbs / HBM_PEAK_GBS})
+        del s
+        torch.cuda.empty_cache()
+    return {"workload": "wtmd22-one-walker-hill-sweep", "unit": "GB/s", "peak": HBM_PEAK_GBS, "rows": rows}
 
 
 def surrogate_leg(args):
@@ -448,6 +498,8 @@ def main():
         torch.cuda.synchronize()
     if not args.no_bust:
         out["roofline_above_infinity_cache"] = bust_leg(d, p, tile, grid, args.hill_reps)
+    if not args.no_sweep:
+        out["hill_sweep_one_walker"] = sweep_leg(args.hill_reps)
     sg_data = None
     if not args.no_surrogate:
         out["surrogate"], sg_data = surrogate_leg(args)

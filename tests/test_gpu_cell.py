@@ -212,3 +212,27 @@ def mlp_init(H, F):
     from oracle import mlp
     P = mlp.init_params(H, F, 2)
     return [P[k] for k in mlp.PARAM_ORDER]
+
+
+def test_cell_autograd_harmonic(gpu):
+    """A harmonic bias k/2 (xi - xi0)^2 on the three cell-list CNs through
+    torch.autograd (CVFunction: forward = the cell-list kernels, backward =
+    the stored-gradient VJP), against the exact chain rule with the oracle's
+    Jacobian, two walkers."""
+    from paper_2301_04835_amd.autograd import cv
+
+    W, n, L = 2, 300, 4.0
+    pos, off, cvs = small_system(W, n, L, 31)
+    s = ctx(cvs, L, off, 1)
+    assert s.cell_list_cvs() == 3
+    k = torch.tensor([40.0, 25.0, 60.0], dtype=torch.float64, device=gpu)
+    xi0 = torch.tensor([1.0, 1.3, 0.8], dtype=torch.float64, device=gpu)
+    P = dev(pos).requires_grad_(True)
+    xi = cv(P, s)
+    (0.5 * (k * (xi - xi0) ** 2)).sum().backward()
+    g = P.grad.cpu().numpy()
+    for w in range(W):
+        xr, J = oracle_walker(pos[off[w]:off[w + 1]], cvs, L)
+        assert np.max(np.abs(xi[w].detach().cpu().numpy() - xr) / xr) <= 1e-6
+        xb = k.cpu().numpy() * (xr - xi0.cpu().numpy())
+        assert rel_inf(g[off[w]:off[w + 1]], np.tensordot(xb, J, axes=1)) <= 1e-5
