@@ -164,6 +164,36 @@ sx_status sx_metad_config(sx_ctx *ctx, const double *sigma, double w, double tem
 sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double delta_T, int32_t stride,
                              int64_t capacity);
 
+/* Keep the metadynamics bias on a grid (Sec. 2.1.5: the bias may be stored
+ * on a pre-defined grid, trading accuracy for speed).  Per CV d: nbins[d]
+ * (>= 2) intervals of [lo_d, hi_d]; a periodic CV (dihedral) needs
+ * hi - lo = 2 pi and has nbins[d] nodes lo + i delta that wrap, a
+ * non-periodic one nbins[d] + 1 nodes up to hi.  Each hill list (one per
+ * walker, or the shared one) has a grid of FP64 node values: the list's
+ * bias V and its gradient dV/dxi at every node (the exact Gaussian sum,
+ * kept current as hills are appended and rebuilt by sx_hills_set).  A step
+ * then reads V and dV/dxi at xi by multilinear interpolation over the 2^D
+ * nodes of xi's cell (each interpolated on its own: the force uses the
+ * interpolated gradient), instead of summing the hills; outside a
+ * non-periodic range the bias is zero and nothing is deposited (a walker of
+ * a shared list keeps its slot with a zero-height hill).  Well-tempered
+ * heights use the grid's V.  Grids live in the state (so export/import
+ * carry them).  sx_hillsum and sx_bias_eval still sum the hills exactly.
+ * All three arguments NULL: no grid.  Before sx_bind; sx_bind fails with
+ * EINVAL unless metadynamics is configured.  EINVAL: lo >= hi, nbins < 2,
+ * a periodic range other than 2 pi, D > 3, more than 2^28 nodes. */
+sx_status sx_metad_grid(sx_ctx *ctx, const double *lo, const double *hi, const int32_t *nbins);
+/* Nodes per grid of the bound state (0 without a grid). */
+int64_t sx_grid_nodes(const sx_ctx *ctx);
+/* The grid read-back at n points xi (device, n x D, FP64) of the grid of
+ * `walker`'s hill list (0 for a shared list): V_out (device, n) and, if
+ * not NULL, dVdxi_out (device, n x D).  Stream-ordered.  ESTATE: no grid. */
+sx_status sx_grid_eval(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double *V_out, double *dVdxi_out);
+/* Copy the node values of `walker`'s grid to the host: V (n_nodes) and, if
+ * not NULL, dVdxi (D x n_nodes, CV-major), nodes row-major (first CV
+ * slowest).  n_nodes must equal sx_grid_nodes.  Synchronous. */
+sx_status sx_grid_get(sx_ctx *ctx, int32_t walker, double *V, double *dVdxi, int64_t n_nodes);
+
 /* Adaptive biasing force (Sec. 2.1.4; Darve et al. 2008).  A grid of
  * nbins[d] bins on [lo_d, hi_d) per CV (row-major, first CV slowest).  At
  * every step, with J = dxi/dx and the system force F passed to sx_step:

@@ -63,6 +63,10 @@ SIGNATURES = {
     "sx_get_tuning": (i32, [P, P, P]),
     "sx_autotune": (i32, [P, P, i32, i32, ctypes.c_char_p]),
     "sx_time_hill": (i32, [P, P, i32, i32, P, i32, P, P]),
+    "sx_metad_grid": (i32, [P, P, P, P]),
+    "sx_grid_nodes": (ctypes.c_int64, [P]),
+    "sx_grid_eval": (i32, [P, i32, P, ctypes.c_int64, P, P]),
+    "sx_grid_get": (i32, [P, i32, P, P, ctypes.c_int64]),
     "sx_time_cell": (i32, [P, P, i32, i32, P, i32, P, P, P]),
     "sx_probe_read": (i32, [P, sz, P, i32, P]),
     "sx_probe_copy": (i32, [P, P, sz, i32, P]),

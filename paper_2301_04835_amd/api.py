@@ -146,6 +146,17 @@ class Sampler:
         s, p = _host(sigma, np.float64)
         self._check(self.L.sx_metad_config_dT(self.h, p, float(height), float(delta_T), int(stride), int(capacity)))
 
+    def metad_grid(self, lo, hi, nbins):
+        """Keep the metadynamics bias on a grid (see sx_metad_grid); pass
+        None for all three to switch it off."""
+        if lo is None and hi is None and nbins is None:
+            self._check(self.L.sx_metad_grid(self.h, None, None, None))
+            return
+        lo_, plo = _host(lo, np.float64)
+        hi_, phi = _host(hi, np.float64)
+        nb, pn = _host(nbins, np.int32)
+        self._check(self.L.sx_metad_grid(self.h, plo, phi, pn))
+
     def abf(self, lo, hi, nbins, n_threshold=500):
         lo_, plo = _host(lo, np.float64)
         hi_, phi = _host(hi, np.float64)
@@ -212,6 +223,25 @@ class Sampler:
         dV = torch.empty((n, self.D), dtype=torch.float64, device=self.device) if grad else None
         self._check(self.L.sx_bias_eval(self.h, int(walker), _ptr(xi.contiguous()), n, _ptr(V), _ptr(dV)))
         return V, dV
+
+    def grid_eval(self, xi, walker=0, grad=True):
+        """The bias grid's read-back (multilinear interpolation) at points xi
+        (n x D, device float64)."""
+        n = xi.shape[0]
+        V = torch.empty(n, dtype=torch.float64, device=self.device)
+        dV = torch.empty((n, self.D), dtype=torch.float64, device=self.device) if grad else None
+        self._check(self.L.sx_grid_eval(self.h, int(walker), _ptr(xi.contiguous()), n, _ptr(V), _ptr(dV)))
+        return V, dV
+
+    def grid_get(self, walker=0):
+        """Node values of a bias grid: V (nodes,) and dV/dxi (D, nodes), host
+        float64, nodes row-major (first CV slowest)."""
+        n = int(self.L.sx_grid_nodes(self.h))
+        V = np.empty(n)
+        G = np.empty((self.D, n))
+        self._check(self.L.sx_grid_get(self.h, int(walker), V.ctypes.data_as(ctypes.c_void_p),
+                                       G.ctypes.data_as(ctypes.c_void_p), n))
+        return V, G
 
     def deposit(self, xi):
         self._check(self.L.sx_deposit(self.h, _ptr(xi)))

@@ -1,0 +1,230 @@
+// Metadynamics bias kept on a grid (Sec. 2.1.5: the bias may be stored on a
+// pre-defined grid, trading accuracy for speed).  Each hill list has a grid
+// holding, at every node, the list's bias V and its gradient dV/dxi; a CV
+// value reads them back by multilinear interpolation over the 2^D nodes of
+// its cell (V and each gradient component interpolated on their own).
+// Outside the range of a non-periodic CV there is no bias.
+//
+//   k_grid_step     one workgroup per walker: the read-back, the outputs, the
+//                   well-tempered deposit into the hill list (height from
+//                   the read-back V) and the force gather.
+//   k_grid_add      one workgroup per grid: the hills the step appended
+//                   (FP64, list order) added to every node, then the list's
+//                   count advanced; the workgroup of grid 0 also advances
+//                   the device step counter.  With rebuild set, many
+//                   workgroups per grid refill it from the whole list.
+//   k_grid_eval     the read-back at arbitrary points.
+//
+// Node sums run in FP64 in the order the hills sit in the list, so a grid
+// holds the exact hill sum at its nodes up to the rounding of exp.
+#include "sx_internal.h"
+#include "dev_gather.h"
+
+namespace sx {
+namespace {
+
+constexpr int kAddBlock = 1024;
+
+// The cell of xi and the interpolated (V, dV/dxi) of grid l; false (and
+// zeros) outside the range of a non-periodic CV.  Corner c takes node i1 of
+// CV d when bit D - 1 - d of c is set (first CV the most significant).
+__device__ bool grid_read(const GridArgs &g, int32_t l, const double *xi, double &V, double (&G)[kMaxBiasDim])
+{
+    int32_t i0[kMaxBiasDim], i1[kMaxBiasDim];
+    double t[kMaxBiasDim];
+    bool inside = true;
+    for (int d = 0; d < g.D; ++d) {
+        const double u = (xi[d] - g.lo[d]) / g.delta[d];
+        double fl = floor(u);
+        t[d] = u - fl;
+        if (g.per[d]) {
+            int64_t k = (int64_t)fl % g.nbins[d];
+            if (k < 0) k += g.nbins[d];
+            i0[d] = (int32_t)k;
+            i1[d] = i0[d] + 1 == g.nbins[d] ? 0 : i0[d] + 1;
+        } else {
+            if (!(u >= 0.0 && u <= (double)g.nbins[d])) {
+                inside = false;
+                i0[d] = i1[d] = 0;
+                continue;
+            }
+            int32_t k = (int32_t)fl;
+            if (k == g.nbins[d]) {  // xi == hi: the last cell, weight 1 on its far node
+                k = g.nbins[d] - 1;
+                t[d] = 1.0;
+            }
+            i0[d] = k;
+            i1[d] = k + 1;
+        }
+    }
+    V = 0.0;
+    for (int d = 0; d < kMaxBiasDim; ++d) G[d] = 0.0;
+    if (!inside) return false;
+    const double *Vg = g.V + (int64_t)l * g.N;
+    const double *Gg = g.G + (int64_t)l * g.D * g.N;
+    for (int c = 0; c < (1 << g.D); ++c) {
+        int64_t idx = 0;
+        double wgt = 1.0;
+        for (int d = 0; d < g.D; ++d) {
+            const bool hi = (c >> (g.D - 1 - d)) & 1;
+            idx = idx * g.n[d] + (hi ? i1[d] : i0[d]);
+            wgt *= hi ? t[d] : 1.0 - t[d];
+        }
+        V += wgt * Vg[idx];
+        for (int d = 0; d < g.D; ++d) G[d] += wgt * Gg[(int64_t)d * g.N + idx];
+    }
+    return true;
+}
+
+__global__ void __launch_bounds__(kBlock) k_grid_step(GridArgs g)
+{
+    __shared__ double s_coef[kMaxCv];
+    const int32_t w = blockIdx.x;
+    const int32_t l = g.shared ? 0 : w;
+    if (threadIdx.x == 0) {
+        double xi[kMaxBiasDim], V, G[kMaxBiasDim];
+        for (int d = 0; d < g.D; ++d) xi[d] = g.xi[(int64_t)w * g.D + d];
+        const bool inside = grid_read(g, l, xi, V, G);
+        bool finite = isfinite(V);
+        g.V_ws[w] = V;
+        if (g.V_out) g.V_out[w] = V;
+        for (int d = 0; d < g.D; ++d) {
+            finite = finite && isfinite(G[d]);
+            g.dV_ws[(int64_t)w * g.D + d] = G[d];
+            if (g.dV_out) g.dV_out[(int64_t)w * g.D + d] = G[d];
+            if (g.xi_out) g.xi_out[(int64_t)w * g.D + d] = xi[d];
+            s_coef[d] = -G[d];
+        }
+        if (!finite) atomicOr(g.flags, kFlagNonFinite);
+        // the step number after this one: the step kernel reads the device
+        // counter, the add kernel that follows advances it
+        const int64_t next_step = g.step >= 0 ? g.step + 1 : *g.dstep + 1;
+        bool dep = g.deposit == 2;
+        if (g.deposit == 1 && g.stride > 0) dep = (next_step - 1) % g.stride == 0;
+        if (dep && (inside || g.shared)) {
+            // outside the grid nothing is deposited, except that a walker
+            // keeps its slot of a shared list (walker order) with a hill of
+            // height 0, which adds nothing to the bias
+            const double h = !inside ? 0.0 : g.inv_kdT > 0.0 ? g.height * exp(-V * g.inv_kdT) : g.height;
+            const WalkerRec wr = g.wrec[l];
+            const int64_t hb = (int64_t)wr.hb4 * 4;
+            const int32_t cnt = g.count[l];
+            const int32_t nnew = g.shared ? g.tabs.W : 1;
+            if ((int64_t)cnt + nnew <= wr.cap) {
+                const int64_t k = hb + cnt + (g.shared ? w : 0);
+                for (int d = 0; d < g.D; ++d) g.c[d][k] = (float)xi[d];
+                g.h[k] = (float)h;
+                if (!g.shared || w == 0) g.pend[l] = nnew;
+            } else {
+                atomicOr(g.flags, kFlagCapacity);
+            }
+        }
+    }
+    __syncthreads();
+    if (g.do_forces) gather_forces(g.tabs, g.J + (int64_t)w * g.nslots * 3, w, s_coef, g.F);
+}
+
+// hills [k0, k1) of list l onto nodes [first, N) of its grid, node stride
+// `stride`; rebuild: the nodes start from zero
+__device__ void add_hills(const GridArgs &g, int32_t l, int32_t k0, int32_t k1, bool rebuild, int64_t first,
+                          int64_t stride)
+{
+    const int64_t hb = (int64_t)g.wrec[l].hb4 * 4;
+    double *Vg = g.V + (int64_t)l * g.N;
+    double *Gg = g.G + (int64_t)l * g.D * g.N;
+    for (int64_t node = first; node < g.N; node += stride) {
+        double x[kMaxBiasDim];
+        int64_t r = node;
+        for (int d = g.D - 1; d >= 0; --d) {
+            const int64_t i = r % g.n[d];
+            r /= g.n[d];
+            x[d] = g.lo[d] + (double)i * g.delta[d];
+        }
+        double v = rebuild ? 0.0 : Vg[node];
+        double gd[kMaxBiasDim];
+        for (int d = 0; d < g.D; ++d) gd[d] = rebuild ? 0.0 : Gg[(int64_t)d * g.N + node];
+        for (int32_t j = k0; j < k1; ++j) {
+            double q = 0.0, dl[kMaxBiasDim];
+            for (int d = 0; d < g.D; ++d) {
+                double u = x[d] - (double)g.c[d][hb + j];
+                if (g.period[d] > 0.0) u -= g.period[d] * rint(u / g.period[d]);
+                dl[d] = u;
+                q += u * u * (0.5 * g.inv_sig2[d]);
+            }
+            const double e = (double)g.h[hb + j] * exp(-q);
+            v += e;
+            for (int d = 0; d < g.D; ++d) gd[d] -= e * dl[d] * g.inv_sig2[d];
+        }
+        Vg[node] = v;
+        for (int d = 0; d < g.D; ++d) Gg[(int64_t)d * g.N + node] = gd[d];
+    }
+}
+
+// After k_grid_step: one workgroup per grid (gridDim.x = L).
+__global__ void __launch_bounds__(kAddBlock) k_grid_add(GridArgs g)
+{
+    const int32_t l = blockIdx.x;
+    const int32_t k0 = g.count[l], nnew = g.pend[l];
+    if (nnew > 0) add_hills(g, l, k0, k0 + nnew, false, threadIdx.x, kAddBlock);
+    __syncthreads();  // every node has read the window before it moves
+    if (threadIdx.x == 0) {
+        if (nnew > 0) {
+            g.count[l] = k0 + nnew;
+            g.pend[l] = 0;
+        }
+        if (l == 0 && g.count_step) *g.dstep = g.step >= 0 ? g.step + 1 : *g.dstep + 1;
+    }
+}
+
+// Rebuild grids l0 + blockIdx.x from their whole lists; the gridDim.y
+// workgroups of a grid split its nodes.
+__global__ void __launch_bounds__(kAddBlock) k_grid_rebuild(GridArgs g, int32_t l0)
+{
+    const int32_t l = l0 + blockIdx.x;
+    add_hills(g, l, 0, g.count[l], true, (int64_t)blockIdx.y * kAddBlock + threadIdx.x,
+              (int64_t)gridDim.y * kAddBlock);
+}
+
+__global__ void __launch_bounds__(kBlock) k_grid_eval(GridArgs g, int32_t l, const double *xi, int64_t n, double *V,
+                                                        double *dV)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v, G[kMaxBiasDim];
+    grid_read(g, l, xi + i * g.D, v, G);
+    V[i] = v;
+    if (dV)
+        for (int d = 0; d < g.D; ++d) dV[i * g.D + d] = G[d];
+}
+
+}  // namespace
+
+hipError_t launch_grid_step(const GridArgs &g, hipStream_t s)
+{
+    if (g.tabs.W < 1 || g.L < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grid_step, dim3(g.tabs.W), dim3(kBlock), 0, s, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grid_add, dim3(g.L), dim3(kAddBlock), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_rebuild(const GridArgs &g, int32_t l0, int32_t nl, hipStream_t s)
+{
+    if (nl < 1 || l0 < 0 || l0 + nl > g.L) return hipErrorInvalidValue;
+    const int64_t nb = std::min<int64_t>((g.N + kAddBlock - 1) / kAddBlock, 1024);
+    hipLaunchKernelGGL(k_grid_rebuild, dim3(nl, (unsigned)nb), dim3(kAddBlock), 0, s, g, l0);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_eval(const GridArgs &g, int32_t l, const double *xi, int64_t n, double *V, double *dV,
+                            hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (l < 0 || l >= g.L) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grid_eval, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, l, xi, n, V,
+                       dV);
+    return hipGetLastError();
+}
+
+}  // namespace sx

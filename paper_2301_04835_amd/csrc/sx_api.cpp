@@ -64,6 +64,11 @@ struct Plan {
     int64_t nbins_total = 0;
     // state sub-buffers
     Sub s_hdr, s_count, s_c[kMaxBiasDim], s_h, s_N, s_Fsum;
+    // metadynamics bias on a grid: nodes per grid, grids (hill lists), and
+    // in the state the node values, gradients and pending-hill counts
+    int64_t mg_N = 0;
+    int32_t mg_L = 0, mg_n[kMaxBiasDim] = {0, 0, 0};
+    Sub s_mgV, s_mgG, s_mgPend;
     size_t state_bytes = 0;
     // cell lists of coordination numbers
     CellArgs cell{};
@@ -106,6 +111,10 @@ struct sx_ctx {
     double lo[kMaxBiasDim] = {0, 0, 0}, hi[kMaxBiasDim] = {0, 0, 0};
     int32_t nbins[kMaxBiasDim] = {0, 0, 0};
     int32_t n_threshold = 0;
+    // metadynamics bias kept on a grid (sx_metad_grid)
+    bool mg_on = false;
+    double mg_lo[kMaxBiasDim] = {0, 0, 0}, mg_hi[kMaxBiasDim] = {0, 0, 0};
+    int32_t mg_nbins[kMaxBiasDim] = {0, 0, 0};
     // binding
     Plan plan;
     bool bound = false;
@@ -455,6 +464,23 @@ sx_status make_plan(sx_ctx *c)
     p.s_h = ls.take(sizeof(float) * total);
     p.s_N = ls.take(sizeof(uint32_t) * p.W * p.nbins_total);
     p.s_Fsum = ls.take(sizeof(double) * p.W * p.nbins_total * p.D);
+    if (c->mg_on) {
+        if (c->method != M_METAD) return fail(c, SX_EINVAL, "a bias grid needs metadynamics (sx_metad_config)");
+        if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "a bias grid spans at most 3 CVs");
+        p.mg_N = 1;
+        for (int d = 0; d < p.D; ++d) {
+            if (cv_periodic(c->cvs[d]) && std::fabs((c->mg_hi[d] - c->mg_lo[d]) - kTwoPi) > 1e-9)
+                return fail(c, SX_EINVAL, "a periodic CV's grid must span one period (2 pi)");
+            p.mg_n[d] = c->mg_nbins[d] + (cv_periodic(c->cvs[d]) ? 0 : 1);
+            p.mg_N *= p.mg_n[d];
+        }
+        p.mg_L = nlists;
+        if (p.mg_N * p.mg_L * (1 + p.D) > ((int64_t)1 << 31))
+            return fail(c, SX_EINVAL, "bias grids above 2^31 values in all");
+        p.s_mgV = ls.take(sizeof(double) * p.mg_N * p.mg_L);
+        p.s_mgG = ls.take(sizeof(double) * p.mg_N * p.mg_L * p.D);
+        p.s_mgPend = ls.take(sizeof(int32_t) * p.mg_L);
+    }
     if (c->sg_H) {
         if (c->method != M_METAD) return fail(c, SX_EINVAL, "the surrogate network fits a metadynamics bias");
         if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "the surrogate takes at most 3 CVs");
@@ -746,6 +772,46 @@ sx_status enqueue_surrogate_step(sx_ctx *c, const PosView &pv, int64_t step, dou
     return cell_forces(c, pv, dV, -1.0, forces, layout);
 }
 
+GridArgs grid_args(sx_ctx *c, const double *xi)
+{
+    const Plan &p = c->plan;
+    GridArgs g{};
+    g.D = p.D;
+    g.L = p.mg_L;
+    g.shared = c->shared;
+    for (int d = 0; d < p.D; ++d) {
+        const bool per = cv_periodic(c->cvs[d]);
+        g.nbins[d] = c->mg_nbins[d];
+        g.n[d] = p.mg_n[d];
+        g.per[d] = per;
+        g.lo[d] = c->mg_lo[d];
+        g.delta[d] = (c->mg_hi[d] - c->mg_lo[d]) / c->mg_nbins[d];
+        g.period[d] = per ? kTwoPi : 0.0;
+        g.inv_sig2[d] = 1.0 / (c->sigma[d] * c->sigma[d]);
+    }
+    g.N = p.mg_N;
+    g.V = at<double>(c->state, p.s_mgV);
+    g.G = at<double>(c->state, p.s_mgG);
+    g.pend = at<int32_t>(c->state, p.s_mgPend);
+    for (int d = 0; d < kMaxBiasDim; ++d) g.c[d] = d < p.D ? at<float>(c->state, p.s_c[d]) : nullptr;
+    g.h = at<float>(c->state, p.s_h);
+    g.count = at<int32_t>(c->state, p.s_count);
+    g.wrec = at<WalkerRec>(c->ws, p.w_wrec);
+    g.xi = xi;
+    g.V_ws = at<double>(c->ws, p.w_V);
+    g.dV_ws = at<double>(c->ws, p.w_dV);
+    g.stride = c->stride;
+    g.step = 0;
+    g.height = c->height;
+    g.inv_kdT = c->kdT > 0 && std::isfinite(c->kdT) ? 1.0 / c->kdT : 0.0;
+    g.dstep = at<int64_t>(c->state, p.s_hdr);
+    g.flags = reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8);
+    g.nslots = p.nslots;
+    g.J = at<float>(c->ws, p.w_J);
+    g.tabs = tabs_of(c);
+    return g;
+}
+
 CellArgs cell_args(sx_ctx *c)
 {
     const Plan &p = c->plan;
@@ -790,14 +856,27 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
     double *xi = at<double>(c->ws, p.w_xi);
     float *J = at<float>(c->ws, p.w_J);
     if (c->method == M_NONE) return fail(c, SX_ESTATE, "no method configured (sx_metad_config / sx_abf_config)");
-    const bool fuse = c->method == M_METAD && p.all_dihedral && !c->shared && !c->sg_on;
+    const bool fuse = c->method == M_METAD && p.all_dihedral && !c->shared && !c->sg_on && !c->mg_on;
     if (c->sg_on) return enqueue_surrogate_step(c, pv, step, xi, J, xi_out, V_out, dVdxi_out, forces, layout);
     if (!fuse) {
         sx_status st = launch_cvs(c, pv, xi, J);
         if (st != SX_OK) return st;
     }
     if (c->method == M_METAD && !c->sg_on && c->stride > 0) c->sg_certified = false;  // may deposit
-    if (c->method == M_METAD && c->shared) {
+    if (c->method == M_METAD && c->mg_on) {
+        GridArgs g = grid_args(c, xi);
+        g.xi_out = xi_out;
+        g.V_out = V_out;
+        g.dV_out = dVdxi_out;
+        g.deposit = 1;
+        g.count_step = 1;
+        g.step = step;
+        g.do_forces = forces != nullptr;
+        g.F = force_view(c, forces, layout);
+        hipError_t e = launch_grid_step(g, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "bias-grid kernels");
+        if (sx_status st = cell_forces(c, pv, g.dV_ws, -1.0, forces, layout)) return st;
+    } else if (c->method == M_METAD && c->shared) {
         SharedArgs a = shared_args(c, 0, xi, p.W, c->grid > 0 ? c->grid : kSharedTarget);
         a.V_ws = at<double>(c->ws, p.w_V);
         a.dV_ws = at<double>(c->ws, p.w_dV);
@@ -1108,6 +1187,75 @@ sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double 
     return metad_common(ctx, sigma, w, kdT, stride, capacity);
 }
 
+sx_status sx_metad_grid(sx_ctx *ctx, const double *lo, const double *hi, const int32_t *nbins)
+{
+    if (!ctx) return SX_EINVAL;
+    if (sx_status s = require_unbound(ctx)) return s;
+    const int D = (int)ctx->cvs.size();
+    if (D < 1) return fail(ctx, SX_ESTATE, "define the CVs before the grid");
+    if (D > kMaxBiasDim) return fail(ctx, SX_EINVAL, "a bias grid spans at most 3 CVs");
+    if (!lo && !hi && !nbins) {  // off
+        ctx->mg_on = false;
+        invalidate(ctx);
+        return SX_OK;
+    }
+    if (!lo || !hi || !nbins) return fail(ctx, SX_EINVAL, "NULL grid argument");
+    int64_t tot = 1;
+    for (int d = 0; d < D; ++d) {
+        if (!(lo[d] < hi[d]) || !std::isfinite(lo[d]) || !std::isfinite(hi[d]))
+            return fail(ctx, SX_EINVAL, "grid needs finite lo < hi");
+        if (nbins[d] < 2) return fail(ctx, SX_EINVAL, "nbins must be >= 2");
+        if (cv_periodic(ctx->cvs[d]) && std::fabs((hi[d] - lo[d]) - kTwoPi) > 1e-9)
+            return fail(ctx, SX_EINVAL, "a periodic CV's grid must span one period (2 pi)");
+        tot *= (int64_t)nbins[d] + 1;
+        if (tot > ((int64_t)1 << 28)) return fail(ctx, SX_EINVAL, "grid too large");
+    }
+    for (int d = 0; d < D; ++d) {
+        ctx->mg_lo[d] = lo[d];
+        ctx->mg_hi[d] = hi[d];
+        ctx->mg_nbins[d] = nbins[d];
+    }
+    ctx->mg_on = true;
+    invalidate(ctx);
+    return SX_OK;
+}
+
+int64_t sx_grid_nodes(const sx_ctx *ctx)
+{
+    return ctx && ctx->bound && ctx->mg_on ? ctx->plan.mg_N : 0;
+}
+
+sx_status sx_grid_eval(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double *V_out, double *dVdxi_out)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (!ctx->mg_on) return fail(ctx, SX_ESTATE, "no bias grid on this context (sx_metad_grid)");
+    const int wl = walker_list(ctx, walker);
+    if (wl < 0 || wl >= ctx->plan.mg_L) return fail(ctx, SX_EINVAL, "walker out of range");
+    if (n < 0 || (n > 0 && (!xi || !V_out))) return fail(ctx, SX_EINVAL, "bad points or outputs");
+    hipError_t e = launch_grid_eval(grid_args(ctx, nullptr), wl, xi, n, V_out, dVdxi_out, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "bias-grid read-back");
+    return SX_OK;
+}
+
+sx_status sx_grid_get(sx_ctx *ctx, int32_t walker, double *V, double *dVdxi, int64_t n_nodes)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (!ctx->mg_on) return fail(ctx, SX_ESTATE, "no bias grid on this context (sx_metad_grid)");
+    const Plan &p = ctx->plan;
+    const int wl = walker_list(ctx, walker);
+    if (wl < 0 || wl >= p.mg_L) return fail(ctx, SX_EINVAL, "walker out of range");
+    if (n_nodes != p.mg_N || !V) return fail(ctx, SX_EINVAL, "n_nodes must equal sx_grid_nodes; V needed");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(V, at<double>(ctx->state, p.s_mgV) + (int64_t)wl * p.mg_N, sizeof(double) * p.mg_N,
+                      hipMemcpyDeviceToHost);
+    if (e == hipSuccess && dVdxi)
+        e = hipMemcpy(dVdxi, at<double>(ctx->state, p.s_mgG) + (int64_t)wl * p.D * p.mg_N,
+                      sizeof(double) * p.D * p.mg_N, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "bias-grid copy");
+    return SX_OK;
+}
+
 sx_status sx_abf_config(sx_ctx *ctx, const double *lo, const double *hi, const int32_t *nbins, int32_t n_threshold)
 {
     if (!ctx) return SX_EINVAL;
@@ -1184,9 +1332,15 @@ sx_status sx_bind(sx_ctx *ctx, void *dev_state, size_t state_bytes, void *dev_ws
     if (e == hipSuccess && p.cell.ncn) e = up(p.w_gatoms, p.gatoms.data(), sizeof(int32_t) * p.gatoms.size());
     if (e != hipSuccess) return hip_fail(ctx, e, "table upload");
     ctx->bound = true;
-    if (ctx->method != M_METAD || ctx->shared)
+    if (ctx->method != M_METAD || (ctx->shared && !ctx->mg_on))
         return hipStreamSynchronize(ctx->stream) == hipSuccess ? SX_OK : fail(ctx, SX_EDEVICE, "bind");
     build_tiles(ctx);
+    if (ctx->shared) {  // no tile table; the grid kernels read the shared list's record
+        e = hipMemcpyAsync(at<WalkerRec>(ctx->ws, p.w_wrec), ctx->wrecs.data(), sizeof(WalkerRec) * p.W,
+                           hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "walker record upload");
+    }
     return upload_tiles(ctx);
     SX_GUARD_END
 }
@@ -1296,6 +1450,12 @@ sx_status sx_deposit(sx_ctx *ctx, const double *xi)
     if (sx_status s = require_bound(ctx)) return s;
     if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
     if (!xi) return fail(ctx, SX_EINVAL, "xi is NULL");
+    if (ctx->mg_on) {  // the hills go onto the grids as they are appended
+        GridArgs g = grid_args(ctx, xi);
+        g.deposit = 2;
+        hipError_t e = launch_grid_step(g, ctx->stream);
+        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "bias-grid deposit kernels");
+    }
     if (ctx->shared) {
         SharedArgs sa = shared_args(ctx, 0, xi, ctx->plan.W);
         sa.deposit = 2;
@@ -1678,6 +1838,10 @@ sx_status sx_hills_set(sx_ctx *ctx, int32_t walker, const float *centers, const 
         e = hipMemcpy(at<float>(ctx->state, p.s_h) + p.hill_base[wl], heights, sizeof(float) * K, hipMemcpyHostToDevice);
     int32_t k32 = (int32_t)K;
     if (e == hipSuccess) e = hipMemcpy(at<int32_t>(ctx->state, p.s_count) + wl, &k32, 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && ctx->mg_on) {  // the list's grid from the new list
+        e = launch_grid_rebuild(grid_args(ctx, nullptr), wl, 1, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    }
     if (e != hipSuccess) return hip_fail(ctx, e, "hill upload");
     return SX_OK;
     SX_GUARD_END

@@ -158,6 +158,37 @@ struct AbfArgs {
 };
 
 // Hill sum over one shared list at nq query points.
+// Metadynamics bias kept on a grid: V and dV/dxi of each hill list at the
+// nodes (row-major, first CV slowest; a periodic CV has n bins = n nodes and
+// wraps, a non-periodic one n + 1 nodes up to hi), read back by multilinear
+// interpolation.  One grid per hill list.
+struct GridArgs {
+    int32_t D, L, shared;                 // CVs, hill lists (grids), one list for all walkers
+    int32_t nbins[kMaxBiasDim], n[kMaxBiasDim], per[kMaxBiasDim];  // bins, nodes, periodic
+    double lo[kMaxBiasDim], delta[kMaxBiasDim];
+    double period[kMaxBiasDim], inv_sig2[kMaxBiasDim];
+    int64_t N;                            // nodes per grid
+    double *V, *G;                        // L x N, L x D x N
+    int32_t *pend;                        // L: hills appended by the step, not yet on the grid
+    // hill lists: list l starts at wrec[l].hb4 * 4, holds wrec[l].cap
+    float *c[kMaxBiasDim];
+    float *h;
+    int32_t *count;
+    const WalkerRec *wrec;
+    // step
+    const double *xi;                     // W x D
+    double *V_ws, *dV_ws, *xi_out, *V_out, *dV_out;  // outputs may be null
+    int32_t deposit, count_step, stride;
+    int64_t step;
+    double height, inv_kdT;
+    int64_t *dstep;
+    uint32_t *flags;
+    int32_t do_forces, nslots;
+    const float *J;
+    WalkerTabs tabs;
+    ForceView F;
+};
+
 struct SharedArgs {
     int32_t D;
     float *c[kMaxBiasDim];
@@ -261,6 +292,13 @@ hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *
 hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s,
                                int which = 3);
 hipError_t launch_abf(const AbfArgs &a, hipStream_t s);
+// grid bias: a step (read-back, outputs, deposit, forces, then the step's
+// hills onto the grids); rebuilding grids l0 .. l0 + nl - 1 from their whole
+// lists; read-back at n points of grid l
+hipError_t launch_grid_step(const GridArgs &g, hipStream_t s);
+hipError_t launch_grid_rebuild(const GridArgs &g, int32_t l0, int32_t nl, hipStream_t s);
+hipError_t launch_grid_eval(const GridArgs &g, int32_t l, const double *xi, int64_t n, double *V, double *dV,
+                            hipStream_t s);
 // chunking of a shared-list sum over nq queries: chunk (hills) and count
 // chunking of a shared-list sum: about `target` workgroups, chunks of whole
 // 256-hill stages (nchunk <= ceil(cap / 256))
