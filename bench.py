@@ -288,6 +288,57 @@ def surrogate_leg(args):
     return res, (C, H, pos_np, off, sg)
 
 
+def grid_leg(args, sg_data, exact_rate, n=512):
+    """The surrogate workload's bias kept on an n x n grid (multilinear
+    read-back of V and dV/dxi; the 100,000 hills summed once onto the nodes):
+    replayed graphs of whole steps, bias frozen as in the surrogate leg.  The
+    read-back's force error against the exact hill sum (GPU, FP64 sums) at
+    2^14 random torus points and at the walkers."""
+    import torch
+    from paper_2301_04835_amd import Sampler, synth, synth_wt
+
+    C, H, pos_np, off, _ = sg_data
+    K, W = len(H), len(off) - 1
+    s = Sampler(0)
+    s.add_cvs(synth.backbone_cvs(4))
+    s.set_walkers(off, [K + 64], shared=True)
+    s.metad([0.3, 0.3], 1.0, 300.0, 6.0, 0, K + 64)
+    s.metad_grid([-np.pi, -np.pi], [np.pi, np.pi], [n, n])
+    s.bind()
+    t0 = time.perf_counter()
+    s.hills_set(0, C, H)  # fills the grid (synchronous)
+    t_build = time.perf_counter() - t0
+    pos = torch.from_numpy(pos_np).cuda()
+    forces = torch.zeros_like(pos)
+    mk = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+    out = (mk(W, 2), mk(W), mk(W, 2))
+    rate, nst = timed_graph(s, pos, forces, out, args.sg_steps, 200)
+    s.check()
+    X = torch.from_numpy(synth_wt.torus_points(1 << 14, 9)).cuda()
+    _, Gg = s.grid_eval(X)
+    _, Ge = s.bias_eval(X)
+    e = torch.linalg.norm(Gg - Ge, dim=1)
+    _, Gw = s.bias_eval(out[0])
+    ew = torch.linalg.norm(out[2] - Gw, dim=1)
+    res = {"grid": "%d x %d nodes, multilinear read-back" % (n, n), "grid_fill_s": t_build,
+           "steps_per_s": rate, "steps_timed": nst, "speedup_vs_exact": rate / exact_rate,
+           "max_dV_err_vs_exact_random_points": float(e.max()), "rms_dV_err_vs_exact_random_points":
+           float(torch.sqrt((e ** 2).mean())), "max_dV_err_vs_exact_gpu_walkers": float(ew.max())}
+    return res, (C, H, out[0].cpu().numpy(), out[2].cpu().numpy())
+
+
+def grid_oracle_check(gd):
+    """CPU oracle leg of the grid workload: the FP64 hill sum at the walkers'
+    CV values, against which the grid step's dV/dxi error is stated."""
+    import oracle
+
+    C, H, xi, dv = gd
+    _, dVr = oracle.hillsum_batch(xi, None, C.astype(np.float64), H.astype(np.float64), [0.3, 0.3],
+                                  [2 * np.pi, 2 * np.pi], nthreads=1)
+    err = np.linalg.norm(dv - dVr, axis=1)
+    return {"max_dV_err_vs_oracle": float(err.max()), "median_dV_err_vs_oracle": float(np.median(err))}
+
+
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
 
 
@@ -500,9 +551,10 @@ def main():
         out["roofline_above_infinity_cache"] = bust_leg(d, p, tile, grid, args.hill_reps)
     if not args.no_sweep:
         out["hill_sweep_one_walker"] = sweep_leg(args.hill_reps)
-    sg_data = None
+    sg_data = gd = None
     if not args.no_surrogate:
         out["surrogate"], sg_data = surrogate_leg(args)
+        out["surrogate"]["bias_grid"], gd = grid_leg(args, sg_data, out["surrogate"]["exact_steps_per_s"])
     cn_data = None
     if not args.no_cn3:
         out["cn3"], cn_data = cn3_leg(args)
@@ -510,6 +562,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(d, p, args.cpu_seconds)
         if sg_data is not None:
             out["surrogate"].update(surrogate_oracle_check(sg_data))
+            out["surrogate"]["bias_grid"].update(grid_oracle_check(gd))
         if cn_data is not None:
             out["cn3"].update(cn3_oracle(cn_data))
     print(json.dumps(out))

@@ -193,3 +193,39 @@ def test_grid_arguments(gpu):
     s.abf([-PI, -PI], [PI, PI], [10, 10])
     with pytest.raises(Exception):
         s.bind()  # a grid bias needs metadynamics
+
+
+def test_graph_replay_matches_eager_steps(gpu):
+    """A captured 3-step graph of the grid path (shared list of 4 walkers,
+    a deposit every 2 steps, device step counter), replayed four times,
+    against the same steps run eagerly: forces, V, the hill list and the
+    grid agree bitwise."""
+    W, n = 4, 22
+    tmpl = synth.chain_template(n, 5)
+    pos = np.concatenate([tmpl + 0.2 * np.random.default_rng(w).normal(size=tmpl.shape) for w in range(W)])
+    C = synth.uniform_centers(300, 2, 6)
+    H = synth.uniform_heights(300, 7)
+    mk = lambda: sampler(synth.backbone_cvs(4), [0.35, 0.35], [-PI, -PI], [PI, PI], [48, 48],
+                         atom_off=np.arange(W + 1) * n, cap=[400], shared=True, stride=2)
+    a, b = mk(), mk()
+    a.hills_set(0, C, H)
+    b.hills_set(0, C, H)
+    P = dev(pos)
+    Fa = torch.zeros((W * n, 3), dtype=torch.float32, device=gpu)
+    Fb = torch.zeros_like(Fa)
+    Va = torch.zeros(W, dtype=torch.float64, device=gpu)
+    Vb = torch.zeros_like(Va)
+    a.graph_capture(3, P, forces=Fa, V_out=Va)
+    for rep in range(4):
+        a.graph_launch()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.step(P, forces=Fb, V_out=Vb)
+        torch.cuda.synchronize()
+        assert torch.equal(Fa, Fb) and torch.equal(Va, Vb), rep
+    assert a.get_step() == 12 and b.get_step() == 12
+    ca, ha = a.hills_get(0)
+    cb, hb = b.hills_get(0)
+    assert ca.shape[0] == 300 + 6 * W and np.array_equal(ca, cb) and np.array_equal(ha, hb)
+    Ga, Gb = a.grid_get(0), b.grid_get(0)
+    assert np.array_equal(Ga[0], Gb[0]) and np.array_equal(Ga[1], Gb[1])
