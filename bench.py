@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-bust", action="store_true", help="skip the cache-busting replica of the hill kernel")
     ap.add_argument("--no-cn3", action="store_true", help="skip the cell-list coordination-number workload")
     ap.add_argument("--no-sweep", action="store_true", help="skip the one-walker hill-count sweep")
+    ap.add_argument("--no-umbrella", action="store_true", help="skip the harmonic-window workload")
     ap.add_argument("--cn3-steps", type=int, default=50, help="timed steps of the coordination-number workload")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2301_04835_amd", "tuning_mi355x.json"),
                     help="autotuner cache (JSON): an entry for this problem shape is reused, else searched and added")
@@ -226,6 +227,36 @@ def sweep_leg(reps):
         del s
         torch.cuda.empty_cache()
     return {"workload": "wtmd22-one-walker-hill-sweep", "unit": "GB/s", "peak": HBM_PEAK_GBS, "rows": rows}
+
+
+def umbrella_leg(args, d):
+    """Harmonic biasing with one window per walker on the 256-walker
+    workload (uneven walkers, the same two dihedrals): window centres along
+    a path across the (phi, psi) torus, k = 100 kJ/mol/rad^2; replayed
+    graphs of whole steps (CVs, spring, forces, window sums), then umbrella
+    integration of the windows on the host."""
+    import torch
+    from paper_2301_04835_amd import Sampler
+
+    W = len(d["atom_off"]) - 1
+    t = np.linspace(0.0, 1.0, W)
+    centers = np.stack([-2.5 + 5.0 * t, 1.5 - 3.0 * t], 1)
+    s = Sampler(0)
+    s.add_cvs(d["cvs"])
+    s.set_walkers(d["atom_off"])
+    s.harmonic([100.0, 100.0], centers)
+    s.bind()
+    pos = torch.from_numpy(d["pos"]).cuda()
+    forces = torch.zeros_like(pos)
+    mk = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+    rate, nst = timed_graph(s, pos, forces, (mk(W, 2), mk(W), mk(W, 2)), args.steps, args.warmup)
+    s.check()
+    t0 = time.perf_counter()
+    _, A = s.umbrella_integrate()
+    t_int = time.perf_counter() - t0
+    return {"workload": "umbrella-windows-256-walkers", "walkers": W, "k": [100.0, 100.0],
+            "steps_per_s": rate, "ms_per_step": 1e3 / rate, "steps_timed": nst,
+            "integrate_s": t_int, "A_range": float(np.max(A) - np.min(A))}
 
 
 def surrogate_leg(args):
@@ -551,6 +582,8 @@ def main():
         out["roofline_above_infinity_cache"] = bust_leg(d, p, tile, grid, args.hill_reps)
     if not args.no_sweep:
         out["hill_sweep_one_walker"] = sweep_leg(args.hill_reps)
+    if not args.no_umbrella:
+        out["umbrella"] = umbrella_leg(args, d)
     sg_data = gd = None
     if not args.no_surrogate:
         out["surrogate"], sg_data = surrogate_leg(args)

@@ -164,6 +164,31 @@ sx_status sx_metad_config(sx_ctx *ctx, const double *sigma, double w, double tem
 sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double delta_T, int32_t stride,
                              int64_t capacity);
 
+/* Harmonic biasing (Sec. 2.1.1) with one window per walker, the sampling
+ * of umbrella sampling / umbrella integration (Sec. 2.1.2).  k: D spring
+ * constants (> 0; kJ/mol per CV unit squared); centers: n_walkers x D
+ * window centres xi0_w (host, copied).  Each sx_step adds
+ *   V_w = sum_d k_d D_d^2 / 2,   D = xi_w - xi0_w (minimum image for a
+ *   periodic CV),   forces += -sum_d k_d D_d dxi_d/dx
+ * and adds the sample to the walker's window sums (count, sum D,
+ * sum D D^T; FP64, in the state).  n_walkers must equal the walker count at
+ * sx_bind (EINVAL there otherwise).  EINVAL: k <= 0, non-finite centre,
+ * D > 3.  Before sx_bind.  Exclusive with metadynamics and ABF. */
+sx_status sx_harmonic_config(sx_ctx *ctx, const double *k, const double *centers, int32_t n_walkers);
+/* Clear the window sums (e.g. after equilibration).  Stream-ordered. */
+sx_status sx_umbrella_reset(sx_ctx *ctx);
+/* Per window: samples n (W), mean xi0 + <D> (W x D) and covariance
+ * <D D^T> - <D><D>^T (W x D x D); host outputs, each may be NULL.
+ * Synchronous. */
+sx_status sx_umbrella_stats(sx_ctx *ctx, int64_t *n, double *mean, double *cov);
+/* Umbrella integration over the windows in walker order (the path): the
+ * mean force on window w, k (xi0_w - <xi>_w) (minimum image), estimates
+ * dA/dxi at the window mean; A along the path of means by the trapezoidal
+ * rule, A_0 = 0, A_{w+1} = A_w + (g_w + g_{w+1}) . (m_{w+1} - m_w) / 2.
+ * mean_force (W x D) and A (W): host, may be NULL (not both).  ESTATE: a
+ * window without samples.  Synchronous. */
+sx_status sx_umbrella_integrate(sx_ctx *ctx, double *mean_force, double *A);
+
 /* Keep the metadynamics bias on a grid (Sec. 2.1.5: the bias may be stored
  * on a pre-defined grid, trading accuracy for speed).  Per CV d: nbins[d]
  * (>= 2) intervals of [lo_d, hi_d]; a periodic CV (dihedral) needs

@@ -64,6 +64,10 @@ SIGNATURES = {
     "sx_autotune": (i32, [P, P, i32, i32, ctypes.c_char_p]),
     "sx_time_hill": (i32, [P, P, i32, i32, P, i32, P, P]),
     "sx_metad_grid": (i32, [P, P, P, P]),
+    "sx_harmonic_config": (i32, [P, P, P, i32]),
+    "sx_umbrella_reset": (i32, [P]),
+    "sx_umbrella_stats": (i32, [P, P, P, P]),
+    "sx_umbrella_integrate": (i32, [P, P, P]),
     "sx_grid_nodes": (ctypes.c_int64, [P]),
     "sx_grid_eval": (i32, [P, i32, P, ctypes.c_int64, P, P]),
     "sx_grid_get": (i32, [P, i32, P, P, ctypes.c_int64]),

@@ -146,6 +146,35 @@ class Sampler:
         s, p = _host(sigma, np.float64)
         self._check(self.L.sx_metad_config_dT(self.h, p, float(height), float(delta_T), int(stride), int(capacity)))
 
+    def harmonic(self, k, centers):
+        """Harmonic bias with one window centre per walker (centers: W x D)."""
+        k_, pk = _host(k, np.float64)
+        c, pc = _host(centers, np.float64)
+        self._check(self.L.sx_harmonic_config(self.h, pk, pc, int(c.reshape(-1, k_.size).shape[0])))
+
+    def umbrella_reset(self):
+        self._check(self.L.sx_umbrella_reset(self.h))
+
+    def umbrella_stats(self):
+        """(samples (W,), means (W, D), covariances (W, D, D)), host."""
+        W, D = self.n_walkers, self.D
+        n = np.zeros(W, dtype=np.int64)
+        m = np.zeros((W, D))
+        c = np.zeros((W, D, D))
+        self._check(self.L.sx_umbrella_stats(self.h, n.ctypes.data_as(ctypes.c_void_p),
+                                             m.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p)))
+        return n, m, c
+
+    def umbrella_integrate(self):
+        """(mean forces (W, D), A (W,)) by umbrella integration along the
+        windows in walker order."""
+        W, D = self.n_walkers, self.D
+        g = np.zeros((W, D))
+        A = np.zeros(W)
+        self._check(self.L.sx_umbrella_integrate(self.h, g.ctypes.data_as(ctypes.c_void_p),
+                                                 A.ctypes.data_as(ctypes.c_void_p)))
+        return g, A
+
     def metad_grid(self, lo, hi, nbins):
         """Keep the metadynamics bias on a grid (see sx_metad_grid); pass
         None for all three to switch it off."""

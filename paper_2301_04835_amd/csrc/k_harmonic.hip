@@ -1,0 +1,60 @@
+// Harmonic biasing (Sec. 2.1.1) and the samples of umbrella sampling /
+// umbrella integration (Sec. 2.1.2): walker w is a window with centre
+// xi0_w; its bias is sum_d k_d D_d^2 / 2 with D = xi - xi0_w (minimum image
+// for a periodic CV), dV/dxi = k D, and the force -sum_d k_d D_d dxi_d/dx is
+// gathered onto its atoms.  Each step may add the sample to the window's
+// FP64 sums (count, sum D, sum D D^T), from which its mean and covariance
+// and the mean force k (xi0 - <xi>) follow.
+#include "sx_internal.h"
+#include "dev_gather.h"
+
+namespace sx {
+namespace {
+
+// one workgroup per walker; thread 0 owns the window's bookkeeping
+__global__ void __launch_bounds__(kBlock) k_harmonic(HarmonicArgs a)
+{
+    __shared__ double s_coef[kMaxCv];
+    const int32_t w = blockIdx.x;
+    if (threadIdx.x == 0) {
+        double Dv[kMaxBiasDim], V = 0.0;
+        bool finite = true;
+        for (int d = 0; d < a.D; ++d) {
+            const double x = a.xi[(int64_t)w * a.D + d];
+            double t = x - a.xi0[(int64_t)w * a.D + d];
+            if (a.period[d] > 0.0) t -= a.period[d] * rint(t / a.period[d]);
+            Dv[d] = t;
+            const double g = a.k[d] * t;
+            V += 0.5 * g * t;
+            finite = finite && isfinite(g);
+            a.dV_ws[(int64_t)w * a.D + d] = g;
+            if (a.dV_out) a.dV_out[(int64_t)w * a.D + d] = g;
+            if (a.xi_out) a.xi_out[(int64_t)w * a.D + d] = x;
+            s_coef[d] = -g;
+        }
+        a.V_ws[w] = V;
+        if (a.V_out) a.V_out[w] = V;
+        if (!finite || !isfinite(V)) atomicOr(a.flags, kFlagNonFinite);
+        if (a.accumulate) {
+            a.n[w] += 1;
+            for (int d = 0; d < a.D; ++d) {
+                a.s1[(int64_t)w * a.D + d] += Dv[d];
+                for (int e = 0; e < a.D; ++e) a.s2[((int64_t)w * a.D + d) * a.D + e] += Dv[d] * Dv[e];
+            }
+        }
+        if (w == 0 && a.count_step) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
+    }
+    __syncthreads();
+    if (a.do_forces) gather_forces(a.tabs, a.J + (int64_t)w * a.nslots * 3, w, s_coef, a.F);
+}
+
+}  // namespace
+
+hipError_t launch_harmonic(const HarmonicArgs &a, hipStream_t s)
+{
+    if (a.tabs.W < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_harmonic, dim3(a.tabs.W), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sx

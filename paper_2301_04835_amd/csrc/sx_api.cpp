@@ -41,7 +41,7 @@ struct CvDef {
     int32_t normalize = 0;
 };
 
-enum Method { M_NONE = 0, M_METAD = 1, M_ABF = 2 };
+enum Method { M_NONE = 0, M_METAD = 1, M_ABF = 2, M_HARMONIC = 3 };
 
 struct Sub {  // a sub-buffer: byte offset and size
     size_t off = 0, bytes = 0;
@@ -69,6 +69,8 @@ struct Plan {
     int64_t mg_N = 0;
     int32_t mg_L = 0, mg_n[kMaxBiasDim] = {0, 0, 0};
     Sub s_mgV, s_mgG, s_mgPend;
+    // harmonic windows: sample counts and sums (state), centres (workspace)
+    Sub s_umN, s_umS1, s_umS2, w_hbXi0;
     size_t state_bytes = 0;
     // cell lists of coordination numbers
     CellArgs cell{};
@@ -111,6 +113,9 @@ struct sx_ctx {
     double lo[kMaxBiasDim] = {0, 0, 0}, hi[kMaxBiasDim] = {0, 0, 0};
     int32_t nbins[kMaxBiasDim] = {0, 0, 0};
     int32_t n_threshold = 0;
+    // harmonic bias: spring constants and one centre per walker (W x D)
+    double hb_k[kMaxBiasDim] = {0, 0, 0};
+    std::vector<double> hb_xi0;
     // metadynamics bias kept on a grid (sx_metad_grid)
     bool mg_on = false;
     double mg_lo[kMaxBiasDim] = {0, 0, 0}, mg_hi[kMaxBiasDim] = {0, 0, 0};
@@ -464,6 +469,14 @@ sx_status make_plan(sx_ctx *c)
     p.s_h = ls.take(sizeof(float) * total);
     p.s_N = ls.take(sizeof(uint32_t) * p.W * p.nbins_total);
     p.s_Fsum = ls.take(sizeof(double) * p.W * p.nbins_total * p.D);
+    if (c->method == M_HARMONIC) {
+        if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "a harmonic bias spans at most 3 CVs");
+        if ((int64_t)c->hb_xi0.size() != (int64_t)p.W * p.D)
+            return fail(c, SX_EINVAL, "one harmonic centre per walker and CV is needed (W x D)");
+        p.s_umN = ls.take(sizeof(int64_t) * p.W);
+        p.s_umS1 = ls.take(sizeof(double) * p.W * p.D);
+        p.s_umS2 = ls.take(sizeof(double) * p.W * p.D * p.D);
+    }
     if (c->mg_on) {
         if (c->method != M_METAD) return fail(c, SX_EINVAL, "a bias grid needs metadynamics (sx_metad_config)");
         if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "a bias grid spans at most 3 CVs");
@@ -510,6 +523,7 @@ sx_status make_plan(sx_ctx *c)
     p.w_atom_off = lw.take(sizeof(int64_t) * (p.W + 1));
     p.w_tiles = lw.take(sizeof(TileRec) * p.ntiles_max);
     p.w_wrec = lw.take(sizeof(WalkerRec) * p.W);
+    p.w_hbXi0 = lw.take(c->method == M_HARMONIC ? sizeof(double) * p.W * p.D : 0);
     p.w_slot_atom = lw.take(sizeof(int32_t) * p.nslots);
     p.w_slot_cv = lw.take(sizeof(int32_t) * p.nslots);
     p.w_touched = lw.take(sizeof(int32_t) * p.U);
@@ -772,6 +786,30 @@ sx_status enqueue_surrogate_step(sx_ctx *c, const PosView &pv, int64_t step, dou
     return cell_forces(c, pv, dV, -1.0, forces, layout);
 }
 
+HarmonicArgs harmonic_args(sx_ctx *c, const double *xi)
+{
+    const Plan &p = c->plan;
+    HarmonicArgs a{};
+    a.D = p.D;
+    for (int d = 0; d < p.D; ++d) {
+        a.period[d] = cv_periodic(c->cvs[d]) ? kTwoPi : 0.0;
+        a.k[d] = c->hb_k[d];
+    }
+    a.xi0 = at<double>(c->ws, p.w_hbXi0);
+    a.xi = xi;
+    a.V_ws = at<double>(c->ws, p.w_V);
+    a.dV_ws = at<double>(c->ws, p.w_dV);
+    a.n = at<int64_t>(c->state, p.s_umN);
+    a.s1 = at<double>(c->state, p.s_umS1);
+    a.s2 = at<double>(c->state, p.s_umS2);
+    a.dstep = at<int64_t>(c->state, p.s_hdr);
+    a.flags = reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8);
+    a.nslots = p.nslots;
+    a.J = at<float>(c->ws, p.w_J);
+    a.tabs = tabs_of(c);
+    return a;
+}
+
 GridArgs grid_args(sx_ctx *c, const double *xi)
 {
     const Plan &p = c->plan;
@@ -904,6 +942,19 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.F = force_view(c, forces, layout);
         hipError_t e = launch_hill_private(a, p.cs, pv, c->grid, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "hill-sum kernels");
+        if (sx_status st = cell_forces(c, pv, a.dV_ws, -1.0, forces, layout)) return st;
+    } else if (c->method == M_HARMONIC) {
+        HarmonicArgs a = harmonic_args(c, xi);
+        a.accumulate = 1;
+        a.xi_out = xi_out;
+        a.V_out = V_out;
+        a.dV_out = dVdxi_out;
+        a.count_step = 1;
+        a.step = step;
+        a.do_forces = forces != nullptr;
+        a.F = force_view(c, forces, layout);
+        hipError_t e = launch_harmonic(a, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "harmonic kernel");
         if (sx_status st = cell_forces(c, pv, a.dV_ws, -1.0, forces, layout)) return st;
     } else {
         if (!sys_forces) return fail(c, SX_EINVAL, "ABF needs the system forces");
@@ -1150,6 +1201,7 @@ static sx_status metad_common(sx_ctx *ctx, const double *sigma, double w, double
     if (D < 1) return fail(ctx, SX_ESTATE, "define the CVs before the method");
     if (D > kMaxBiasDim) return fail(ctx, SX_EINVAL, "metadynamics supports at most 3 CVs");
     if (ctx->method == M_ABF) return fail(ctx, SX_EINVAL, "ABF already configured on this context");
+    if (ctx->method == M_HARMONIC) return fail(ctx, SX_EINVAL, "a harmonic bias is already configured on this context");
     if (!sigma) return fail(ctx, SX_EINVAL, "sigma is NULL");
     for (int d = 0; d < D; ++d)
         if (!(sigma[d] > 0) || !std::isfinite(sigma[d])) return fail(ctx, SX_EINVAL, "sigma must be > 0");
@@ -1185,6 +1237,116 @@ sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double 
     if (!ctx) return SX_EINVAL;
     double kdT = (delta_T > 0 && std::isfinite(delta_T)) ? kBoltzmann * delta_T : 0.0;
     return metad_common(ctx, sigma, w, kdT, stride, capacity);
+}
+
+sx_status sx_harmonic_config(sx_ctx *ctx, const double *k, const double *centers, int32_t n_walkers)
+{
+    if (!ctx) return SX_EINVAL;
+    if (sx_status s = require_unbound(ctx)) return s;
+    const int D = (int)ctx->cvs.size();
+    if (D < 1) return fail(ctx, SX_ESTATE, "define the CVs before the method");
+    if (D > kMaxBiasDim) return fail(ctx, SX_EINVAL, "a harmonic bias spans at most 3 CVs");
+    if (ctx->method != M_NONE && ctx->method != M_HARMONIC)
+        return fail(ctx, SX_EINVAL, "another method is already configured on this context");
+    if (!k || !centers || n_walkers < 1) return fail(ctx, SX_EINVAL, "NULL argument or no walkers");
+    for (int d = 0; d < D; ++d)
+        if (!(k[d] > 0) || !std::isfinite(k[d])) return fail(ctx, SX_EINVAL, "spring constants must be finite and > 0");
+    for (int64_t i = 0; i < (int64_t)n_walkers * D; ++i)
+        if (!std::isfinite(centers[i])) return fail(ctx, SX_EINVAL, "centres must be finite");
+    for (int d = 0; d < D; ++d) ctx->hb_k[d] = k[d];
+    ctx->hb_xi0.assign(centers, centers + (int64_t)n_walkers * D);
+    ctx->method = M_HARMONIC;
+    invalidate(ctx);
+    return SX_OK;
+}
+
+sx_status sx_umbrella_reset(sx_ctx *ctx)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (ctx->method != M_HARMONIC) return fail(ctx, SX_ESTATE, "no harmonic windows on this context");
+    const Plan &p = ctx->plan;
+    hipError_t e = launch_zero_bytes(ctx->state + p.s_umN.off, (int64_t)p.s_umN.bytes, ctx->stream);
+    if (e == hipSuccess) e = launch_zero_bytes(ctx->state + p.s_umS1.off, (int64_t)p.s_umS1.bytes, ctx->stream);
+    if (e == hipSuccess) e = launch_zero_bytes(ctx->state + p.s_umS2.off, (int64_t)p.s_umS2.bytes, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "window reset");
+    return SX_OK;
+}
+
+namespace {
+// the windows' sums on the host: counts, means (centre + mean displacement)
+// and covariances
+sx_status window_moments(sx_ctx *ctx, std::vector<int64_t> &n, std::vector<double> &mean, std::vector<double> &cov)
+{
+    const Plan &p = ctx->plan;
+    const int W = p.W, D = p.D;
+    n.assign(W, 0);
+    std::vector<double> s1((size_t)W * D), s2((size_t)W * D * D);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(n.data(), ctx->state + p.s_umN.off, sizeof(int64_t) * W, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(s1.data(), ctx->state + p.s_umS1.off, sizeof(double) * s1.size(), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(s2.data(), ctx->state + p.s_umS2.off, sizeof(double) * s2.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "window sums copy");
+    mean.assign((size_t)W * D, 0.0);
+    cov.assign((size_t)W * D * D, 0.0);
+    for (int w = 0; w < W; ++w) {
+        if (n[w] < 1) continue;
+        const double inv = 1.0 / (double)n[w];
+        for (int d = 0; d < D; ++d) mean[(size_t)w * D + d] = ctx->hb_xi0[(size_t)w * D + d] + s1[(size_t)w * D + d] * inv;
+        for (int d = 0; d < D; ++d)
+            for (int f = 0; f < D; ++f) {
+                const double md = s1[(size_t)w * D + d] * inv, mf = s1[(size_t)w * D + f] * inv;
+                cov[((size_t)w * D + d) * D + f] = s2[((size_t)w * D + d) * D + f] * inv - md * mf;
+            }
+    }
+    return SX_OK;
+}
+}  // namespace
+
+sx_status sx_umbrella_stats(sx_ctx *ctx, int64_t *n, double *mean, double *cov)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (ctx->method != M_HARMONIC) return fail(ctx, SX_ESTATE, "no harmonic windows on this context");
+    SX_GUARD_BEGIN
+    std::vector<int64_t> nn;
+    std::vector<double> m, c;
+    if (sx_status st = window_moments(ctx, nn, m, c)) return st;
+    if (n) std::copy(nn.begin(), nn.end(), n);
+    if (mean) std::copy(m.begin(), m.end(), mean);
+    if (cov) std::copy(c.begin(), c.end(), cov);
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_umbrella_integrate(sx_ctx *ctx, double *mean_force, double *A)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (ctx->method != M_HARMONIC) return fail(ctx, SX_ESTATE, "no harmonic windows on this context");
+    if (!mean_force && !A) return fail(ctx, SX_EINVAL, "no output");
+    SX_GUARD_BEGIN
+    const Plan &p = ctx->plan;
+    const int W = p.W, D = p.D;
+    std::vector<int64_t> nn;
+    std::vector<double> m, c;
+    if (sx_status st = window_moments(ctx, nn, m, c)) return st;
+    for (int w = 0; w < W; ++w)
+        if (nn[w] < 1) return fail(ctx, SX_ESTATE, "a window has no samples");
+    auto wrap = [&](double t, int d) { return cv_periodic(ctx->cvs[d]) ? t - kTwoPi * std::rint(t / kTwoPi) : t; };
+    std::vector<double> g((size_t)W * D);
+    for (int w = 0; w < W; ++w)
+        for (int d = 0; d < D; ++d)
+            g[(size_t)w * D + d] = ctx->hb_k[d] * wrap(ctx->hb_xi0[(size_t)w * D + d] - m[(size_t)w * D + d], d);
+    std::vector<double> a(W, 0.0);
+    for (int w = 0; w + 1 < W; ++w) {
+        double dot = 0.0;
+        for (int d = 0; d < D; ++d)
+            dot += (g[(size_t)w * D + d] + g[(size_t)(w + 1) * D + d]) *
+                   wrap(m[(size_t)(w + 1) * D + d] - m[(size_t)w * D + d], d);
+        a[w + 1] = a[w] + 0.5 * dot;
+    }
+    if (mean_force) std::copy(g.begin(), g.end(), mean_force);
+    if (A) std::copy(a.begin(), a.end(), A);
+    return SX_OK;
+    SX_GUARD_END
 }
 
 sx_status sx_metad_grid(sx_ctx *ctx, const double *lo, const double *hi, const int32_t *nbins)
@@ -1264,6 +1426,7 @@ sx_status sx_abf_config(sx_ctx *ctx, const double *lo, const double *hi, const i
     if (D < 1) return fail(ctx, SX_ESTATE, "define the CVs before the method");
     if (D > kMaxBiasDim) return fail(ctx, SX_EINVAL, "ABF supports at most 3 CVs");
     if (ctx->method == M_METAD) return fail(ctx, SX_EINVAL, "metadynamics already configured on this context");
+    if (ctx->method == M_HARMONIC) return fail(ctx, SX_EINVAL, "a harmonic bias is already configured on this context");
     if (!lo || !hi || !nbins) return fail(ctx, SX_EINVAL, "NULL grid argument");
     if (n_threshold < 0) return fail(ctx, SX_EINVAL, "threshold must be >= 0");
     int64_t tot = 1;
@@ -1324,6 +1487,8 @@ sx_status sx_bind(sx_ctx *ctx, void *dev_state, size_t state_bytes, void *dev_ws
         return hipMemcpyAsync(ctx->ws + s.off, src, bytes, hipMemcpyHostToDevice, ctx->stream);
     };
     e = up(p.w_atom_off, p.atom_off.data(), sizeof(int64_t) * (p.W + 1));
+    if (e == hipSuccess && ctx->method == M_HARMONIC)
+        e = up(p.w_hbXi0, ctx->hb_xi0.data(), sizeof(double) * ctx->hb_xi0.size());
     if (e == hipSuccess) e = up(p.w_slot_atom, p.slot_atom.data(), sizeof(int32_t) * p.nslots);
     if (e == hipSuccess) e = up(p.w_slot_cv, p.slot_cv.data(), sizeof(int32_t) * p.nslots);
     if (e == hipSuccess) e = up(p.w_touched, p.touched.data(), sizeof(int32_t) * p.U);

@@ -189,6 +189,27 @@ struct GridArgs {
     ForceView F;
 };
 
+// Harmonic bias k/2 (xi - xi0_w)^2 per walker (umbrella windows) and the
+// windows' running sums for umbrella integration.
+struct HarmonicArgs {
+    int32_t D, accumulate;
+    double period[kMaxBiasDim];           // 0: not periodic
+    double k[kMaxBiasDim];
+    const double *xi0;                    // W x D window centres
+    const double *xi;                     // W x D
+    double *V_ws, *dV_ws, *xi_out, *V_out, *dV_out;  // outputs may be null
+    int64_t *n;                           // W samples
+    double *s1, *s2;                      // W x D sums of D, W x D x D sums of D D^T
+    int64_t *dstep;
+    int32_t count_step;
+    int64_t step;
+    uint32_t *flags;
+    int32_t do_forces, nslots;
+    const float *J;
+    WalkerTabs tabs;
+    ForceView F;
+};
+
 struct SharedArgs {
     int32_t D;
     float *c[kMaxBiasDim];
@@ -295,6 +316,7 @@ hipError_t launch_abf(const AbfArgs &a, hipStream_t s);
 // grid bias: a step (read-back, outputs, deposit, forces, then the step's
 // hills onto the grids); rebuilding grids l0 .. l0 + nl - 1 from their whole
 // lists; read-back at n points of grid l
+hipError_t launch_harmonic(const HarmonicArgs &a, hipStream_t s);
 hipError_t launch_grid_step(const GridArgs &g, hipStream_t s);
 hipError_t launch_grid_rebuild(const GridArgs &g, int32_t l0, int32_t nl, hipStream_t s);
 hipError_t launch_grid_eval(const GridArgs &g, int32_t l, const double *xi, int64_t n, double *V, double *dV,
