@@ -164,6 +164,22 @@ sx_status sx_metad_config(sx_ctx *ctx, const double *sigma, double w, double tem
 sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double delta_T, int32_t stride,
                              int64_t capacity);
 
+/* Free energy from a metadynamics bias (Sec. 2.1.5) at n points xi
+ * (device, n x D): F = -V (plain) or, well-tempered, F = -(T + dT)/dT V with
+ * V the exact hill sum of `walker`'s list (0 for a shared list) and T the
+ * simulation temperature (ignored for plain metadynamics).  F_out (device,
+ * n); not shifted.  Stream-ordered.  ESTATE: no metadynamics. */
+sx_status sx_fes_metad(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double temperature, double *F_out);
+/* Free energy A from `walker`'s ABF grid (Sec. 2.1.4) at the bin centres:
+ * the mean forces g = Fsum / N of the visited bins integrated by least
+ * squares over pairs of neighbouring visited bins along each CV,
+ * ((A_j - A_i)/delta - (g_i + g_j)/2)^2 summed (periodic CVs wrap; the
+ * trapezoidal rule in 1-D), solved by conjugate gradients in FP64 on the
+ * host; shifted to min 0 over the visited bins, NaN at unvisited ones.
+ * A: host, nbins_total.  Assumes the visited bins are connected.
+ * Synchronous.  ESTATE: no ABF. */
+sx_status sx_abf_fes(sx_ctx *ctx, int32_t walker, double *A);
+
 /* Harmonic biasing (Sec. 2.1.1) with one window per walker, the sampling
  * of umbrella sampling / umbrella integration (Sec. 2.1.2).  k: D spring
  * constants (> 0; kJ/mol per CV unit squared); centers: n_walkers x D

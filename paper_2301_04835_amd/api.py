@@ -54,6 +54,7 @@ class Sampler:
         self.state = None
         self.ws = None
         self.n_walkers = 1
+        self._per = []  # periodicity of each CV as added (dihedrals)
         self.n_atoms = None
 
     # ------------------------------------------------------------ plumbing
@@ -84,16 +85,22 @@ class Sampler:
         a, p = _host(idx, np.int32)
         assert a.size == 4
         self._check(self.L.sx_add_cv_dihedral(self.h, p))
+        self._per.append(True)
 
     def add_gyration(self, idx):
         a, p = _host(idx, np.int32)
         self._check(self.L.sx_add_cv_gyration(self.h, p, a.size))
+        self._per.append(False)
 
     def add_coordination(self, a, b, r0, n=6, m=12, rcut=0.0, normalize=False):
         aa, pa = _host(a, np.int32)
         bb, pb = _host(b, np.int32)
         self._check(self.L.sx_add_cv_coordination(self.h, pa, aa.size, pb, bb.size, float(r0), int(n), int(m),
                                                   float(rcut), int(bool(normalize))))
+        self._per.append(False)
+
+    def _periodic(self):
+        return list(self._per)
 
     def add_cvs(self, cvs):
         """Add CVs from the dict description used by the synthetic inputs."""
@@ -145,6 +152,28 @@ class Sampler:
     def metad_dT(self, sigma, height, delta_T, stride=500, capacity=4096):
         s, p = _host(sigma, np.float64)
         self._check(self.L.sx_metad_config_dT(self.h, p, float(height), float(delta_T), int(stride), int(capacity)))
+
+    def metad_fes(self, lo, hi, nbins, temperature=300.0, walker=0):
+        """Free energy of the metadynamics bias at the nodes of an analysis
+        grid (per CV nbins nodes over a periodic range, nbins + 1 up to hi
+        otherwise; row-major), shifted to min 0; host array of the grid's
+        shape.  See sx_fes_metad."""
+        periodic = self._periodic()
+        axes = [np.linspace(l, h, n, endpoint=False) if p else np.linspace(l, h, n + 1)
+                for l, h, n, p in zip(lo, hi, nbins, periodic)]
+        mesh = np.meshgrid(*axes, indexing="ij")
+        X = torch.from_numpy(np.stack([m.reshape(-1) for m in mesh], 1)).to(self.device)
+        F = torch.empty(X.shape[0], dtype=torch.float64, device=self.device)
+        self._check(self.L.sx_fes_metad(self.h, int(walker), _ptr(X), X.shape[0], float(temperature), _ptr(F)))
+        F = F.cpu().numpy()
+        return (F - F.min()).reshape([len(a) for a in axes])
+
+    def abf_fes(self, walker=0):
+        """Free energy at the ABF bin centres (see sx_abf_fes): host array of
+        the grid's shape, NaN at unvisited bins."""
+        A = np.empty(int(np.prod(self.nbins)))
+        self._check(self.L.sx_abf_fes(self.h, int(walker), A.ctypes.data_as(ctypes.c_void_p)))
+        return A.reshape(self.nbins)
 
     def harmonic(self, k, centers):
         """Harmonic bias with one window centre per walker (centers: W x D)."""

@@ -197,7 +197,20 @@ __global__ void __launch_bounds__(kBlock) k_grid_eval(GridArgs g, int32_t l, con
         for (int d = 0; d < g.D; ++d) dV[i * g.D + d] = G[d];
 }
 
+__global__ void __launch_bounds__(kBlock) k_scale_f64(double *x, int64_t n, double a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] *= a;
+}
+
 }  // namespace
+
+hipError_t launch_scale_f64(double *x, int64_t n, double a, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_f64, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, n, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_grid_step(const GridArgs &g, hipStream_t s)
 {

@@ -20,6 +20,7 @@
 #include <sstream>
 #include <string>
 #include <vector>
+#include <limits>
 
 #include "sx_internal.h"
 
@@ -2057,6 +2058,107 @@ sx_status sx_abf_grid_get(sx_ctx *ctx, int32_t walker, uint32_t *N, double *Fsum
                       sizeof(double) * p.nbins_total * p.D, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(ctx, e, "grid read");
     return SX_OK;
+}
+
+// ---------------------------------------------------------------- analysis
+sx_status sx_fes_metad(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double temperature, double *F_out)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
+    if (!F_out && n > 0) return fail(ctx, SX_EINVAL, "NULL output");
+    const bool wt = ctx->kdT > 0 && std::isfinite(ctx->kdT);
+    if (wt && !(temperature > 0 && std::isfinite(temperature)))
+        return fail(ctx, SX_EINVAL, "well-tempered analysis needs the temperature (> 0)");
+    if (sx_status st = sx_bias_eval(ctx, walker, xi, n, F_out, nullptr)) return st;
+    const double factor = wt ? (kBoltzmann * temperature + ctx->kdT) / ctx->kdT : 1.0;
+    hipError_t e = launch_scale_f64(F_out, n, -factor, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "free-energy scale");
+    return SX_OK;
+}
+
+sx_status sx_abf_fes(sx_ctx *ctx, int32_t walker, double *A)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    if (ctx->method != M_ABF) return fail(ctx, SX_ESTATE, "no ABF grid on this context");
+    if (!A) return fail(ctx, SX_EINVAL, "NULL output");
+    SX_GUARD_BEGIN
+    const Plan &p = ctx->plan;
+    const int D = p.D;
+    const int64_t nb = p.nbins_total;
+    std::vector<uint32_t> N(nb);
+    std::vector<double> Fs((size_t)nb * D);
+    if (sx_status st = sx_abf_grid_get(ctx, walker, N.data(), Fs.data())) return st;
+    // unknowns: the visited bins; equations: one per pair of neighbouring
+    // visited bins along a CV, (A_j - A_i) / delta - (g_i + g_j) / 2 = 0
+    std::vector<int64_t> idx(nb, -1);
+    int64_t nv = 0;
+    for (int64_t b = 0; b < nb; ++b)
+        if (N[b] > 0) idx[b] = nv++;
+    std::vector<int64_t> stride(D);
+    for (int d = D - 1, st = 1; d >= 0; st *= ctx->nbins[d], --d) stride[d] = st;
+    std::vector<double> delta(D);
+    for (int d = 0; d < D; ++d) delta[d] = (ctx->hi[d] - ctx->lo[d]) / ctx->nbins[d];
+    struct Edge {
+        int64_t i, j;
+        double w, r;  // 1 / delta, mean gradient
+    };
+    std::vector<Edge> edges;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (N[b] == 0) continue;
+        for (int d = 0; d < D; ++d) {
+            const int64_t c = (b / stride[d]) % ctx->nbins[d];
+            int64_t c1 = c + 1;
+            if (c1 == ctx->nbins[d]) {
+                if (!cv_periodic(ctx->cvs[d])) continue;
+                c1 = 0;
+            }
+            const int64_t nbr = b + (c1 - c) * stride[d];
+            if (N[nbr] == 0) continue;
+            const double gi = Fs[(size_t)b * D + d] / N[b], gj = Fs[(size_t)nbr * D + d] / N[nbr];
+            edges.push_back({idx[b], idx[nbr], 1.0 / delta[d], 0.5 * (gi + gj)});
+        }
+    }
+    // normal equations L x = B of the least squares, by conjugate gradients
+    // from x = 0 (B lies in the range of L, so CG keeps to it and reaches
+    // the minimum-norm solution; the shift below fixes the constant)
+    std::vector<double> x(nv, 0.0), r(nv, 0.0), q(nv), Lq(nv);
+    for (const Edge &e : edges) {
+        r[e.j] += e.w * e.r;
+        r[e.i] -= e.w * e.r;
+    }
+    auto apply = [&](const std::vector<double> &v, std::vector<double> &out) {
+        std::fill(out.begin(), out.end(), 0.0);
+        for (const Edge &e : edges) {
+            const double t = e.w * e.w * (v[e.j] - v[e.i]);
+            out[e.j] += t;
+            out[e.i] -= t;
+        }
+    };
+    q = r;
+    double rr = 0.0, r0 = 0.0;
+    for (double v : r) rr += v * v;
+    r0 = rr;
+    for (int it = 0; it < 20 * (int)std::max<int64_t>(nv, 10) && rr > 1e-28 * std::max(r0, 1e-300); ++it) {
+        apply(q, Lq);
+        double qLq = 0.0;
+        for (int64_t i = 0; i < nv; ++i) qLq += q[i] * Lq[i];
+        if (!(qLq > 0)) break;
+        const double alpha = rr / qLq;
+        double rr2 = 0.0;
+        for (int64_t i = 0; i < nv; ++i) {
+            x[i] += alpha * q[i];
+            r[i] -= alpha * Lq[i];
+            rr2 += r[i] * r[i];
+        }
+        const double beta = rr2 / rr;
+        rr = rr2;
+        for (int64_t i = 0; i < nv; ++i) q[i] = r[i] + beta * q[i];
+    }
+    double mn = std::numeric_limits<double>::infinity();
+    for (double v : x) mn = std::min(mn, v);
+    for (int64_t b = 0; b < nb; ++b) A[b] = N[b] > 0 ? x[idx[b]] - mn : std::numeric_limits<double>::quiet_NaN();
+    return SX_OK;
+    SX_GUARD_END
 }
 
 sx_status sx_get_step(sx_ctx *ctx, int64_t *step)

@@ -318,6 +318,8 @@ hipError_t launch_abf(const AbfArgs &a, hipStream_t s);
 // lists; read-back at n points of grid l
 hipError_t launch_harmonic(const HarmonicArgs &a, hipStream_t s);
 hipError_t launch_grid_step(const GridArgs &g, hipStream_t s);
+// x[i] *= a for i < n (device FP64)
+hipError_t launch_scale_f64(double *x, int64_t n, double a, hipStream_t s);
 hipError_t launch_grid_rebuild(const GridArgs &g, int32_t l0, int32_t nl, hipStream_t s);
 hipError_t launch_grid_eval(const GridArgs &g, int32_t l, const double *xi, int64_t n, double *V, double *dV,
                             hipStream_t s);
