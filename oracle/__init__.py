@@ -33,6 +33,8 @@ from .methods import (  # noqa: F401
     AbfGrid,
     abf_bin,
     abf_step,
+    abf_step_momentum,
+    abf_momentum_wp,
     abf_theta,
     cv_eval,
     cv_periods,

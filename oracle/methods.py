@@ -142,3 +142,41 @@ def abf_step(grid, xi, J, Fsys):
         grid.N[k] += 1
         grid.Fsum[k] += theta
     return b, chain_rule(b, J), k, theta
+
+
+# ------------------------------------------------------------------------- #
+# ABF with the momentum-derivative estimator (Darve et al. 2008, the         #
+# algorithm the paper's ABF follows, Sec. 2.1.4).  Reading: with masses M,   #
+# the CV-space momentum is W p = (J M^-1 J^T)^-1 J M^-1 p; over a step of    #
+# length dt it changes by the system's generalised force plus the bias b     #
+# applied during that step, so                                              #
+#   theta_t = b_{t-1} - ((W p)_t - (W p)_{t-1}) / dt                         #
+# estimates dA/dxi (backward difference, binned at the current xi); the      #
+# first step only records (W p)_0 and b_0.                                   #
+# ------------------------------------------------------------------------- #
+def abf_momentum_wp(J, p, inv_mass):
+    """W p = (J M^-1 J^T)^-1 J M^-1 p (J: D x natoms x 3, p: natoms x 3,
+    inv_mass: natoms)."""
+    Jm = J * np.asarray(inv_mass, dtype=np.float64)[None, :, None]
+    G = Jm.reshape(J.shape[0], -1) @ J.reshape(J.shape[0], -1).T
+    u = Jm.reshape(J.shape[0], -1) @ np.asarray(p, dtype=np.float64).reshape(-1)
+    return np.linalg.solve(G, u)
+
+
+def abf_step_momentum(grid, xi, J, p, inv_mass, dt, prev):
+    """One ABF step with the momentum estimator.  prev: (W p, b) of the
+    previous step or None.  Returns (b, per-atom biasing force, bin, theta
+    or None, (W p, b) for the next step)."""
+    D = len(xi)
+    k = abf_bin(xi, grid.lo, grid.hi, grid.nbins, grid.periodic)
+    wp = abf_momentum_wp(J, p, inv_mass)
+    theta = None if prev is None else prev[1] - (wp - prev[0]) / dt
+    if k < 0:
+        b = np.zeros(D)
+    else:
+        den = max(int(grid.N[k]), grid.n_threshold)
+        b = grid.Fsum[k] / den if den > 0 else np.zeros(D)
+        if theta is not None:
+            grid.N[k] += 1
+            grid.Fsum[k] += theta
+    return b, chain_rule(b, J), k, theta, (wp, b)
