@@ -69,7 +69,7 @@ def build_context(d, p):
     return s, pos, forces
 
 
-TRAFFIC_SOURCES = ("k_bias.hip", "dev_cv.h", "dev_gather.h")
+TRAFFIC_SOURCES = ("k_bias.hip", "dev_cv.h", "dev_gather.h", "dev_reduce.h")
 
 
 def kernel_sources_sha():

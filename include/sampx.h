@@ -164,6 +164,21 @@ sx_status sx_metad_config(sx_ctx *ctx, const double *sigma, double w, double tem
 sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double delta_T, int32_t stride,
                              int64_t capacity);
 
+/* ABF with the momentum-derivative estimator (Darve et al. 2008, the
+ * algorithm the ABF of Sec. 2.1.4 follows) instead of the projected system
+ * force.  masses: n_atoms (all walkers' atoms, > 0; host, copied); dt: the
+ * time between consecutive sx_step calls.  sx_step's sys_forces argument
+ * then carries the atoms' momenta p (float32, the layout of pos), and per
+ * walker
+ *   W p   = (J M^-1 J^T)^-1 J M^-1 p          (CV-space momentum)
+ *   theta = b_prev - (W p - (W p)_prev) / dt   (estimate of dA/dxi)
+ * with b_prev the bias of the previous step; the walker's first step adds
+ * no sample.  The previous W p and bias live in the state.  masses NULL and
+ * n_atoms 0: back to the projected force.  sx_bind fails with EINVAL
+ * unless ABF is configured and n_atoms equals the walkers' total.  Before
+ * sx_bind. */
+sx_status sx_abf_momentum(sx_ctx *ctx, double dt, const double *masses, int64_t n_atoms);
+
 /* Free energy from a metadynamics bias (Sec. 2.1.5) at n points xi
  * (device, n x D): F = -V (plain) or, well-tempered, F = -(T + dT)/dT V with
  * V the exact hill sum of `walker`'s list (0 for a shared list) and T the

@@ -153,6 +153,12 @@ class Sampler:
         s, p = _host(sigma, np.float64)
         self._check(self.L.sx_metad_config_dT(self.h, p, float(height), float(delta_T), int(stride), int(capacity)))
 
+    def abf_momentum(self, dt, masses):
+        """Use the momentum-derivative ABF estimator (see sx_abf_momentum);
+        step() then takes the momenta as sys_forces."""
+        m, pm = _host(masses, np.float64)
+        self._check(self.L.sx_abf_momentum(self.h, float(dt), pm, m.size))
+
     def metad_fes(self, lo, hi, nbins, temperature=300.0, walker=0):
         """Free energy of the metadynamics bias at the nodes of an analysis
         grid (per CV nbins nodes over a periodic range, nbins + 1 up to hi

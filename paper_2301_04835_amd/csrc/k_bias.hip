@@ -1,6 +1,6 @@
 // Bias kernels: the metadynamics hill sum with well-tempered deposition
-// (Sec. 2.1.5), the adaptive-biasing-force grid (Sec. 2.1.4), and the
-// atomic-free force gather that adds the bias to the engine's forces (Sec. 2).
+// (Sec. 2.1.5) and the atomic-free force gather that adds a bias to the
+// engine's forces (Sec. 2).
 //
 // Hill sum over private hill lists (one list per walker), two kernels:
 //   A  k_hill_tiles: a static table of tiles (walker, first hill), each
@@ -23,32 +23,11 @@
 //      only cross-workgroup synchronisation: no fences, no atomics.
 #include "dev_cv.h"
 #include "dev_gather.h"
+#include "dev_reduce.h"
 
 namespace sx {
 namespace {
 
-template <int N>
-__device__ __forceinline__ void block_sum0(double (&v)[N], double *lds /* N * kBlock/64 */)
-{
-    // fixed tree: wave butterfly, then waves in index order; result in thread 0
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < N; ++k) lds[wv * N + k] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            double s = lds[k];
-            for (int q = 1; q < kBlock / 64; ++q) s += lds[q * N + k];
-            v[k] = s;
-        }
-    }
-    __syncthreads();
-}
 
 // Gaussian term of one hill: returns h exp(-sum_d D_d^2/(2 sigma_d^2)) and
 // the wrapped displacements D_d (float).  The difference xi - c and its
@@ -426,115 +405,6 @@ hipError_t launch_hill_dd(const HillArgs &a, const CvSet &cs, const PosView &pos
                   : launch_hill_d<D, false>(a, cs, pos, grid, s, which);
 }
 
-// ----------------------------------------------------------------- ABF grid
-// One workgroup per walker.  theta = -(J J^T)^{-1} J F from the per-atom
-// Jacobian rows (slots of one atom and one CV summed), FP64 reductions.
-__global__ void __launch_bounds__(kBlock) k_abf(AbfArgs a)
-{
-    constexpr int MD = kMaxBiasDim;
-    __shared__ double lds[(MD * MD + MD) * (kBlock / 64)];
-    __shared__ double s_coef[kMaxCv];
-    const int32_t w = blockIdx.x;
-    const int D = a.D;
-    const WalkerTabs &t = a.tabs;
-    const int64_t jb = (int64_t)w * a.nslots, ab = t.atom_off[w];
-    double acc[MD * MD + MD];
-#pragma unroll
-    for (int j = 0; j < MD * MD + MD; ++j) acc[j] = 0.0;
-    for (int u = threadIdx.x; u < t.U; u += blockDim.x) {
-        double jv[MD][3];
-#pragma unroll
-        for (int d = 0; d < MD; ++d) jv[d][0] = jv[d][1] = jv[d][2] = 0.0;
-        for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
-            const int32_t s = t.inv_slot[q];
-            const int d = t.slot_cv[s];
-            const float *js = a.J + (jb + s) * 3;
-#pragma unroll
-            for (int dd = 0; dd < MD; ++dd)
-                if (dd == d) {
-                    jv[dd][0] += js[0];
-                    jv[dd][1] += js[1];
-                    jv[dd][2] += js[2];
-                }
-        }
-        const float *fp = static_cast<const float *>(a.Fsys.ptr) + (ab + t.touched[u]) * a.Fsys.sa;
-        const double f[3] = {fp[0], fp[a.Fsys.sk], fp[2 * a.Fsys.sk]};
-#pragma unroll
-        for (int d = 0; d < MD; ++d) {
-#pragma unroll
-            for (int e = 0; e < MD; ++e)
-                acc[d * MD + e] += jv[d][0] * jv[e][0] + jv[d][1] * jv[e][1] + jv[d][2] * jv[e][2];
-            acc[MD * MD + d] += jv[d][0] * f[0] + jv[d][1] * f[1] + jv[d][2] * f[2];
-        }
-    }
-    block_sum0<MD * MD + MD>(acc, lds);
-    if (threadIdx.x == 0) {
-        // solve G theta = -JF by Gaussian elimination with partial pivoting
-        double G[MD][MD + 1];
-        for (int d = 0; d < D; ++d) {
-            for (int e = 0; e < D; ++e) G[d][e] = acc[d * MD + e];
-            G[d][D] = -acc[MD * MD + d];
-        }
-        for (int col = 0; col < D; ++col) {
-            int piv = col;
-            for (int r = col + 1; r < D; ++r)
-                if (fabs(G[r][col]) > fabs(G[piv][col])) piv = r;
-            if (piv != col)
-                for (int e = 0; e <= D; ++e) {
-                    double tmp = G[col][e];
-                    G[col][e] = G[piv][e];
-                    G[piv][e] = tmp;
-                }
-            for (int r = col + 1; r < D; ++r) {
-                const double fct = G[r][col] / G[col][col];
-                for (int e = col; e <= D; ++e) G[r][e] -= fct * G[col][e];
-            }
-        }
-        double theta[MD];
-        for (int d = D - 1; d >= 0; --d) {
-            double s = G[d][D];
-            for (int e = d + 1; e < D; ++e) s -= G[d][e] * theta[e];
-            theta[d] = s / G[d][d];
-        }
-        // bin of xi (row-major, first CV slowest)
-        int64_t k = 0;
-        bool inr = true;
-        for (int d = 0; d < D; ++d) {
-            const double x = a.xi[(int64_t)w * D + d];
-            int64_t i = (int64_t)floor((x - a.lo[d]) / a.delta[d]);
-            if (a.periodic[d]) {
-                i %= a.nbins[d];
-                if (i < 0) i += a.nbins[d];
-            } else if (i < 0 || i >= a.nbins[d]) {
-                inr = false;
-            }
-            k = k * a.nbins[d] + i;
-        }
-        bool finite = true;
-        for (int d = 0; d < D; ++d) finite = finite && isfinite(theta[d]);
-        if (!finite) atomicOr(a.flags, kFlagNonFinite);
-        double b[MD] = {0.0, 0.0, 0.0};
-        if (inr && finite) {
-            uint32_t *Nk = a.N + (int64_t)w * a.nbins_total + k;
-            double *Fk = a.Fsum + ((int64_t)w * a.nbins_total + k) * D;
-            const uint32_t cnt = *Nk;
-            const double den = (double)max((int64_t)cnt, (int64_t)a.n_threshold);
-            for (int d = 0; d < D; ++d) b[d] = den > 0.0 ? Fk[d] / den : 0.0;
-            *Nk = cnt + 1u;
-            for (int d = 0; d < D; ++d) Fk[d] += theta[d];
-        }
-        for (int d = 0; d < D; ++d) {
-            s_coef[d] = b[d];
-            if (a.dV_out) a.dV_out[(int64_t)w * D + d] = -b[d];
-            if (a.xi_out) a.xi_out[(int64_t)w * D + d] = a.xi[(int64_t)w * D + d];
-        }
-        if (a.V_out) a.V_out[w] = 0.0;
-        if (w == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
-    }
-    __syncthreads();
-    gather_forces(t, a.J + jb * 3, w, s_coef, a.F);
-}
-
 // One lane per (walker, touched atom): out += sign * sum_s coef[w][cv(s)] J_s.
 __global__ void __launch_bounds__(kBlock) k_gather(WalkerTabs t, const float *J, int32_t nslots, int32_t D,
                                                     const double *coef, double sign, ForceView out)
@@ -583,11 +453,6 @@ hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView
     }
 }
 
-hipError_t launch_abf(const AbfArgs &a, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_abf, dim3(a.tabs.W), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
 
 hipError_t launch_gather(const WalkerTabs &t, const float *J, int32_t nslots, int32_t D, const double *coef,
                          double coef_sign, ForceView out, hipStream_t s)

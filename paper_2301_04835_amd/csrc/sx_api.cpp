@@ -72,6 +72,9 @@ struct Plan {
     Sub s_mgV, s_mgG, s_mgPend;
     // harmonic windows: sample counts and sums (state), centres (workspace)
     Sub s_umN, s_umS1, s_umS2, w_hbXi0;
+    // ABF momentum estimator: previous W p, bias and flag per walker (state),
+    // inverse masses per atom (workspace)
+    Sub s_abfWp, s_abfB, s_abfHas, w_invm;
     size_t state_bytes = 0;
     // cell lists of coordination numbers
     CellArgs cell{};
@@ -114,6 +117,9 @@ struct sx_ctx {
     double lo[kMaxBiasDim] = {0, 0, 0}, hi[kMaxBiasDim] = {0, 0, 0};
     int32_t nbins[kMaxBiasDim] = {0, 0, 0};
     int32_t n_threshold = 0;
+    int32_t abf_est = 0;  // 0 projected force, 1 momentum derivative
+    double abf_dt = 0.0;
+    std::vector<double> abf_masses;
     // harmonic bias: spring constants and one centre per walker (W x D)
     double hb_k[kMaxBiasDim] = {0, 0, 0};
     std::vector<double> hb_xi0;
@@ -470,6 +476,14 @@ sx_status make_plan(sx_ctx *c)
     p.s_h = ls.take(sizeof(float) * total);
     p.s_N = ls.take(sizeof(uint32_t) * p.W * p.nbins_total);
     p.s_Fsum = ls.take(sizeof(double) * p.W * p.nbins_total * p.D);
+    if (c->abf_est == 1) {
+        if (c->method != M_ABF) return fail(c, SX_EINVAL, "the momentum estimator needs ABF (sx_abf_config)");
+        if ((int64_t)c->abf_masses.size() != p.total_atoms)
+            return fail(c, SX_EINVAL, "one mass per atom of all walkers is needed");
+        p.s_abfWp = ls.take(sizeof(double) * p.W * p.D);
+        p.s_abfB = ls.take(sizeof(double) * p.W * p.D);
+        p.s_abfHas = ls.take(sizeof(int32_t) * p.W);
+    }
     if (c->method == M_HARMONIC) {
         if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "a harmonic bias spans at most 3 CVs");
         if ((int64_t)c->hb_xi0.size() != (int64_t)p.W * p.D)
@@ -525,6 +539,7 @@ sx_status make_plan(sx_ctx *c)
     p.w_tiles = lw.take(sizeof(TileRec) * p.ntiles_max);
     p.w_wrec = lw.take(sizeof(WalkerRec) * p.W);
     p.w_hbXi0 = lw.take(c->method == M_HARMONIC ? sizeof(double) * p.W * p.D : 0);
+    p.w_invm = lw.take(c->abf_est == 1 ? sizeof(double) * p.total_atoms : 0);
     p.w_slot_atom = lw.take(sizeof(int32_t) * p.nslots);
     p.w_slot_cv = lw.take(sizeof(int32_t) * p.nslots);
     p.w_touched = lw.take(sizeof(int32_t) * p.U);
@@ -958,7 +973,7 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         if (e != hipSuccess) return hip_fail(c, e, "harmonic kernel");
         if (sx_status st = cell_forces(c, pv, a.dV_ws, -1.0, forces, layout)) return st;
     } else {
-        if (!sys_forces) return fail(c, SX_EINVAL, "ABF needs the system forces");
+        if (!sys_forces) return fail(c, SX_EINVAL, "ABF needs the system forces (momenta for the momentum estimator)");
         if (!forces) return fail(c, SX_EINVAL, "ABF needs the force buffer");
         AbfArgs a{};
         a.D = p.D;
@@ -971,6 +986,14 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.N = at<uint32_t>(c->state, p.s_N);
         a.Fsum = at<double>(c->state, p.s_Fsum);
         a.nbins_total = p.nbins_total;
+        a.estimator = c->abf_est;
+        a.dt = c->abf_dt;
+        if (c->abf_est == 1) {
+            a.inv_mass = at<double>(c->ws, p.w_invm);
+            a.Wp_prev = at<double>(c->state, p.s_abfWp);
+            a.b_prev = at<double>(c->state, p.s_abfB);
+            a.has_prev = at<int32_t>(c->state, p.s_abfHas);
+        }
         for (int d = 0; d < p.D; ++d) {
             a.lo[d] = c->lo[d];
             a.delta[d] = (c->hi[d] - c->lo[d]) / c->nbins[d];
@@ -1240,6 +1263,27 @@ sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double 
     return metad_common(ctx, sigma, w, kdT, stride, capacity);
 }
 
+sx_status sx_abf_momentum(sx_ctx *ctx, double dt, const double *masses, int64_t n_atoms)
+{
+    if (!ctx) return SX_EINVAL;
+    if (sx_status s = require_unbound(ctx)) return s;
+    if (!masses && n_atoms == 0) {  // back to the projected-force estimator
+        ctx->abf_est = 0;
+        ctx->abf_masses.clear();
+        invalidate(ctx);
+        return SX_OK;
+    }
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, SX_EINVAL, "dt must be finite and > 0");
+    if (!masses || n_atoms < 1) return fail(ctx, SX_EINVAL, "masses needed");
+    for (int64_t i = 0; i < n_atoms; ++i)
+        if (!(masses[i] > 0) || !std::isfinite(masses[i])) return fail(ctx, SX_EINVAL, "masses must be finite and > 0");
+    ctx->abf_masses.assign(masses, masses + n_atoms);
+    ctx->abf_dt = dt;
+    ctx->abf_est = 1;
+    invalidate(ctx);
+    return SX_OK;
+}
+
 sx_status sx_harmonic_config(sx_ctx *ctx, const double *k, const double *centers, int32_t n_walkers)
 {
     if (!ctx) return SX_EINVAL;
@@ -1490,6 +1534,12 @@ sx_status sx_bind(sx_ctx *ctx, void *dev_state, size_t state_bytes, void *dev_ws
     e = up(p.w_atom_off, p.atom_off.data(), sizeof(int64_t) * (p.W + 1));
     if (e == hipSuccess && ctx->method == M_HARMONIC)
         e = up(p.w_hbXi0, ctx->hb_xi0.data(), sizeof(double) * ctx->hb_xi0.size());
+    std::vector<double> invm;
+    if (e == hipSuccess && ctx->abf_est == 1) {
+        invm.resize(ctx->abf_masses.size());
+        for (size_t i = 0; i < invm.size(); ++i) invm[i] = 1.0 / ctx->abf_masses[i];
+        e = up(p.w_invm, invm.data(), sizeof(double) * invm.size());
+    }
     if (e == hipSuccess) e = up(p.w_slot_atom, p.slot_atom.data(), sizeof(int32_t) * p.nslots);
     if (e == hipSuccess) e = up(p.w_slot_cv, p.slot_cv.data(), sizeof(int32_t) * p.nslots);
     if (e == hipSuccess) e = up(p.w_touched, p.touched.data(), sizeof(int32_t) * p.U);

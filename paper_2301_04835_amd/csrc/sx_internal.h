@@ -155,6 +155,15 @@ struct AbfArgs {
     uint32_t *flags;
     int64_t step;
     int64_t *dstep;
+    // estimator 0: theta from the projected system force (unit masses; Fsys
+    // holds the system forces); 1: from the time derivative of the CV-space
+    // momentum (Fsys holds the momenta; inverse masses per atom, step dt, and
+    // per walker the previous step's W p, bias and whether there was one)
+    int32_t estimator;
+    double dt;
+    const double *inv_mass;   // total atoms
+    double *Wp_prev, *b_prev; // W x D
+    int32_t *has_prev;        // W
 };
 
 // Hill sum over one shared list at nq query points.
