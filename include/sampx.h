@@ -164,6 +164,24 @@ sx_status sx_metad_config(sx_ctx *ctx, const double *sigma, double w, double tem
 sx_status sx_metad_config_dT(sx_ctx *ctx, const double *sigma, double w, double delta_T, int32_t stride,
                              int64_t capacity);
 
+/* FUNN (Sec. 2.1.8, force-biasing using neural networks): the context's
+ * network (sx_surrogate_config, which on an ABF context sets up FUNN's
+ * network; its features and output scale as for the surrogate) is fitted by
+ * Adam, gradient term only (alpha 0, beta 1), to `walker`'s ABF mean
+ * forces Fsum / N at the centres of the visited bins (bin order; the
+ * batches cycle through them), `steps` steps of `batch` with a cosine decay
+ * from lr to lr_final.  n_samples (host, may be NULL): visited bins used.
+ * loss_out as sx_surrogate_fit.  Synchronous.  ESTATE: not ABF, no
+ * parameters, no visited bin; EINVAL: more visited bins than max_samples. */
+sx_status sx_funn_fit(sx_ctx *ctx, int32_t walker, int32_t batch, int32_t steps, double lr, double lr_final,
+                      int64_t *n_samples, double *loss_out);
+/* on != 0: every ABF step biases with the network's gradient at xi (one
+ * network for all walkers; inside the grid's range) instead of
+ * Fsum / max(N, N_thr); samples keep accumulating into the grid, so the
+ * network can be refitted as the run advances.  ESTATE: not ABF or no
+ * parameters. */
+sx_status sx_funn_enable(sx_ctx *ctx, int32_t on);
+
 /* ABF with the momentum-derivative estimator (Darve et al. 2008, the
  * algorithm the ABF of Sec. 2.1.4 follows) instead of the projected system
  * force.  masses: n_atoms (all walkers' atoms, > 0; host, copied); dt: the

@@ -68,6 +68,8 @@ SIGNATURES = {
     "sx_fes_metad": (i32, [P, i32, P, ctypes.c_int64, f64, P]),
     "sx_abf_fes": (i32, [P, i32, P]),
     "sx_abf_momentum": (i32, [P, f64, P, ctypes.c_int64]),
+    "sx_funn_fit": (i32, [P, i32, i32, i32, f64, f64, P, P]),
+    "sx_funn_enable": (i32, [P, i32]),
     "sx_umbrella_reset": (i32, [P]),
     "sx_umbrella_stats": (i32, [P, P, P, P]),
     "sx_umbrella_integrate": (i32, [P, P, P]),

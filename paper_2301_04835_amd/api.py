@@ -153,6 +153,17 @@ class Sampler:
         s, p = _host(sigma, np.float64)
         self._check(self.L.sx_metad_config_dT(self.h, p, float(height), float(delta_T), int(stride), int(capacity)))
 
+    def funn_fit(self, walker=0, batch=4096, steps=2000, lr=3e-3, lr_final=1e-5):
+        """Fit the network to a walker's ABF mean forces (see sx_funn_fit);
+        returns (visited bins used, final loss)."""
+        n, loss = ctypes.c_int64(), ctypes.c_double()
+        self._check(self.L.sx_funn_fit(self.h, int(walker), int(batch), int(steps), float(lr), float(lr_final),
+                                       ctypes.byref(n), ctypes.byref(loss)))
+        return n.value, loss.value
+
+    def funn_enable(self, on=True):
+        self._check(self.L.sx_funn_enable(self.h, int(bool(on))))
+
     def abf_momentum(self, dt, masses):
         """Use the momentum-derivative ABF estimator (see sx_abf_momentum);
         step() then takes the momenta as sys_forces."""

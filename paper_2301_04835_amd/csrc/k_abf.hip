@@ -7,8 +7,10 @@
 // CV-space momentum, W = (J M^-1 J^T)^-1 J M^-1), and
 // theta = b_prev - (W p - (W p)_prev) / dt, b_prev the bias of the previous
 // step (no sample on a walker's first step).  The bias of the bin of xi is
-// Fsum / max(N, N_thr) from the samples before this step; then N += 1,
-// Fsum += theta, and the bias force is gathered onto the atoms.
+// Fsum / max(N, N_thr) from the samples before this step (with FUNN: the
+// gradient of the network fitted to the mean forces, evaluated at xi, inside
+// the grid's range); then N += 1, Fsum += theta, and the bias force is
+// gathered onto the atoms.
 #include "sx_internal.h"
 #include "dev_gather.h"
 #include "dev_reduce.h"
@@ -117,7 +119,8 @@ __global__ void __launch_bounds__(kBlock) k_abf(AbfArgs a)
             double *Fk = a.Fsum + ((int64_t)w * a.nbins_total + k) * D;
             const uint32_t cnt = *Nk;
             const double den = (double)max((int64_t)cnt, (int64_t)a.n_threshold);
-            for (int d = 0; d < D; ++d) b[d] = den > 0.0 ? Fk[d] / den : 0.0;
+            for (int d = 0; d < D; ++d)
+                b[d] = a.b_ext ? a.b_ext[(int64_t)w * D + d] : den > 0.0 ? Fk[d] / den : 0.0;
             if (sample) {
                 *Nk = cnt + 1u;
                 for (int d = 0; d < D; ++d) Fk[d] += theta[d];

@@ -151,6 +151,7 @@ struct sx_ctx {
     double sg_cert_lo[kMaxBiasDim] = {0, 0, 0}, sg_cert_inv_h[kMaxBiasDim] = {0, 0, 0};
     int64_t sg_t = 0;  // Adam steps taken since the parameters were set
     bool sg_params = false, sg_certified = false, sg_on = false;
+    bool funn_on = false;  // ABF: bias from the network's gradient
 };
 
 namespace {
@@ -510,7 +511,8 @@ sx_status make_plan(sx_ctx *c)
         p.s_mgPend = ls.take(sizeof(int32_t) * p.mg_L);
     }
     if (c->sg_H) {
-        if (c->method != M_METAD) return fail(c, SX_EINVAL, "the surrogate network fits a metadynamics bias");
+        if (c->method != M_METAD && c->method != M_ABF)
+            return fail(c, SX_EINVAL, "the network fits a metadynamics bias or ABF mean forces (FUNN)");
         if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "the surrogate takes at most 3 CVs");
         p.sgP = mlp_param_count(c->sg_H, p.D);
         p.sgCells = 1;
@@ -988,6 +990,13 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.nbins_total = p.nbins_total;
         a.estimator = c->abf_est;
         a.dt = c->abf_dt;
+        if (c->funn_on) {  // the network's gradient at xi is the bias
+            double *g = at<double>(c->ws, p.w_dV);
+            hipError_t e = launch_mlp_fwd(mlp_args(c), xi, p.W, at<double>(c->ws, p.w_V), g, nullptr, nullptr, nullptr,
+                                          nullptr, nullptr, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "FUNN network");
+            a.b_ext = g;
+        }
         if (c->abf_est == 1) {
             a.inv_mass = at<double>(c->ws, p.w_invm);
             a.Wp_prev = at<double>(c->state, p.s_abfWp);
@@ -1904,6 +1913,7 @@ sx_status sx_surrogate_train(sx_ctx *ctx, const double *xi, int64_t n, int32_t b
                              double lr_final, double *loss_out)
 {
     if (sx_status s = require_surrogate(ctx)) return s;
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "the exact bias needs metadynamics hills");
     SX_GUARD_BEGIN
     const Plan &p = ctx->plan;
     if (!ctx->sg_params) return fail(ctx, SX_ESTATE, "surrogate parameters not set");
@@ -1942,6 +1952,7 @@ sx_status sx_surrogate_train(sx_ctx *ctx, const double *xi, int64_t n, int32_t b
 sx_status sx_surrogate_certify(sx_ctx *ctx, const double *lo, const double *hi, double *certified_fraction)
 {
     if (sx_status s = require_surrogate(ctx)) return s;
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "the exact bias needs metadynamics hills");
     SX_GUARD_BEGIN
     const Plan &p = ctx->plan;
     if (!ctx->sg_params) return fail(ctx, SX_ESTATE, "surrogate parameters not set");
@@ -2006,6 +2017,7 @@ sx_status sx_surrogate_tolerance(sx_ctx *ctx, double tol_force)
 sx_status sx_surrogate_enable(sx_ctx *ctx, int32_t on)
 {
     if (sx_status s = require_surrogate(ctx)) return s;
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "the surrogate stands for a metadynamics bias (FUNN: sx_funn_enable)");
     if (on) {
         if (!ctx->sg_params || !ctx->sg_certified)
             return fail(ctx, SX_ESTATE, "the surrogate needs parameters and a certification first");
@@ -2013,6 +2025,60 @@ sx_status sx_surrogate_enable(sx_ctx *ctx, int32_t on)
             return fail(ctx, SX_ESTATE, "the surrogate replaces one bias: use a shared hill list or one walker");
     }
     ctx->sg_on = on != 0;
+    return SX_OK;
+}
+
+sx_status sx_funn_fit(sx_ctx *ctx, int32_t walker, int32_t batch, int32_t steps, double lr, double lr_final,
+                      int64_t *n_samples, double *loss_out)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    if (ctx->method != M_ABF) return fail(ctx, SX_ESTATE, "FUNN fits the ABF mean forces (sx_abf_config)");
+    SX_GUARD_BEGIN
+    const Plan &p = ctx->plan;
+    const int D = p.D;
+    if (walker < 0 || walker >= p.W) return fail(ctx, SX_EINVAL, "walker out of range");
+    std::vector<uint32_t> N(p.nbins_total);
+    std::vector<double> Fs((size_t)p.nbins_total * D);
+    if (sx_status st = sx_abf_grid_get(ctx, walker, N.data(), Fs.data())) return st;
+    // samples: the visited bins' centres and mean forces, in bin order
+    std::vector<double> X, G;
+    for (int64_t b = 0; b < p.nbins_total; ++b) {
+        if (N[b] == 0) continue;
+        int64_t r = b;
+        double c[kMaxBiasDim];
+        for (int d = D - 1; d >= 0; --d) {
+            const int64_t i = r % ctx->nbins[d];
+            r /= ctx->nbins[d];
+            c[d] = ctx->lo[d] + (i + 0.5) * (ctx->hi[d] - ctx->lo[d]) / ctx->nbins[d];
+        }
+        for (int d = 0; d < D; ++d) {
+            X.push_back(c[d]);
+            G.push_back(Fs[(size_t)b * D + d] / N[b]);
+        }
+    }
+    const int64_t n = (int64_t)(X.size() / std::max(D, 1));
+    if (n_samples) *n_samples = n;
+    if (n < 1) return fail(ctx, SX_ESTATE, "no visited bins");
+    if (n > ctx->sg_max_samples) return fail(ctx, SX_EINVAL, "more visited bins than the network's max_samples");
+    double *Xd = at<double>(ctx->ws, p.w_sgX), *Vd = at<double>(ctx->ws, p.w_sgVt), *Gd = at<double>(ctx->ws, p.w_sgGt);
+    std::vector<double> zeros(n, 0.0);
+    hipError_t e = hipMemcpy(Xd, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(Gd, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(Vd, zeros.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "FUNN sample upload");
+    const bool on = ctx->funn_on;
+    sx_status st = sx_surrogate_fit(ctx, Xd, Vd, Gd, n, batch, steps, lr, lr_final, 0.0, 1.0, loss_out);
+    ctx->funn_on = on && st == SX_OK;
+    return st;
+    SX_GUARD_END
+}
+
+sx_status sx_funn_enable(sx_ctx *ctx, int32_t on)
+{
+    if (sx_status s = require_surrogate(ctx)) return s;
+    if (ctx->method != M_ABF) return fail(ctx, SX_ESTATE, "FUNN biases ABF (sx_abf_config)");
+    if (on && !ctx->sg_params) return fail(ctx, SX_ESTATE, "the network needs parameters first");
+    ctx->funn_on = on != 0;
     return SX_OK;
 }
 

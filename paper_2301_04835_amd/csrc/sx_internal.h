@@ -164,6 +164,9 @@ struct AbfArgs {
     const double *inv_mass;   // total atoms
     double *Wp_prev, *b_prev; // W x D
     int32_t *has_prev;        // W
+    // FUNN: the bias is this W x D gradient of a network fitted to the mean
+    // forces (null: the grid's Fsum / max(N, N_thr))
+    const double *b_ext;
 };
 
 // Hill sum over one shared list at nq query points.
