@@ -489,6 +489,8 @@ sx_status make_plan(sx_ctx *c)
         if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "a harmonic bias spans at most 3 CVs");
         if ((int64_t)c->hb_xi0.size() != (int64_t)p.W * p.D)
             return fail(c, SX_EINVAL, "one harmonic centre per walker and CV is needed (W x D)");
+        for (int d = 0; d < p.D; ++d)
+            if (!(c->hb_k[d] > 0)) return fail(c, SX_EINVAL, "a spring constant per CV is needed (CVs added later?)");
         p.s_umN = ls.take(sizeof(int64_t) * p.W);
         p.s_umS1 = ls.take(sizeof(double) * p.W * p.D);
         p.s_umS2 = ls.take(sizeof(double) * p.W * p.D * p.D);
@@ -497,6 +499,8 @@ sx_status make_plan(sx_ctx *c)
         if (c->method != M_METAD) return fail(c, SX_EINVAL, "a bias grid needs metadynamics (sx_metad_config)");
         if (p.D > kMaxBiasDim) return fail(c, SX_EINVAL, "a bias grid spans at most 3 CVs");
         p.mg_N = 1;
+        for (int d = 0; d < p.D; ++d)
+            if (c->mg_nbins[d] < 2) return fail(c, SX_EINVAL, "a grid range per CV is needed (CVs added later?)");
         for (int d = 0; d < p.D; ++d) {
             if (cv_periodic(c->cvs[d]) && std::fabs((c->mg_hi[d] - c->mg_lo[d]) - kTwoPi) > 1e-9)
                 return fail(c, SX_EINVAL, "a periodic CV's grid must span one period (2 pi)");
@@ -2297,6 +2301,15 @@ static uint64_t config_hash(const sx_ctx *c)
        << c->sg_cert_n << ' ' << c->plan.sgP;
     for (int d = 0; d < c->plan.D; ++d) os << ' ' << c->sigma[d] << ' ' << c->lo[d] << ' ' << c->hi[d];
     for (auto v : c->plan.hill_cap) os << ' ' << v;
+    // bias grid, harmonic windows, ABF estimator: their state has a layout
+    // and a meaning of its own
+    os << " g" << c->mg_on;
+    if (c->mg_on)
+        for (int d = 0; d < c->plan.D; ++d) os << ' ' << c->mg_lo[d] << ' ' << c->mg_hi[d] << ' ' << c->mg_nbins[d];
+    os << " h";
+    for (int d = 0; d < c->plan.D && c->method == M_HARMONIC; ++d) os << ' ' << c->hb_k[d];
+    for (double v : c->hb_xi0) os << ' ' << v;
+    os << " a" << c->abf_est << ' ' << c->abf_dt;
     std::string s = os.str();
     uint64_t h = 1469598103934665603ull;  // FNV-1a
     for (unsigned char ch : s) {
