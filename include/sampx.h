@@ -13,7 +13,7 @@
  *     force-like callback inserted into the integrator);
  *   - methods: metadynamics and well-tempered metadynamics (Sec. 2.1.5), the
  *     adaptive biasing force (Sec. 2.1.4), multiple walkers / replicas
- *     (Sec. 2, parallel runs; Sec. 4 performance);
+ *     (Sec. 2, parallel runs; Sec. 3.2 performance);
  *   - collective variables: DihedralAngle, RadiusofGyration (Sec. 2.2) and a
  *     rational-switching coordination number.
  *
