@@ -361,6 +361,107 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     }
 }
 
+// The same finalize in one wavefront, for walkers whose force table travels
+// in the kernel arguments (at most 32 touched atoms): the tile records are
+// summed by a fixed butterfly across the wavefront (every lane ends with the
+// same bits, as each lane adds in the same order), every lane forms dV/dxi
+// itself, lane 0 writes the outputs and deposits, and lane u < U gathers
+// atom u's force -- no LDS and no barrier on the path.
+template <int D, bool FUSE>
+__global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs, PosView pos)
+{
+    const int32_t w = blockIdx.x;
+    const int lane = threadIdx.x;
+    const WalkerRec wr = ld_uniform(a.wrec + w);
+    const int64_t next_step = a.deposit == 1 ? ld_uniform(a.dstep) : 0;
+    const int32_t cnt0 = a.deposit ? a.count[w] : 0;
+    const bool small_lane = a.do_forces && lane < a.small.U;
+    SmallGather sg{0.f, 0.f, 0.f, nullptr};
+    int nent = 0;
+    int32_t cvq[kSmallPer];
+    float jr[kSmallPer][3];
+    if (small_lane) {
+        const float *Jw = a.J + (int64_t)w * a.nslots * 3;
+        nent = a.small.nent[lane];
+        sg.dst = a.F.ptr + (wr.aoff + a.small.touched[lane]) * a.F.sa;
+        sg.f0 = sg.dst[0];
+        sg.f1 = sg.dst[a.F.sk];
+        sg.f2 = sg.dst[2 * a.F.sk];
+#pragma unroll
+        for (int q = 0; q < kSmallPer; ++q) {
+            const int32_t e = q < nent ? a.small.ent[lane][q] : 0;
+            cvq[q] = e >> 20;
+            const int32_t slot = e & 0xFFFFF;
+            jr[q][0] = q < nent ? Jw[slot * 3 + 0] : 0.f;
+            jr[q][1] = q < nent ? Jw[slot * 3 + 1] : 0.f;
+            jr[q][2] = q < nent ? Jw[slot * 3 + 2] : 0.f;
+        }
+    }
+    double acc[1 + D];
+#pragma unroll
+    for (int j = 0; j <= D; ++j) acc[j] = 0.0;
+    for (int i = lane; i < wr.nt; i += 64) {
+        const double *p = a.partial + (int64_t)(wr.t0 + i) * 4;
+#pragma unroll
+        for (int j = 0; j <= D; ++j) acc[j] += p[j];
+    }
+#pragma unroll
+    for (int j = 0; j <= D; ++j)
+        for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
+    // every lane now holds the sums; take lane 0's bits so all agree
+#pragma unroll
+    for (int j = 0; j <= D; ++j) acc[j] = __shfl(acc[j], 0, 64);
+    double coef[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) coef[d] = acc[1 + d] * a.inv_sig2[d];  // -dV/dxi
+    if (lane == 0) {
+        double xi[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) xi[d] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + d];
+        const double V = acc[0];
+        bool finite = isfinite(V);
+        a.V_ws[w] = V;
+        if (a.V_out) a.V_out[w] = V;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const double dv = -coef[d];
+            finite = finite && isfinite(dv);
+            a.dV_ws[(int64_t)w * D + d] = dv;
+            if (a.dV_out) a.dV_out[(int64_t)w * D + d] = dv;
+            if (a.xi_out) a.xi_out[(int64_t)w * D + d] = xi[d];
+        }
+        if (!finite) atomicOr(a.flags, kFlagNonFinite);
+        bool dep = a.deposit == 2;
+        if (a.deposit == 1 && a.stride > 0) dep = (next_step - 1) % a.stride == 0;  // kernel A set the counter
+        if (dep) {
+            if (cnt0 < wr.cap) {
+                const int64_t k = (int64_t)wr.hb4 * 4 + cnt0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) a.c[d][k] = (float)xi[d];
+                a.h[k] = (float)(a.inv_kdT > 0.0 ? a.height * exp(-V * a.inv_kdT) : a.height);
+                a.count[w] = cnt0 + 1;
+            } else {
+                atomicOr(a.flags, kFlagCapacity);
+            }
+        }
+    }
+    if (small_lane) {
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSmallPer; ++q) {
+            double cf = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) cf = (q < nent && cvq[q] == d) ? coef[d] : cf;
+            fx += cf * (double)jr[q][0];
+            fy += cf * (double)jr[q][1];
+            fz += cf * (double)jr[q][2];
+        }
+        sg.dst[0] = sg.f0 + (float)fx;
+        sg.dst[a.F.sk] = sg.f1 + (float)fy;
+        sg.dst[2 * a.F.sk] = sg.f2 + (float)fz;
+    }
+}
+
 template <int D, bool FUSE, typename T>
 hipError_t launch_tiles(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t g, hipStream_t s)
 {
@@ -393,7 +494,12 @@ hipError_t launch_hill_d(const HillArgs &a, const CvSet &cs, const PosView &pos,
                                          : launch_tiles<D, FUSE, float>(a, cs, pos, g, s);
         if (e != hipSuccess) return e;
     }
-    if (which & 2) hipLaunchKernelGGL((k_hill_finalize<D, FUSE>), dim3(a.tabs.W), dim3(kBlock), 0, s, a, cs, pos);
+    if (which & 2) {
+        if (a.small.on)
+            hipLaunchKernelGGL((k_hill_finalize_wave<D, FUSE>), dim3(a.tabs.W), dim3(64), 0, s, a, cs, pos);
+        else
+            hipLaunchKernelGGL((k_hill_finalize<D, FUSE>), dim3(a.tabs.W), dim3(kBlock), 0, s, a, cs, pos);
+    }
     return hipGetLastError();
 }
 
