@@ -229,3 +229,36 @@ def test_graph_replay_matches_eager_steps(gpu):
     assert ca.shape[0] == 300 + 6 * W and np.array_equal(ca, cb) and np.array_equal(ha, hb)
     Ga, Gb = a.grid_get(0), b.grid_get(0)
     assert np.array_equal(Ga[0], Gb[0]) and np.array_equal(Ga[1], Gb[1])
+
+
+@pytest.mark.parametrize("D", [1, 3])
+def test_nodes_and_read_back_one_and_three_cvs(gpu, D):
+    """D = 1 (phi) and D = 3 (phi, psi, Rg of 12 atoms): node values after
+    sx_hills_set and the read-back at random points, against the oracle."""
+    g = np.random.default_rng(30 + D)
+    if D == 1:
+        cvs, per = synth.backbone_cvs(4)[:1], [True]
+        lo, hi, nb, sigma = [-PI], [PI], [80], [0.3]
+        C = g.uniform(-PI, PI, size=(500, 1))
+    else:
+        cvs = synth.backbone_cvs(4) + [{"kind": "gyration", "idx": list(range(0, 12))}]
+        per = [True, True, False]
+        lo, hi, nb, sigma = [-PI, -PI, 0.2], [PI, PI, 0.6], [24, 20, 10], [0.35, 0.35, 0.04]
+        C = np.concatenate([g.uniform(-PI, PI, size=(800, 2)), g.uniform(0.25, 0.55, size=(800, 1))], 1)
+    C = C.astype(np.float32)
+    H = g.uniform(0.5, 1.5, len(C)).astype(np.float32)
+    s = sampler(cvs, sigma, lo, hi, nb, cap=[len(C) + 8])
+    s.hills_set(0, C, H)
+    ref = BiasGrid(lo, hi, nb, per)
+    ref.set_hills(C.astype(np.float64), H.astype(np.float64), sigma)
+    V, G = s.grid_get(0)
+    sV, sG = np.max(np.abs(ref.V)), np.max(np.abs(ref.G))
+    assert np.max(np.abs(V - ref.V.reshape(-1))) <= 1e-12 * sV
+    assert np.max(np.abs(G.T - ref.G.reshape(-1, D))) <= 1e-12 * sG
+    X = g.uniform(lo, hi, size=(300, D))
+    Vg, Gg = s.grid_eval(dev(X))
+    Vg, Gg = Vg.cpu().numpy(), Gg.cpu().numpy()
+    for i, x in enumerate(X):
+        Vr, Gr = ref.lookup(x)
+        assert abs(Vg[i] - Vr) <= 1e-12 * sV
+        assert np.max(np.abs(Gg[i] - Gr)) <= 1e-12 * sG
