@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--graph-steps", type=int, default=10, help="steps per captured graph")
+    ap.add_argument("--graph-steps", type=int, default=50, help="steps per captured graph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU sample")
     ap.add_argument("--hill-reps", type=int, default=200, help="launches timed for the hill-sum kernel")
