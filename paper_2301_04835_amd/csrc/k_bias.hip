@@ -260,6 +260,33 @@ struct SmallGather {
     float *dst;
 };
 
+// Lane u's row of the small table and the Jacobian rows it names, requested
+// together: the whole row is read (unused entries are zero, i.e. slot 0 of
+// CV 0, which exists), then every slot's row.  Entries q >= nent are left
+// in place and skipped where they are used, so nothing here waits for the
+// rows to arrive.
+__device__ __forceinline__ void small_rows(const HillArgs &a, int u, int32_t w, int64_t aoff, SmallGather &sg,
+                                           int &nent, int32_t (&cvq)[kSmallPer], float (&jr)[kSmallPer][3])
+{
+    const float *Jw = a.J + (int64_t)w * a.nslots * 3;
+    nent = a.small.nent[u];
+    sg.dst = a.F.ptr + (aoff + a.small.touched[u]) * a.F.sa;
+    sg.f0 = sg.dst[0];
+    sg.f1 = sg.dst[a.F.sk];
+    sg.f2 = sg.dst[2 * a.F.sk];
+    int32_t e[kSmallPer];
+#pragma unroll
+    for (int q = 0; q < kSmallPer; ++q) e[q] = a.small.ent[u][q];
+#pragma unroll
+    for (int q = 0; q < kSmallPer; ++q) {
+        const int32_t slot = e[q] & 0xFFFFF;
+        cvq[q] = e[q] >> 20;
+        jr[q][0] = Jw[slot * 3 + 0];
+        jr[q][1] = Jw[slot * 3 + 1];
+        jr[q][2] = Jw[slot * 3 + 2];
+    }
+}
+
 template <int D, bool FUSE>
 __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, PosView pos)
 {
@@ -280,24 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     int nent = 0;
     int32_t cvq[kSmallPer];
     float jr[kSmallPer][3];
-    if (small_lane) {
-        const int u = threadIdx.x;
-        const float *Jw = a.J + (int64_t)w * a.nslots * 3;
-        nent = a.small.nent[u];
-        sg.dst = a.F.ptr + (wr.aoff + a.small.touched[u]) * a.F.sa;
-        sg.f0 = sg.dst[0];
-        sg.f1 = sg.dst[a.F.sk];
-        sg.f2 = sg.dst[2 * a.F.sk];
-#pragma unroll
-        for (int q = 0; q < kSmallPer; ++q) {
-            const int32_t e = q < nent ? a.small.ent[u][q] : 0;
-            cvq[q] = e >> 20;
-            const int32_t slot = e & 0xFFFFF;
-            jr[q][0] = q < nent ? Jw[slot * 3 + 0] : 0.f;
-            jr[q][1] = q < nent ? Jw[slot * 3 + 1] : 0.f;
-            jr[q][2] = q < nent ? Jw[slot * 3 + 2] : 0.f;
-        }
-    }
+    if (small_lane) small_rows(a, threadIdx.x, w, wr.aoff, sg, nent, cvq, jr);
     if ((int)threadIdx.x < D) s_xi[threadIdx.x] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + threadIdx.x];
     double acc[1 + D];
 #pragma unroll
@@ -347,10 +357,10 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
             double fx = 0.0, fy = 0.0, fz = 0.0;
 #pragma unroll
             for (int q = 0; q < kSmallPer; ++q) {
-                const double cf = q < nent ? s_coef[cvq[q]] : 0.0;
-                fx += cf * (double)jr[q][0];
-                fy += cf * (double)jr[q][1];
-                fz += cf * (double)jr[q][2];
+                const double cf = s_coef[cvq[q]];
+                fx += q < nent ? cf * (double)jr[q][0] : 0.0;
+                fy += q < nent ? cf * (double)jr[q][1] : 0.0;
+                fz += q < nent ? cf * (double)jr[q][2] : 0.0;
             }
             sg.dst[0] = sg.f0 + (float)fx;
             sg.dst[a.F.sk] = sg.f1 + (float)fy;
@@ -361,12 +371,13 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     }
 }
 
-// The same finalize in one wavefront, for walkers whose force table travels
-// in the kernel arguments (at most 32 touched atoms): the tile records are
-// summed by a fixed butterfly across the wavefront (every lane ends with the
-// same bits, as each lane adds in the same order), every lane forms dV/dxi
-// itself, lane 0 writes the outputs and deposits, and lane u < U gathers
-// atom u's force -- no LDS and no barrier on the path.
+// The same finalize in one wavefront, for steps that gather forces through a
+// table small enough for the kernel arguments (at most 32 touched atoms, 8
+// slots each): the tile records are summed by a fixed butterfly across the
+// wavefront (every lane ends with the same bits, as each lane adds in the
+// same order), every lane forms dV/dxi itself, lane 0 writes the outputs and
+// deposits, and lane u < U gathers atom u's force -- no LDS and no barrier
+// on the path.
 template <int D, bool FUSE>
 __global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs, PosView pos)
 {
@@ -374,33 +385,34 @@ __global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs,
     const int lane = threadIdx.x;
     const WalkerRec wr = ld_uniform(a.wrec + w);
     const int64_t next_step = a.deposit == 1 ? ld_uniform(a.dstep) : 0;
-    const int32_t cnt0 = a.deposit ? a.count[w] : 0;
-    const bool small_lane = a.do_forces && lane < a.small.U;
+    const int32_t cnt0 = a.deposit ? ld_uniform(a.count + w) : 0;  // scalar: no vector wait
+    const bool small_lane = lane < a.small.U;  // launched only when forces are gathered
     SmallGather sg{0.f, 0.f, 0.f, nullptr};
     int nent = 0;
     int32_t cvq[kSmallPer];
     float jr[kSmallPer][3];
-    if (small_lane) {
-        const float *Jw = a.J + (int64_t)w * a.nslots * 3;
-        nent = a.small.nent[lane];
-        sg.dst = a.F.ptr + (wr.aoff + a.small.touched[lane]) * a.F.sa;
-        sg.f0 = sg.dst[0];
-        sg.f1 = sg.dst[a.F.sk];
-        sg.f2 = sg.dst[2 * a.F.sk];
-#pragma unroll
-        for (int q = 0; q < kSmallPer; ++q) {
-            const int32_t e = q < nent ? a.small.ent[lane][q] : 0;
-            cvq[q] = e >> 20;
-            const int32_t slot = e & 0xFFFFF;
-            jr[q][0] = q < nent ? Jw[slot * 3 + 0] : 0.f;
-            jr[q][1] = q < nent ? Jw[slot * 3 + 1] : 0.f;
-            jr[q][2] = q < nent ? Jw[slot * 3 + 2] : 0.f;
-        }
-    }
+    // requested before anything waits, with no branch between the loads:
+    // the first tile record of each lane (lanes past the walker's count
+    // re-read its last one, nt >= 1, and drop it), the CV values, and a
+    // small-table row per lane (lanes past U re-read row U - 1 and store
+    // nothing)
     double acc[1 + D];
+    double r0[1 + D];
+    {
+        const double *p = a.partial + (int64_t)(wr.t0 + min(lane, wr.nt - 1)) * 4;
 #pragma unroll
-    for (int j = 0; j <= D; ++j) acc[j] = 0.0;
-    for (int i = lane; i < wr.nt; i += 64) {
+        for (int j = 0; j <= D; ++j) r0[j] = p[j];
+    }
+    double xi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xi[d] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + d];
+    small_rows(a, min(lane, a.small.U - 1), w, wr.aoff, sg, nent, cvq, jr);
+    // the record is kept or replaced by +0.0 through a bit mask, which uses
+    // the loaded value on every lane (a select lets the load move under a branch)
+    const long long keep = lane < wr.nt ? -1LL : 0LL;
+#pragma unroll
+    for (int j = 0; j <= D; ++j) acc[j] = 0.0 + __longlong_as_double(__double_as_longlong(r0[j]) & keep);
+    for (int i = lane + 64; i < wr.nt; i += 64) {  // the same order as one loop from i = lane
         const double *p = a.partial + (int64_t)(wr.t0 + i) * 4;
 #pragma unroll
         for (int j = 0; j <= D; ++j) acc[j] += p[j];
@@ -415,9 +427,6 @@ __global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs,
 #pragma unroll
     for (int d = 0; d < D; ++d) coef[d] = acc[1 + d] * a.inv_sig2[d];  // -dV/dxi
     if (lane == 0) {
-        double xi[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) xi[d] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + d];
         const double V = acc[0];
         bool finite = isfinite(V);
         a.V_ws[w] = V;
@@ -451,10 +460,10 @@ __global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs,
         for (int q = 0; q < kSmallPer; ++q) {
             double cf = 0.0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) cf = (q < nent && cvq[q] == d) ? coef[d] : cf;
-            fx += cf * (double)jr[q][0];
-            fy += cf * (double)jr[q][1];
-            fz += cf * (double)jr[q][2];
+            for (int d = 0; d < D; ++d) cf = cvq[q] == d ? coef[d] : cf;
+            fx += q < nent ? cf * (double)jr[q][0] : 0.0;
+            fy += q < nent ? cf * (double)jr[q][1] : 0.0;
+            fz += q < nent ? cf * (double)jr[q][2] : 0.0;
         }
         sg.dst[0] = sg.f0 + (float)fx;
         sg.dst[a.F.sk] = sg.f1 + (float)fy;
@@ -495,7 +504,7 @@ hipError_t launch_hill_d(const HillArgs &a, const CvSet &cs, const PosView &pos,
         if (e != hipSuccess) return e;
     }
     if (which & 2) {
-        if (a.small.on)
+        if (a.small.on && a.do_forces && a.small.U > 0)
             hipLaunchKernelGGL((k_hill_finalize_wave<D, FUSE>), dim3(a.tabs.W), dim3(64), 0, s, a, cs, pos);
         else
             hipLaunchKernelGGL((k_hill_finalize<D, FUSE>), dim3(a.tabs.W), dim3(kBlock), 0, s, a, cs, pos);
