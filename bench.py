@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cn3", action="store_true", help="skip the cell-list coordination-number workload")
     ap.add_argument("--no-sweep", action="store_true", help="skip the one-walker hill-count sweep")
     ap.add_argument("--no-umbrella", action="store_true", help="skip the harmonic-window workload")
+    ap.add_argument("--no-abf", action="store_true", help="skip the ABF workload")
     ap.add_argument("--cn3-steps", type=int, default=50, help="timed steps of the coordination-number workload")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2301_04835_amd", "tuning_mi355x.json"),
                     help="autotuner cache (JSON): an entry for this problem shape is reused, else searched and added")
@@ -180,12 +181,12 @@ def bust_leg(d, p, tile, grid, reps):
             "frac": nbytes / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
-def timed_graph(s, pos, forces, outs, steps, warmup, gsteps=10):
+def timed_graph(s, pos, forces, outs, steps, warmup, gsteps=10, sys_forces=None):
     """Capture gsteps steps in a HIP graph, replay warmup, then time
     replays for `steps` steps (wall clock around synchronisations)."""
     import torch
     xi, V, dV = outs
-    s.graph_capture(gsteps, pos, forces=forces, xi_out=xi, V_out=V, dV_out=dV)
+    s.graph_capture(gsteps, pos, forces=forces, xi_out=xi, V_out=V, dV_out=dV, sys_forces=sys_forces)
     for _ in range(max(1, warmup // gsteps)):
         s.graph_launch()
     torch.cuda.synchronize()
@@ -257,6 +258,69 @@ def umbrella_leg(args, d):
     return {"workload": "umbrella-windows-256-walkers", "walkers": W, "k": [100.0, 100.0],
             "steps_per_s": rate, "ms_per_step": 1e3 / rate, "steps_timed": nst,
             "integrate_s": t_int, "A_range": float(np.max(A) - np.min(A))}
+
+
+def abf_leg(args):
+    """ABF on (Rg of 500 atoms, coordination number between two groups of
+    1,000 atoms, all pairs, rational switch r0 = 0.5 nm, 6/12) in a
+    50,000-atom box of 10 nm, 100 x 100 bins, threshold 500: two eager steps,
+    the second kept for the oracle check, then 10^4 steps in replayed graphs.
+    Positions and system forces (N(0, 100^2) kJ/mol/nm) stay fixed, so every
+    sample lands in one bin, which must then hold exactly one count per step."""
+    import torch
+    from paper_2301_04835_amd import Sampler, synth
+
+    p = synth.ABF50K
+    cvs = synth.abf50k_cvs()
+    box = [p["box"]] * 3
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    s.set_box(box)
+    s.set_walkers(np.array([0, p["n_atoms"]]))
+    s.abf(list(p["lo"]), list(p["hi"]), list(p["nbins"]), p["n_threshold"])
+    s.bind()
+    pos_np = synth.abf50k_box(seed=2)
+    fs_np = np.random.default_rng(12).normal(0.0, p["fsys_sd"], size=pos_np.shape).astype(np.float32)
+    pos, fs = torch.from_numpy(pos_np).cuda(), torch.from_numpy(fs_np).cuda()
+    forces = torch.zeros_like(pos)
+    mk = lambda *sh: torch.zeros(sh, dtype=torch.float64, device="cuda")
+    out = (mk(1, 2), mk(1), mk(1, 2))
+    for t in range(2):  # the second step carries the first sample's bias
+        forces.zero_()
+        s.step(pos, forces=forces, xi_out=out[0], V_out=out[1], dV_out=out[2], sys_forces=fs)
+    first = (out[0].cpu().numpy()[0], -out[2].cpu().numpy()[0], forces.cpu().numpy())
+    warm = 200
+    rate, nst = timed_graph(s, pos, forces, out, p["n_steps"], warm, gsteps=args.graph_steps, sys_forces=fs)
+    s.check()
+    N, _ = s.abf_grid(0)
+    nsamp = 2 + (max(1, warm // args.graph_steps) + nst // args.graph_steps) * args.graph_steps
+    res = {"workload": "abf-rg500-cn1000x1000-50k-atoms", "atoms": p["n_atoms"], "bins": list(p["nbins"]),
+           "pairs_per_step": p["n_a"] * p["n_b"], "steps_per_s": rate, "ms_per_step": 1e3 / rate,
+           "steps_timed": nst, "graph_steps": args.graph_steps,
+           "samples_one_bin": bool(int(N.sum()) == nsamp and int((N > 0).sum()) == 1)}
+    return res, (cvs, box, pos_np, fs_np, first)
+
+
+def abf_oracle_check(ad):
+    """CPU oracle leg of the ABF workload: the two eager steps recomputed in
+    FP64 from the same inputs; the second step's CVs, bias along the CVs and
+    atom forces are compared."""
+    import oracle
+
+    cvs, box, pos_np, fs_np, (xi, b, F) = ad
+    from paper_2301_04835_amd import synth
+
+    p = synth.ABF50K
+    g = oracle.AbfGrid(list(p["lo"]), list(p["hi"]), list(p["nbins"]), [False, False], p["n_threshold"])
+    fs = fs_np.astype(np.float64)
+    t0 = time.perf_counter()
+    x, J = oracle.cv_eval(pos_np.astype(np.float64), cvs, np.array(box))
+    oracle.abf_step(g, x, J, fs)
+    t_or = time.perf_counter() - t0  # one whole oracle step
+    br, Fb, _, _ = oracle.abf_step(g, x, J, fs)
+    rel = lambda a, r: float(np.max(np.abs(a - r)) / max(np.max(np.abs(r)), 1e-300))
+    return {"oracle_step_s": t_or, "xi_rel_err_vs_oracle": [float(abs(xi[d] - x[d]) / abs(x[d])) for d in range(2)],
+            "b_rel_err_vs_oracle": rel(b, br), "force_rel_err_vs_oracle": rel(F, Fb)}
 
 
 def surrogate_leg(args):
@@ -584,6 +648,9 @@ def main():
         out["hill_sweep_one_walker"] = sweep_leg(args.hill_reps)
     if not args.no_umbrella:
         out["umbrella"] = umbrella_leg(args, d)
+    ad = None
+    if not args.no_abf:
+        out["abf"], ad = abf_leg(args)
     sg_data = gd = None
     if not args.no_surrogate:
         out["surrogate"], sg_data = surrogate_leg(args)
@@ -598,6 +665,8 @@ def main():
             out["surrogate"]["bias_grid"].update(grid_oracle_check(gd))
         if cn_data is not None:
             out["cn3"].update(cn3_oracle(cn_data))
+        if ad is not None:
+            out["abf"].update(abf_oracle_check(ad))
     print(json.dumps(out))
 
 

@@ -18,139 +18,234 @@
 namespace sx {
 namespace {
 
-__global__ void __launch_bounds__(kBlock) k_abf(AbfArgs a)
+constexpr int MD = kMaxBiasDim;
+constexpr int NA = MD * MD + MD;  // G (MD x MD) then u (MD)
+
+// touched atom u of walker w: its Jacobian rows j_d (slots of one CV summed)
+// and its terms m^-1 j_d . j_e and m^-1 j_d . q added to acc
+__device__ __forceinline__ void abf_atom_terms(const AbfArgs &a, int32_t w, int u, double (&acc)[NA])
 {
-    constexpr int MD = kMaxBiasDim;
-    __shared__ double lds[(MD * MD + MD) * (kBlock / 64)];
-    __shared__ double s_coef[kMaxCv];
-    const int32_t w = blockIdx.x;
-    const int D = a.D;
     const WalkerTabs &t = a.tabs;
     const int64_t jb = (int64_t)w * a.nslots, ab = t.atom_off[w];
-    double acc[MD * MD + MD];
+    double jv[MD][3];
 #pragma unroll
-    for (int j = 0; j < MD * MD + MD; ++j) acc[j] = 0.0;
-    for (int u = threadIdx.x; u < t.U; u += blockDim.x) {
-        double jv[MD][3];
+    for (int d = 0; d < MD; ++d) jv[d][0] = jv[d][1] = jv[d][2] = 0.0;
+    for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
+        const int32_t s = t.inv_slot[q];
+        const int d = t.slot_cv[s];
+        const float *js = a.J + (jb + s) * 3;
 #pragma unroll
-        for (int d = 0; d < MD; ++d) jv[d][0] = jv[d][1] = jv[d][2] = 0.0;
-        for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
-            const int32_t s = t.inv_slot[q];
-            const int d = t.slot_cv[s];
-            const float *js = a.J + (jb + s) * 3;
+        for (int dd = 0; dd < MD; ++dd)
+            if (dd == d) {
+                jv[dd][0] += js[0];
+                jv[dd][1] += js[1];
+                jv[dd][2] += js[2];
+            }
+    }
+    const int64_t atom = ab + t.touched[u];
+    const float *fp = static_cast<const float *>(a.Fsys.ptr) + atom * a.Fsys.sa;
+    const double f[3] = {fp[0], fp[a.Fsys.sk], fp[2 * a.Fsys.sk]};
+    const double im = a.estimator == 1 ? a.inv_mass[atom] : 1.0;
 #pragma unroll
-            for (int dd = 0; dd < MD; ++dd)
-                if (dd == d) {
-                    jv[dd][0] += js[0];
-                    jv[dd][1] += js[1];
-                    jv[dd][2] += js[2];
-                }
+    for (int d = 0; d < MD; ++d) {
+#pragma unroll
+        for (int e = 0; e < MD; ++e)
+            acc[d * MD + e] += im * (jv[d][0] * jv[e][0] + jv[d][1] * jv[e][1] + jv[d][2] * jv[e][2]);
+        acc[MD * MD + d] += im * (jv[d][0] * f[0] + jv[d][1] * f[1] + jv[d][2] * f[2]);
+    }
+}
+
+// What the update reads that does not depend on the sums: xi, its bin (row
+// major, first CV slowest), the bin's count and force sums (the samples
+// before this step), FUNN's bias, the momentum estimator's previous values
+// and the device step counter.  Every lane of the workgroup computes the
+// same addresses, so the loads go through the scalar cache and are in
+// flight while the sums are formed.
+struct AbfPre {
+    double xi[MD], F[MD], bext[MD], bprev[MD], wpprev[MD];
+    int64_t k, dstep;
+    uint32_t cnt;
+    int32_t has;
+    bool inr;
+};
+
+__device__ __forceinline__ AbfPre abf_prefetch(const AbfArgs &a, int32_t w)
+{
+    AbfPre r{};
+    const int D = a.D;
+    r.k = 0;
+    r.inr = true;
+    for (int d = 0; d < D; ++d) {
+        r.xi[d] = a.xi[(int64_t)w * D + d];
+        int64_t i = (int64_t)floor((r.xi[d] - a.lo[d]) / a.delta[d]);
+        if (a.periodic[d]) {
+            i %= a.nbins[d];
+            if (i < 0) i += a.nbins[d];
+        } else if (i < 0 || i >= a.nbins[d]) {
+            r.inr = false;
         }
-        const int64_t atom = ab + t.touched[u];
-        const float *fp = static_cast<const float *>(a.Fsys.ptr) + atom * a.Fsys.sa;
-        const double f[3] = {fp[0], fp[a.Fsys.sk], fp[2 * a.Fsys.sk]};
-        const double im = a.estimator == 1 ? a.inv_mass[atom] : 1.0;
-#pragma unroll
-        for (int d = 0; d < MD; ++d) {
-#pragma unroll
-            for (int e = 0; e < MD; ++e)
-                acc[d * MD + e] += im * (jv[d][0] * jv[e][0] + jv[d][1] * jv[e][1] + jv[d][2] * jv[e][2]);
-            acc[MD * MD + d] += im * (jv[d][0] * f[0] + jv[d][1] * f[1] + jv[d][2] * f[2]);
+        r.k = r.k * a.nbins[d] + i;
+    }
+    if (r.inr) {
+        r.cnt = a.N[(int64_t)w * a.nbins_total + r.k];
+        for (int d = 0; d < D; ++d) r.F[d] = a.Fsum[((int64_t)w * a.nbins_total + r.k) * D + d];
+    }
+    if (a.b_ext)
+        for (int d = 0; d < D; ++d) r.bext[d] = a.b_ext[(int64_t)w * D + d];
+    if (a.estimator == 1) {
+        r.has = a.has_prev[w];
+        for (int d = 0; d < D; ++d) {
+            r.bprev[d] = a.b_prev[(int64_t)w * D + d];
+            r.wpprev[d] = a.Wp_prev[(int64_t)w * D + d];
         }
     }
-    block_sum0<MD * MD + MD>(acc, lds);
-    if (threadIdx.x == 0) {
-        // solve G x = u by Gaussian elimination with partial pivoting
-        double G[MD][MD + 1];
-        for (int d = 0; d < D; ++d) {
-            for (int e = 0; e < D; ++e) G[d][e] = acc[d * MD + e];
-            G[d][D] = acc[MD * MD + d];
-        }
-        for (int col = 0; col < D; ++col) {
-            int piv = col;
-            for (int r = col + 1; r < D; ++r)
-                if (fabs(G[r][col]) > fabs(G[piv][col])) piv = r;
-            if (piv != col)
-                for (int e = 0; e <= D; ++e) {
-                    double tmp = G[col][e];
-                    G[col][e] = G[piv][e];
-                    G[piv][e] = tmp;
-                }
-            for (int r = col + 1; r < D; ++r) {
-                const double fct = G[r][col] / G[col][col];
-                for (int e = col; e <= D; ++e) G[r][e] -= fct * G[col][e];
-            }
-        }
-        double x[MD];
-        for (int d = D - 1; d >= 0; --d) {
-            double s = G[d][D];
-            for (int e = d + 1; e < D; ++e) s -= G[d][e] * x[e];
-            x[d] = s / G[d][d];
-        }
-        double theta[MD] = {0.0, 0.0, 0.0};
-        bool sample = true;
-        if (a.estimator == 1) {
-            sample = a.has_prev[w] != 0;
-            for (int d = 0; d < D; ++d)
-                theta[d] = a.b_prev[(int64_t)w * D + d] - (x[d] - a.Wp_prev[(int64_t)w * D + d]) / a.dt;
-        } else {
-            for (int d = 0; d < D; ++d) theta[d] = -x[d];
-        }
-        // bin of xi (row-major, first CV slowest)
-        int64_t k = 0;
-        bool inr = true;
-        for (int d = 0; d < D; ++d) {
-            const double xv = a.xi[(int64_t)w * D + d];
-            int64_t i = (int64_t)floor((xv - a.lo[d]) / a.delta[d]);
-            if (a.periodic[d]) {
-                i %= a.nbins[d];
-                if (i < 0) i += a.nbins[d];
-            } else if (i < 0 || i >= a.nbins[d]) {
-                inr = false;
-            }
-            k = k * a.nbins[d] + i;
-        }
-        bool finite = true;
-        for (int d = 0; d < D; ++d) finite = finite && isfinite(theta[d]) && isfinite(x[d]);
-        if (!finite) atomicOr(a.flags, kFlagNonFinite);
-        double b[MD] = {0.0, 0.0, 0.0};
-        if (inr && finite) {
-            uint32_t *Nk = a.N + (int64_t)w * a.nbins_total + k;
-            double *Fk = a.Fsum + ((int64_t)w * a.nbins_total + k) * D;
-            const uint32_t cnt = *Nk;
-            const double den = (double)max((int64_t)cnt, (int64_t)a.n_threshold);
-            for (int d = 0; d < D; ++d)
-                b[d] = a.b_ext ? a.b_ext[(int64_t)w * D + d] : den > 0.0 ? Fk[d] / den : 0.0;
-            if (sample) {
-                *Nk = cnt + 1u;
-                for (int d = 0; d < D; ++d) Fk[d] += theta[d];
-            }
-        }
-        if (a.estimator == 1) {  // for the next step: this step's W p and bias
-            for (int d = 0; d < D; ++d) {
-                a.Wp_prev[(int64_t)w * D + d] = x[d];
-                a.b_prev[(int64_t)w * D + d] = b[d];
-            }
-            a.has_prev[w] = 1;
-        }
-        for (int d = 0; d < D; ++d) {
-            s_coef[d] = b[d];
-            if (a.dV_out) a.dV_out[(int64_t)w * D + d] = -b[d];
-            if (a.xi_out) a.xi_out[(int64_t)w * D + d] = a.xi[(int64_t)w * D + d];
-        }
-        if (a.V_out) a.V_out[w] = 0.0;
-        if (w == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
+    if (w == 0 && a.step < 0) r.dstep = *a.dstep;
+    return r;
+}
+
+// One thread, walker w, the reduced G and u and the prefetched values: solve
+// G x = u, form theta, take the bias of xi's bin, add the sample, keep the
+// momentum estimator's state, write the outputs; the bias along the CVs
+// goes to coef[0..D).
+__device__ void abf_solve_update(const AbfArgs &a, int32_t w, const double (&acc)[NA], const AbfPre &pre,
+                                 double *coef)
+{
+    const int D = a.D;
+    // solve G x = u by Gaussian elimination with partial pivoting
+    double G[MD][MD + 1];
+    for (int d = 0; d < D; ++d) {
+        for (int e = 0; e < D; ++e) G[d][e] = acc[d * MD + e];
+        G[d][D] = acc[MD * MD + d];
     }
+    for (int col = 0; col < D; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < D; ++r)
+            if (fabs(G[r][col]) > fabs(G[piv][col])) piv = r;
+        if (piv != col)
+            for (int e = 0; e <= D; ++e) {
+                double tmp = G[col][e];
+                G[col][e] = G[piv][e];
+                G[piv][e] = tmp;
+            }
+        for (int r = col + 1; r < D; ++r) {
+            const double fct = G[r][col] / G[col][col];
+            for (int e = col; e <= D; ++e) G[r][e] -= fct * G[col][e];
+        }
+    }
+    double x[MD];
+    for (int d = D - 1; d >= 0; --d) {
+        double s = G[d][D];
+        for (int e = d + 1; e < D; ++e) s -= G[d][e] * x[e];
+        x[d] = s / G[d][d];
+    }
+    double theta[MD] = {0.0, 0.0, 0.0};
+    bool sample = true;
+    if (a.estimator == 1) {
+        sample = pre.has != 0;
+        for (int d = 0; d < D; ++d) theta[d] = pre.bprev[d] - (x[d] - pre.wpprev[d]) / a.dt;
+    } else {
+        for (int d = 0; d < D; ++d) theta[d] = -x[d];
+    }
+    bool finite = true;
+    for (int d = 0; d < D; ++d) finite = finite && isfinite(theta[d]) && isfinite(x[d]);
+    if (!finite) atomicOr(a.flags, kFlagNonFinite);
+    double b[MD] = {0.0, 0.0, 0.0};
+    if (pre.inr && finite) {
+        const double den = (double)max((int64_t)pre.cnt, (int64_t)a.n_threshold);
+        for (int d = 0; d < D; ++d) b[d] = a.b_ext ? pre.bext[d] : den > 0.0 ? pre.F[d] / den : 0.0;
+        if (sample) {
+            a.N[(int64_t)w * a.nbins_total + pre.k] = pre.cnt + 1u;
+            double *Fk = a.Fsum + ((int64_t)w * a.nbins_total + pre.k) * D;
+            for (int d = 0; d < D; ++d) Fk[d] = pre.F[d] + theta[d];
+        }
+    }
+    if (a.estimator == 1) {  // for the next step: this step's W p and bias
+        for (int d = 0; d < D; ++d) {
+            a.Wp_prev[(int64_t)w * D + d] = x[d];
+            a.b_prev[(int64_t)w * D + d] = b[d];
+        }
+        a.has_prev[w] = 1;
+    }
+    for (int d = 0; d < D; ++d) {
+        coef[d] = b[d];
+        if (a.dV_out) a.dV_out[(int64_t)w * D + d] = -b[d];
+        if (a.xi_out) a.xi_out[(int64_t)w * D + d] = pre.xi[d];
+    }
+    if (a.V_out) a.V_out[w] = 0.0;
+    if (w == 0) *a.dstep = a.step >= 0 ? a.step + 1 : pre.dstep + 1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_abf(AbfArgs a)
+{
+    __shared__ double lds[NA * (kBlock / 64)];
+    __shared__ double s_coef[kMaxCv];
+    const int32_t w = blockIdx.x;
+    const AbfPre pre = abf_prefetch(a, w);
+    double acc[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+    for (int u = threadIdx.x; u < a.tabs.U; u += blockDim.x) abf_atom_terms(a, w, u, acc);
+    block_sum0<NA>(acc, lds);
+    if (threadIdx.x == 0) abf_solve_update(a, w, acc, pre, s_coef);
     __syncthreads();
-    gather_forces(t, a.J + jb * 3, w, s_coef, a.F);
+    gather_forces(a.tabs, a.J + (int64_t)w * a.nslots * 3, w, s_coef, a.F);
+}
+
+// Walkers with many touched atoms, in three launches: (1) one lane per
+// touched atom, the terms reduced per workgroup (fixed tree) into a record
+// per (walker, block); (2) one wavefront per walker sums its records in a
+// fixed order and solves and updates as above, the bias along the CVs going
+// to a.coef; (3) the force gather, one lane per (walker, touched atom).
+__global__ void __launch_bounds__(kBlock) k_abf_part(AbfArgs a)
+{
+    __shared__ double lds[NA * (kBlock / 64)];
+    const int32_t w = blockIdx.y;
+    const int u = blockIdx.x * kBlock + threadIdx.x;
+    double acc[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+    if (u < a.tabs.U) abf_atom_terms(a, w, u, acc);
+    block_sum0<NA>(acc, lds);
+    if (threadIdx.x == 0) {
+        double *r = a.part + ((int64_t)w * a.nblk + blockIdx.x) * NA;
+#pragma unroll
+        for (int j = 0; j < NA; ++j) r[j] = acc[j];
+    }
+}
+
+__global__ void __launch_bounds__(64) k_abf_solve(AbfArgs a)
+{
+    const int32_t w = blockIdx.x;
+    const AbfPre pre = abf_prefetch(a, w);
+    double acc[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+    for (int b = threadIdx.x; b < a.nblk; b += 64) {
+        const double *r = a.part + ((int64_t)w * a.nblk + b) * NA;
+#pragma unroll
+        for (int j = 0; j < NA; ++j) acc[j] += r[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NA; ++j)
+        for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
+    if (threadIdx.x == 0) abf_solve_update(a, w, acc, pre, a.coef + (int64_t)w * a.D);
 }
 
 }  // namespace
 
 hipError_t launch_abf(const AbfArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_abf, dim3(a.tabs.W), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    if (a.nblk == 0) {
+        hipLaunchKernelGGL(k_abf, dim3(a.tabs.W), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_abf_part, dim3((unsigned)a.nblk, (unsigned)a.tabs.W), dim3(kBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_abf_solve, dim3(a.tabs.W), dim3(64), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gather(a.tabs, a.J, a.nslots, a.D, a.coef, 1.0, a.F, s);
 }
 
 }  // namespace sx

@@ -8,7 +8,9 @@
 //    tile) x side (A or B) x (walker, CV).  Each lane owns one atom of its
 //    side and gathers over one chunk of the other group staged in LDS, so
 //    every partial sum has exactly one writer (no atomics); a finalize
-//    kernel reduces the chunks in a fixed order (bitwise deterministic).
+//    kernel (8 lanes per member) reduces the chunks in a fixed order, and a
+//    one-wavefront kernel the CV value's per-block records (bitwise
+//    deterministic).
 #include "dev_cv.h"
 
 namespace sx {
@@ -196,38 +198,73 @@ __global__ void __launch_bounds__(kBlock) k_coord_pairs(CvSet cs, WalkerTabs t, 
     part[rec] = CnPart{S, gx, gy, gz};
 }
 
-// one workgroup per (walker, coordination CV): ordered reduction of the
-// chunk partials into the Jacobian slots and the CV value.
+// kCnLanes lanes per member of a (walker, coordination CV), A members first:
+// lane l of a member sums its chunk records l, l + kCnLanes, ... (adjacent
+// records on adjacent lanes), the member's lanes combine in a fixed
+// butterfly, and the first writes the Jacobian slot; the switch sums of the
+// A side's members are reduced per workgroup (fixed tree) into one value
+// record per block.  grid: x = block of kCnFinPer members, y = walker *
+// ncoord + k.
+constexpr int kCnLanes = kBlock / kCnFinPer;
+
 __global__ void __launch_bounds__(kBlock) k_coord_finalize(CvSet cs, WalkerTabs t, const CnPart *part,
-                                                            double *xi, float *J, int32_t ncoord)
+                                                            double *vpart, float *J, int32_t ncoord)
 {
     __shared__ double lds[kBlock / 64];
+    const int32_t w = blockIdx.y / ncoord, k = blockIdx.y % ncoord;
+    int c = 0, seen = 0;
+    for (; c < cs.ncv; ++c)
+        if (cs.cv[c].kind == CV_COORD && seen++ == k) break;
+    const CvDesc cv = cs.cv[c];
+    const int ntot = cv.na + cv.nb;
+    if ((int)blockIdx.x * kCnFinPer >= ntot) return;  // uniform per workgroup
+    const CnPart *pw = part + cv.part0 + (int64_t)w * cs.part_per_walker;
+    const int i = blockIdx.x * kCnFinPer + threadIdx.x / kCnLanes, l = threadIdx.x % kCnLanes;
+    const bool live = i < ntot, sideB = i >= cv.na;
+    double sv = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    if (live) {
+        const int ii = sideB ? i - cv.na : i;
+        const int nch = sideB ? cv.nchunk_b : cv.nchunk_a;
+        const CnPart *p = pw + (sideB ? (int64_t)cv.na * cv.nchunk_a : 0) + (int64_t)ii * nch;
+#pragma unroll 4
+        for (int q = l; q < nch; q += kCnLanes) {
+            const CnPart r = p[q];
+            sv += r.s;
+            gx += r.gx;
+            gy += r.gy;
+            gz += r.gz;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < kCnLanes; o <<= 1) {  // within the member's lanes (aligned groups of a wavefront)
+        sv += __shfl_xor(sv, o, 64);
+        gx += __shfl_xor(gx, o, 64);
+        gy += __shfl_xor(gy, o, 64);
+        gz += __shfl_xor(gz, o, 64);
+    }
+    double S[1] = {live && !sideB && l == 0 ? sv : 0.0};
+    if (J && live && l == 0)
+        st_slot(J, (int64_t)w * cs.nslots + cv.slot0 + i, make_double3(gx * cv.scale, gy * cv.scale, gz * cv.scale));
+    block_sum<1>(S, lds);
+    if (threadIdx.x == 0) vpart[(int64_t)w * cs.vblk_per_walker + cv.vblk0 + blockIdx.x] = S[0];
+}
+
+// one wavefront per (walker, coordination CV): the value records of its
+// member blocks in a fixed order (lane-strided, then a butterfly), times the
+// CV's scale.
+__global__ void __launch_bounds__(64) k_coord_value(CvSet cs, const double *vpart, double *xi, int32_t ncoord)
+{
     const int32_t w = blockIdx.x / ncoord, k = blockIdx.x % ncoord;
     int c = 0, seen = 0;
     for (; c < cs.ncv; ++c)
         if (cs.cv[c].kind == CV_COORD && seen++ == k) break;
     const CvDesc cv = cs.cv[c];
-    const CnPart *pw = part + cv.part0 + (int64_t)w * cs.part_per_walker;
-    double S[1] = {0.0};
-    const int ntot = cv.na + cv.nb;
-    for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
-        const bool sideB = i >= cv.na;
-        const int ii = sideB ? i - cv.na : i;
-        const int nch = sideB ? cv.nchunk_b : cv.nchunk_a;
-        const CnPart *p = pw + (sideB ? (int64_t)cv.na * cv.nchunk_a : 0) + (int64_t)ii * nch;
-        double s = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-        for (int q = 0; q < nch; ++q) {
-            CnPart r = p[q];
-            s += r.s;
-            gx += r.gx;
-            gy += r.gy;
-            gz += r.gz;
-        }
-        if (!sideB) S[0] += s;
-        if (J) st_slot(J, (int64_t)w * cs.nslots + cv.slot0 + i, make_double3(gx * cv.scale, gy * cv.scale, gz * cv.scale));
-    }
-    block_sum<1>(S, lds);
-    if (threadIdx.x == 0) xi[(int64_t)w * cs.D + cv.d] = S[0] * (double)cv.scale;
+    const int nblk = (cv.na + cv.nb + kCnFinPer - 1) / kCnFinPer;
+    const double *p = vpart + (int64_t)w * cs.vblk_per_walker + cv.vblk0;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 64) v += p[b];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (threadIdx.x == 0) xi[(int64_t)w * cs.D + cv.d] = v * (double)cv.scale;
 }
 
 }  // namespace
@@ -236,13 +273,14 @@ hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *
                      int64_t /*max_atoms_per_walker*/, hipStream_t s)
 {
     int ndih = 0, nrg = 0, ncn = 0;
-    int max_tiles_x = 0;
+    int max_tiles_x = 0, max_blk = 0;
     for (int c = 0; c < cs.ncv; ++c) {
         const CvDesc &d = cs.cv[c];
         if (d.kind == CV_DIHEDRAL) ++ndih;
         if (d.kind == CV_GYRATION) ++nrg;
         if (d.kind == CV_COORD) {
             ++ncn;
+            max_blk = max(max_blk, (d.na + d.nb + kCnFinPer - 1) / kCnFinPer);
             int ta = (d.na + kBlock - 1) / kBlock * d.nchunk_a;
             int tb = (d.nb + kBlock - 1) / kBlock * d.nchunk_b;
             max_tiles_x = max(max_tiles_x, max(ta, tb));
@@ -269,7 +307,13 @@ hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *
             hipLaunchKernelGGL(k_coord_pairs<float>, grid, dim3(kBlock), 0, s, cs, t, pos, part, ncn);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_coord_finalize, dim3((unsigned)t.W * ncn), dim3(kBlock), 0, s, cs, t, part, xi, J, ncn);
+        // value records follow the W walkers' chunk records
+        double *vpart = cn_part + 4 * (int64_t)t.W * cs.part_per_walker;
+        hipLaunchKernelGGL(k_coord_finalize, dim3((unsigned)max_blk, (unsigned)t.W * ncn), dim3(kBlock), 0, s, cs, t,
+                           part, vpart, J, ncn);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_coord_value, dim3((unsigned)t.W * ncn), dim3(64), 0, s, cs, vpart, xi, ncn);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

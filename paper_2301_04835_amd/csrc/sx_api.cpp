@@ -89,6 +89,8 @@ struct Plan {
     Sub w_sgFlag, w_sgRed;
     // workspace sub-buffers
     Sub w_xi, w_V, w_dV, w_J, w_part, w_cnpart;
+    int32_t abf_nblk = 0;  // ABF in three launches when > 0 (blocks of touched atoms)
+    Sub w_abfpart, w_abfcoef;
     Sub w_atom_off, w_tiles, w_wrec;
     Sub w_slot_atom, w_slot_cv, w_touched, w_inv_ptr, w_inv_slot;
     size_t ws_bytes = 0;
@@ -346,7 +348,7 @@ sx_status make_plan(sx_ctx *c)
                 }
         }
     }
-    int64_t part = 0;
+    int64_t part = 0, vblk = 0;
     for (int d = 0; d < ncv; ++d) {
         const CvDef &cv = c->cvs[d];
         CvDesc &ds = cs.cv[d];
@@ -404,9 +406,12 @@ sx_status make_plan(sx_ctx *c)
             ds.nchunk_b = (ds.na + chunk - 1) / chunk;
             ds.part0 = part;
             part += (int64_t)ds.na * ds.nchunk_a + (int64_t)ds.nb * ds.nchunk_b;
+            ds.vblk0 = (int32_t)vblk;
+            vblk += (ds.na + ds.nb + kCnFinPer - 1) / kCnFinPer;
         }
     }
     cs.part_per_walker = part;
+    cs.vblk_per_walker = vblk;
     p.all_dihedral = true;
     for (auto &cv : c->cvs) p.all_dihedral = p.all_dihedral && cv.kind == CV_DIHEDRAL;
     p.nslots = (int32_t)p.slot_atom.size();
@@ -540,7 +545,10 @@ sx_status make_plan(sx_ctx *c)
     p.w_dV = lw.take(sizeof(double) * p.W * p.D);
     p.w_J = lw.take(sizeof(float) * 3 * (size_t)p.W * p.nslots);
     p.w_part = lw.take(sizeof(double) * 4 * (size_t)std::max<int64_t>(p.ntiles_max, p.shared_records));
-    p.w_cnpart = lw.take(32 * (size_t)p.W * part);
+    p.w_cnpart = lw.take(32 * (size_t)p.W * part + sizeof(double) * (size_t)p.W * p.cs.vblk_per_walker);
+    p.abf_nblk = (c->method == M_ABF && p.U > kAbfSplitU) ? (p.U + kBlock - 1) / kBlock : 0;
+    p.w_abfpart = lw.take(sizeof(double) * (kMaxBiasDim * kMaxBiasDim + kMaxBiasDim) * (size_t)p.W * p.abf_nblk);
+    p.w_abfcoef = lw.take(p.abf_nblk ? sizeof(double) * (size_t)p.W * p.D : 0);
     p.w_atom_off = lw.take(sizeof(int64_t) * (p.W + 1));
     p.w_tiles = lw.take(sizeof(TileRec) * p.ntiles_max);
     p.w_wrec = lw.take(sizeof(WalkerRec) * p.W);
@@ -1020,6 +1028,9 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.flags = reinterpret_cast<uint32_t *>(c->state + p.s_hdr.off + 8);
         a.step = step;
         a.dstep = at<int64_t>(c->state, p.s_hdr);
+        a.nblk = p.abf_nblk;
+        a.part = at<double>(c->ws, p.w_abfpart);
+        a.coef = at<double>(c->ws, p.w_abfcoef);
         hipError_t e = launch_abf(a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "ABF kernel");
     }

@@ -48,11 +48,14 @@ struct CvDesc {
     int32_t chunk;  // coordination all-pairs: partner chunk size
     int32_t nchunk_a, nchunk_b;  // chunks over B (for side A) and over A (side B)
     int64_t part0;  // coordination: first partial record of this CV (per walker)
+    int32_t vblk0;  // coordination: first value record of this CV (per walker)
     int32_t atom[4];  // dihedral: its four atoms (walker-relative)
     int32_t ga, gb;   // cell-list coordination: the two atom groups
     int32_t cn;       // cell-list coordination: index among those CVs
     double rcut;      // the cut (FP64), for decisions at its edge
 };
+
+constexpr int kCnFinPer = 32;  // coordination members per workgroup of the all-pairs finalize
 
 struct CvSet {
     int32_t ncv, D;
@@ -60,6 +63,7 @@ struct CvSet {
     double box[3], inv_box[3];  // 0: open
     int32_t nslots;
     int64_t part_per_walker;   // coordination partial records per walker
+    int64_t vblk_per_walker;   // coordination value records per walker (one per kCnFinPer members)
 };
 
 // Common walker tables.
@@ -167,7 +171,13 @@ struct AbfArgs {
     // FUNN: the bias is this W x D gradient of a network fitted to the mean
     // forces (null: the grid's Fsum / max(N, N_thr))
     const double *b_ext;
+    // nblk > 0: the three-launch form for walkers with many touched atoms,
+    // with W x nblk records of (D_max^2 + D_max) doubles in part and the
+    // W x D bias along the CVs in coef (workspace)
+    int32_t nblk;
+    double *part, *coef;
 };
+constexpr int kAbfSplitU = 2 * kBlock;  // touched atoms above which ABF takes the three-launch form
 
 // Hill sum over one shared list at nq query points.
 // Metadynamics bias kept on a grid: V and dV/dxi of each hill list at the
