@@ -178,3 +178,72 @@ def test_momentum_estimator_matches_oracle(gpu):
         assert np.array_equal(N.astype(np.int64), grids[w].N)
         assert int(N.sum()) == T - 1
         assert rel_inf(Fsum, grids[w].Fsum) <= 1e-5
+
+
+@pytest.mark.parametrize("estimator", [0, 1])
+def test_abf_many_touched_atoms_matches_oracle(gpu, estimator):
+    """Walkers touching more than 512 atoms (phi and the radius of gyration
+    of 600 atoms: the per-block Gram records, the one-wavefront solve and
+    the separate force gather) on three walkers of 700 atoms, with the
+    projected-force estimator (random system forces) and the momentum
+    estimator (per-atom masses, momenta drawn per step): per step the bias
+    along xi and the forces, after the run the histogram (exact) and the
+    force sums.  The oracle is given its Jacobian rounded to float32, the
+    precision the library keeps it in (the float32 Jacobian is checked
+    against the FP64 one in test_gpu_cv.py): with phi's rows orders of
+    magnitude above those of Rg over 600 atoms, that rounding alone moves
+    theta by up to ~1.5e-5 relative here, so the comparison at 1e-6 checks
+    the sums, solve, grid update and gather themselves."""
+    W, n, T, dt = 3, 700, 40, 0.002
+    cvs = [synth.backbone_cvs(4)[0], {"kind": "gyration", "idx": list(range(0, 600))}]
+    g = np.random.default_rng(31 + estimator)
+    tmpl = [synth.chain_template(n, 120 + w) for w in range(W)]
+    rg0 = [oracle.cv_eval(tm.astype(np.float64), cvs)[0][1] for tm in tmpl]
+    lo, hi, nb, thr = [-np.pi, min(rg0) - 0.6], [np.pi, max(rg0) + 0.6], [16, 12], 3
+    masses = g.uniform(1.0, 16.0, W * n)
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    s.set_walkers(np.arange(W + 1) * n)
+    s.abf(lo, hi, nb, thr)
+    if estimator == 1:
+        s.abf_momentum(dt, masses)
+    s.bind()
+    atom, _ = s.jac_layout()
+    assert len(np.unique(atom)) > 512  # the three-launch form
+    grids = [oracle.AbfGrid(lo, hi, nb, [True, False], thr) for _ in range(W)]
+    prev = [None] * W
+    Fb = torch.zeros((W * n, 3), dtype=torch.float32, device=gpu)
+    dV = torch.zeros((W, 2), dtype=torch.float64, device=gpu)
+    errb = errF = 0.0
+    for t in range(T):
+        pos = np.concatenate([tm + 0.2 * g.normal(size=tm.shape) for tm in tmpl]).astype(np.float32)
+        if estimator == 1:
+            q = (g.normal(size=pos.shape) * np.sqrt(masses)[:, None]).astype(np.float32)
+        else:
+            q = g.normal(0.0, 50.0, size=pos.shape).astype(np.float32)
+        Fb.zero_()
+        s.step(dev(pos), forces=Fb, step=t, dV_out=dV, sys_forces=dev(q))
+        bg, Fg = -dV.cpu().numpy(), Fb.cpu().numpy()
+        for w in range(W):
+            sl = slice(w * n, (w + 1) * n)
+            xi, J = oracle.cv_eval(pos[sl].astype(np.float64), cvs)
+            J = J.astype(np.float32).astype(np.float64)
+            assert not any(near_edge(xi[d], lo[d], hi[d], nb[d], 1e-6) for d in range(2))
+            if estimator == 1:
+                b, F, _, _, prev[w] = oracle.abf_step_momentum(grids[w], xi, J, q[sl].astype(np.float64),
+                                                               1.0 / masses[sl], dt, prev[w])
+            else:
+                b, F, _, _ = oracle.abf_step(grids[w], xi, J, q[sl].astype(np.float64))
+            if np.any(b != 0):
+                errb = max(errb, rel_inf(bg[w], b))
+                errF = max(errF, rel_inf(Fg[sl], F))
+            else:
+                assert np.all(bg[w] == 0) and np.all(Fg[sl] == 0)
+    s.check()
+    assert errb <= 1e-6 and errF <= 1e-6, (errb, errF)
+    for w in range(W):
+        N, Fsum = s.abf_grid(w)
+        assert np.array_equal(N.astype(np.int64), grids[w].N)
+        assert int(N.sum()) == (T if estimator == 0 else T - 1)
+        nz = grids[w].N > 0
+        assert rel_inf(Fsum[nz], grids[w].Fsum[nz]) <= 1e-6
