@@ -4,13 +4,11 @@
 //
 //  * dihedral angle: one lane per (walker, dihedral), FP64 arithmetic;
 //  * radius of gyration: one workgroup per (walker, CV), two passes in FP64;
-//  * coordination number, all pairs: a 3-D grid of (partner chunk, my-atom
-//    tile) x side (A or B) x (walker, CV).  Each lane owns one atom of its
-//    side and gathers over one chunk of the other group staged in LDS, so
-//    every partial sum has exactly one writer (no atomics); a finalize
-//    kernel (8 lanes per member) reduces the chunks in a fixed order, and a
-//    one-wavefront kernel the CV value's per-block records (bitwise
-//    deterministic).
+//  * coordination number, all pairs: a 3-D grid of member blocks x side (A
+//    or B) x (walker, CV).  L lanes own one member of their side and gather
+//    over the other group staged in LDS, so every sum has exactly one writer
+//    (no atomics); a one-wavefront kernel sums the CV value's per-block
+//    records in a fixed order (bitwise deterministic).
 #include "dev_cv.h"
 
 namespace sx {
@@ -111,14 +109,11 @@ __global__ void __launch_bounds__(kBlock) k_gyration(CvSet cs, WalkerTabs t, Pos
 }
 
 // ---------------------------------------------- coordination number, all pairs
-struct CnPart {  // one partial record: switch sum and gradient sum
-    double s, gx, gy, gz;
-};
-
 struct Partner {  // a partner atom staged in LDS
     double x, y, z;
     int32_t idx, pad;
 };
+constexpr int kCnStage = 1024;  // partners staged per round (32 KB)
 
 template <typename T>
 __device__ __forceinline__ double3 ld_d3(const PosView &p, int64_t i)
@@ -130,16 +125,23 @@ __device__ __forceinline__ double3 ld_d3(const PosView &p, int64_t i)
 // minimum-image component in FP64, rounded once to float
 __device__ __forceinline__ float min_img(double d, double L, double iL) { return (float)fma(-L, rint(d * iL), d); }
 
-// grid: x = my-atom tile * nchunk + chunk, y = side (0: A gathers over B,
-// 1: B gathers over A), z = walker * ncoord + k (k-th coordination CV).
-// The pair difference and its minimum image are taken in FP64 (exact for
-// float inputs up to the final rounding), the switching function in FP32,
-// the sums in FP64 per group of 8 partners.
+// grid: x = block of kBlock / L members of one side, y = side (0: A gathers
+// over B, 1: B gathers over A), z = walker * ncoord + k (k-th coordination
+// CV); L = cv.lanes lanes per member.  The other side's members are staged
+// in LDS kCnStage at a time; lane l of a member takes partners l, l + L,
+// ... of each round.  The pair difference and its minimum image are taken in
+// FP64 (exact for float inputs up to the final rounding), the switching
+// function in FP32, its sums in FP32 over each eight of a lane's partners and
+// in FP64 beyond; the member's lanes combine in a fixed butterfly and the
+// first writes the Jacobian slot.  On the A side the members' switch sums are
+// reduced per workgroup (fixed tree) into one value record per block, which
+// k_coord_value sums in order.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_coord_pairs(CvSet cs, WalkerTabs t, PosView pos, CnPart *part,
+__global__ void __launch_bounds__(kBlock) k_coord_pairs(CvSet cs, WalkerTabs t, PosView pos, double *vpart, float *J,
                                                          int32_t ncoord)
 {
-    __shared__ Partner oth[kBlock];
+    __shared__ Partner oth[kCnStage];
+    __shared__ double lds[kBlock / 64];
     const int32_t w = blockIdx.z / ncoord, k = blockIdx.z % ncoord;
     int c = 0, seen = 0;
     for (; c < cs.ncv; ++c)
@@ -148,109 +150,70 @@ __global__ void __launch_bounds__(kBlock) k_coord_pairs(CvSet cs, WalkerTabs t, 
     const int side = blockIdx.y;
     const int nmine = side ? cv.nb : cv.na, noth = side ? cv.na : cv.nb;
     const int mine0 = cv.slot0 + (side ? cv.na : 0), oth0 = cv.slot0 + (side ? 0 : cv.na);
-    const int nchunk = side ? cv.nchunk_b : cv.nchunk_a;
-    const int tile = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
-    if (tile * kBlock >= nmine) return;  // whole workgroup idle: uniform exit
+    const int L = cv.lanes, per = kBlock / L;
+    if ((int)blockIdx.x * per >= nmine) return;  // whole workgroup idle: uniform exit
     const int64_t base = t.atom_off[w];
-    const double L[3] = {cs.box[0], cs.box[1], cs.box[2]};
+    const double Lb[3] = {cs.box[0], cs.box[1], cs.box[2]};
     const double iL[3] = {cs.inv_box[0], cs.inv_box[1], cs.inv_box[2]};
-    // stage the partner chunk
-    const int j0 = chunk * cv.chunk, jn = min(cv.chunk, noth - j0);
-    for (int j = threadIdx.x; j < jn; j += blockDim.x) {
-        int32_t a = t.slot_atom[oth0 + j0 + j];
-        double3 r = ld_d3<T>(pos, base + a);
-        oth[j] = Partner{r.x, r.y, r.z, a, 0};
-    }
-    __syncthreads();
-    const int i = tile * kBlock + threadIdx.x;
-    if (i >= nmine) return;
-    const int32_t me = t.slot_atom[mine0 + i];
-    const double3 ri = ld_d3<T>(pos, base + me);
+    const int i = blockIdx.x * per + threadIdx.x / L, l = threadIdx.x % L;
+    const bool live = i < nmine;
+    const int32_t me = live ? t.slot_atom[mine0 + i] : -1;
+    const double3 ri = live ? ld_d3<T>(pos, base + me) : make_double3(0.0, 0.0, 0.0);
     double S = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int j = 0; j < jn; j += 8) {
-        float s8 = 0.f, x8 = 0.f, y8 = 0.f, z8 = 0.f;
-        const int je = min(jn, j + 8);
-        for (int q = j; q < je; ++q) {
-            const Partner o = oth[q];
-            float dx = min_img(ri.x - o.x, L[0], iL[0]);
-            float dy = min_img(ri.y - o.y, L[1], iL[1]);
-            float dz = min_img(ri.z - o.z, L[2], iL[2]);
-            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            bool use = (o.idx != me) && (cv.rcut2 <= 0.f || r2 < cv.rcut2);
-            float s, f;
-            switch_fn(r2, cv, s, f);
-            s = use ? s : 0.f;
-            f = use ? f : 0.f;
-            s8 += s;
-            x8 = fmaf(f, dx, x8);
-            y8 = fmaf(f, dy, y8);
-            z8 = fmaf(f, dz, z8);
+    for (int j0 = 0; j0 < noth; j0 += kCnStage) {
+        const int jn = min(kCnStage, noth - j0);
+        __syncthreads();  // the previous round is consumed
+        for (int j = threadIdx.x; j < jn; j += blockDim.x) {
+            const int32_t a = t.slot_atom[oth0 + j0 + j];
+            const double3 r = ld_d3<T>(pos, base + a);
+            oth[j] = Partner{r.x, r.y, r.z, a, 0};
         }
-        S += s8;
-        gx += x8;
-        gy += y8;
-        gz += z8;
-    }
-    const int nch = side ? cv.nchunk_b : cv.nchunk_a;
-    // record layout per walker and CV: [A atoms x nchunk_a][B atoms x nchunk_b]
-    int64_t rec = cv.part0 + (int64_t)w * cs.part_per_walker +
-                  (side ? (int64_t)cv.na * cv.nchunk_a : 0) + (int64_t)i * nch + chunk;
-    part[rec] = CnPart{S, gx, gy, gz};
-}
-
-// kCnLanes lanes per member of a (walker, coordination CV), A members first:
-// lane l of a member sums its chunk records l, l + kCnLanes, ... (adjacent
-// records on adjacent lanes), the member's lanes combine in a fixed
-// butterfly, and the first writes the Jacobian slot; the switch sums of the
-// A side's members are reduced per workgroup (fixed tree) into one value
-// record per block.  grid: x = block of kCnFinPer members, y = walker *
-// ncoord + k.
-constexpr int kCnLanes = kBlock / kCnFinPer;
-
-__global__ void __launch_bounds__(kBlock) k_coord_finalize(CvSet cs, WalkerTabs t, const CnPart *part,
-                                                            double *vpart, float *J, int32_t ncoord)
-{
-    __shared__ double lds[kBlock / 64];
-    const int32_t w = blockIdx.y / ncoord, k = blockIdx.y % ncoord;
-    int c = 0, seen = 0;
-    for (; c < cs.ncv; ++c)
-        if (cs.cv[c].kind == CV_COORD && seen++ == k) break;
-    const CvDesc cv = cs.cv[c];
-    const int ntot = cv.na + cv.nb;
-    if ((int)blockIdx.x * kCnFinPer >= ntot) return;  // uniform per workgroup
-    const CnPart *pw = part + cv.part0 + (int64_t)w * cs.part_per_walker;
-    const int i = blockIdx.x * kCnFinPer + threadIdx.x / kCnLanes, l = threadIdx.x % kCnLanes;
-    const bool live = i < ntot, sideB = i >= cv.na;
-    double sv = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    if (live) {
-        const int ii = sideB ? i - cv.na : i;
-        const int nch = sideB ? cv.nchunk_b : cv.nchunk_a;
-        const CnPart *p = pw + (sideB ? (int64_t)cv.na * cv.nchunk_a : 0) + (int64_t)ii * nch;
-#pragma unroll 4
-        for (int q = l; q < nch; q += kCnLanes) {
-            const CnPart r = p[q];
-            sv += r.s;
-            gx += r.gx;
-            gy += r.gy;
-            gz += r.gz;
-        }
-    }
+        __syncthreads();
+        if (!live) continue;
+        for (int j = l; j < jn; j += 8 * L) {
+            float s8 = 0.f, x8 = 0.f, y8 = 0.f, z8 = 0.f;
 #pragma unroll
-    for (int o = 1; o < kCnLanes; o <<= 1) {  // within the member's lanes (aligned groups of a wavefront)
-        sv += __shfl_xor(sv, o, 64);
+            for (int q = 0; q < 8; ++q) {
+                const int jj = j + q * L;
+                if (jj >= jn) break;
+                const Partner o = oth[jj];
+                const float dx = min_img(ri.x - o.x, Lb[0], iL[0]);
+                const float dy = min_img(ri.y - o.y, Lb[1], iL[1]);
+                const float dz = min_img(ri.z - o.z, Lb[2], iL[2]);
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const bool use = (o.idx != me) && (cv.rcut2 <= 0.f || r2 < cv.rcut2);
+                float sv, f;
+                switch_fn(r2, cv, sv, f);
+                sv = use ? sv : 0.f;
+                f = use ? f : 0.f;
+                s8 += sv;
+                x8 = fmaf(f, dx, x8);
+                y8 = fmaf(f, dy, y8);
+                z8 = fmaf(f, dz, z8);
+            }
+            S += s8;
+            gx += x8;
+            gy += y8;
+            gz += z8;
+        }
+    }
+    for (int o = 1; o < L; o <<= 1) {  // within the member's lanes (aligned groups of a wavefront)
+        S += __shfl_xor(S, o, 64);
         gx += __shfl_xor(gx, o, 64);
         gy += __shfl_xor(gy, o, 64);
         gz += __shfl_xor(gz, o, 64);
     }
-    double S[1] = {live && !sideB && l == 0 ? sv : 0.0};
     if (J && live && l == 0)
-        st_slot(J, (int64_t)w * cs.nslots + cv.slot0 + i, make_double3(gx * cv.scale, gy * cv.scale, gz * cv.scale));
-    block_sum<1>(S, lds);
-    if (threadIdx.x == 0) vpart[(int64_t)w * cs.vblk_per_walker + cv.vblk0 + blockIdx.x] = S[0];
+        st_slot(J, (int64_t)w * cs.nslots + mine0 + i, make_double3(gx * cv.scale, gy * cv.scale, gz * cv.scale));
+    if (side == 0) {  // uniform per workgroup
+        double v[1] = {live && l == 0 ? S : 0.0};
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0) vpart[(int64_t)w * cs.vblk_per_walker + cv.vblk0 + blockIdx.x] = v[0];
+    }
 }
 
-// one wavefront per (walker, coordination CV): the value records of its
-// member blocks in a fixed order (lane-strided, then a butterfly), times the
+// one wavefront per (walker, coordination CV): the value records of its A
+// side's blocks in a fixed order (lane-strided, then a butterfly), times the
 // CV's scale.
 __global__ void __launch_bounds__(64) k_coord_value(CvSet cs, const double *vpart, double *xi, int32_t ncoord)
 {
@@ -259,7 +222,7 @@ __global__ void __launch_bounds__(64) k_coord_value(CvSet cs, const double *vpar
     for (; c < cs.ncv; ++c)
         if (cs.cv[c].kind == CV_COORD && seen++ == k) break;
     const CvDesc cv = cs.cv[c];
-    const int nblk = (cv.na + cv.nb + kCnFinPer - 1) / kCnFinPer;
+    const int per = kBlock / cv.lanes, nblk = (cv.na + per - 1) / per;
     const double *p = vpart + (int64_t)w * cs.vblk_per_walker + cv.vblk0;
     double v = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 64) v += p[b];
@@ -269,21 +232,19 @@ __global__ void __launch_bounds__(64) k_coord_value(CvSet cs, const double *vpar
 
 }  // namespace
 
-hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *cn_part,
+hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *cn_vpart,
                      int64_t /*max_atoms_per_walker*/, hipStream_t s)
 {
     int ndih = 0, nrg = 0, ncn = 0;
-    int max_tiles_x = 0, max_blk = 0;
+    int max_blk = 0;
     for (int c = 0; c < cs.ncv; ++c) {
         const CvDesc &d = cs.cv[c];
         if (d.kind == CV_DIHEDRAL) ++ndih;
         if (d.kind == CV_GYRATION) ++nrg;
         if (d.kind == CV_COORD) {
             ++ncn;
-            max_blk = max(max_blk, (d.na + d.nb + kCnFinPer - 1) / kCnFinPer);
-            int ta = (d.na + kBlock - 1) / kBlock * d.nchunk_a;
-            int tb = (d.nb + kBlock - 1) / kBlock * d.nchunk_b;
-            max_tiles_x = max(max_tiles_x, max(ta, tb));
+            const int per = kBlock / d.lanes;
+            max_blk = max(max_blk, (max(d.na, d.nb) + per - 1) / per);
         }
     }
     if (ndih) {
@@ -299,21 +260,14 @@ hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *
         if (e != hipSuccess) return e;
     }
     if (ncn) {
-        CnPart *part = reinterpret_cast<CnPart *>(cn_part);
-        dim3 grid(max_tiles_x, 2, (unsigned)t.W * ncn);
+        dim3 grid((unsigned)max_blk, 2, (unsigned)t.W * ncn);
         if (pos.f64)
-            hipLaunchKernelGGL(k_coord_pairs<double>, grid, dim3(kBlock), 0, s, cs, t, pos, part, ncn);
+            hipLaunchKernelGGL(k_coord_pairs<double>, grid, dim3(kBlock), 0, s, cs, t, pos, cn_vpart, J, ncn);
         else
-            hipLaunchKernelGGL(k_coord_pairs<float>, grid, dim3(kBlock), 0, s, cs, t, pos, part, ncn);
+            hipLaunchKernelGGL(k_coord_pairs<float>, grid, dim3(kBlock), 0, s, cs, t, pos, cn_vpart, J, ncn);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        // value records follow the W walkers' chunk records
-        double *vpart = cn_part + 4 * (int64_t)t.W * cs.part_per_walker;
-        hipLaunchKernelGGL(k_coord_finalize, dim3((unsigned)max_blk, (unsigned)t.W * ncn), dim3(kBlock), 0, s, cs, t,
-                           part, vpart, J, ncn);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_coord_value, dim3((unsigned)t.W * ncn), dim3(64), 0, s, cs, vpart, xi, ncn);
+        hipLaunchKernelGGL(k_coord_value, dim3((unsigned)t.W * ncn), dim3(64), 0, s, cs, cn_vpart, xi, ncn);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

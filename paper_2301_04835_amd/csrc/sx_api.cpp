@@ -348,7 +348,7 @@ sx_status make_plan(sx_ctx *c)
                 }
         }
     }
-    int64_t part = 0, vblk = 0;
+    int64_t vblk = 0;
     for (int d = 0; d < ncv; ++d) {
         const CvDef &cv = c->cvs[d];
         CvDesc &ds = cs.cv[d];
@@ -393,24 +393,20 @@ sx_status make_plan(sx_ctx *c)
             ds.inv_r0 = (float)(1.0 / cv.r0);
             ds.rcut2 = cv.rcut > 0 ? (float)(cv.rcut * cv.rcut) : 0.f;
             ds.scale = cv.normalize ? (float)(1.0 / cv.a.size()) : 1.f;
-            // partner chunk: halve until the pair grid has >= 1024 workgroups
-            int chunk = 256;
-            auto blocks = [&](int ch) {
-                int64_t ta = (ds.na + kBlock - 1) / kBlock * (int64_t)((ds.nb + ch - 1) / ch);
-                int64_t tb = (ds.nb + kBlock - 1) / kBlock * (int64_t)((ds.na + ch - 1) / ch);
-                return (ta + tb) * (int64_t)(c->atom_off.empty() ? 1 : c->W);
+            // lanes per member: 64, halved while the pair grid would still
+            // have >= 1024 workgroups at half as many
+            auto blocks = [&](int L) {
+                const int per = kBlock / L;
+                return ((int64_t)(ds.na + per - 1) / per + (ds.nb + per - 1) / per) *
+                       (int64_t)(c->atom_off.empty() ? 1 : c->W);
             };
-            while (chunk > 32 && blocks(chunk) < 1024) chunk >>= 1;
-            ds.chunk = chunk;
-            ds.nchunk_a = (ds.nb + chunk - 1) / chunk;
-            ds.nchunk_b = (ds.na + chunk - 1) / chunk;
-            ds.part0 = part;
-            part += (int64_t)ds.na * ds.nchunk_a + (int64_t)ds.nb * ds.nchunk_b;
+            int L = 64;
+            while (L > 1 && blocks(L / 2) >= 1024) L >>= 1;
+            ds.lanes = L;
             ds.vblk0 = (int32_t)vblk;
-            vblk += (ds.na + ds.nb + kCnFinPer - 1) / kCnFinPer;
+            vblk += (ds.na + kBlock / L - 1) / (kBlock / L);
         }
     }
-    cs.part_per_walker = part;
     cs.vblk_per_walker = vblk;
     p.all_dihedral = true;
     for (auto &cv : c->cvs) p.all_dihedral = p.all_dihedral && cv.kind == CV_DIHEDRAL;
@@ -545,7 +541,7 @@ sx_status make_plan(sx_ctx *c)
     p.w_dV = lw.take(sizeof(double) * p.W * p.D);
     p.w_J = lw.take(sizeof(float) * 3 * (size_t)p.W * p.nslots);
     p.w_part = lw.take(sizeof(double) * 4 * (size_t)std::max<int64_t>(p.ntiles_max, p.shared_records));
-    p.w_cnpart = lw.take(32 * (size_t)p.W * part + sizeof(double) * (size_t)p.W * p.cs.vblk_per_walker);
+    p.w_cnpart = lw.take(sizeof(double) * (size_t)p.W * p.cs.vblk_per_walker);
     p.abf_nblk = (c->method == M_ABF && p.U > kAbfSplitU) ? (p.U + kBlock - 1) / kBlock : 0;
     p.w_abfpart = lw.take(sizeof(double) * (kMaxBiasDim * kMaxBiasDim + kMaxBiasDim) * (size_t)p.W * p.abf_nblk);
     p.w_abfcoef = lw.take(p.abf_nblk ? sizeof(double) * (size_t)p.W * p.D : 0);

@@ -45,25 +45,20 @@ struct CvDesc {
     float r0, inv_r0;
     float rcut2;    // <= 0: no cut
     float scale;    // 1 or 1/na
-    int32_t chunk;  // coordination all-pairs: partner chunk size
-    int32_t nchunk_a, nchunk_b;  // chunks over B (for side A) and over A (side B)
-    int64_t part0;  // coordination: first partial record of this CV (per walker)
-    int32_t vblk0;  // coordination: first value record of this CV (per walker)
+    int32_t lanes;  // coordination all-pairs: lanes per member (a power of two <= 64)
+    int32_t vblk0;  // coordination all-pairs: first value record of this CV (per walker)
     int32_t atom[4];  // dihedral: its four atoms (walker-relative)
     int32_t ga, gb;   // cell-list coordination: the two atom groups
     int32_t cn;       // cell-list coordination: index among those CVs
     double rcut;      // the cut (FP64), for decisions at its edge
 };
 
-constexpr int kCnFinPer = 32;  // coordination members per workgroup of the all-pairs finalize
-
 struct CvSet {
     int32_t ncv, D;
     CvDesc cv[kMaxCv];
     double box[3], inv_box[3];  // 0: open
     int32_t nslots;
-    int64_t part_per_walker;   // coordination partial records per walker
-    int64_t vblk_per_walker;   // coordination value records per walker (one per kCnFinPer members)
+    int64_t vblk_per_walker;   // coordination value records per walker (one per A-side member block)
 };
 
 // Common walker tables.
