@@ -55,20 +55,12 @@ __device__ __forceinline__ void abf_atom_terms(const AbfArgs &a, int32_t w, int 
     }
 }
 
-// What the update reads that does not depend on the sums: xi, its bin (row
-// major, first CV slowest), the bin's count and force sums (the samples
-// before this step), FUNN's bias, the momentum estimator's previous values
-// and the device step counter.  Every lane of the workgroup computes the
-// same addresses, so the loads go through the scalar cache and are in
-// flight while the sums are formed.
-struct AbfPre {
-    double xi[MD], F[MD], bext[MD], bprev[MD], wpprev[MD];
-    int64_t k, dstep;
-    uint32_t cnt;
-    int32_t has;
-    bool inr;
-};
-
+// What the update reads that does not depend on the sums (AbfPre): xi, its
+// bin (row major, first CV slowest), the bin's count and force sums (the
+// samples before this step), FUNN's bias, the momentum estimator's previous
+// values and the device step counter.  Called by every lane of a workgroup,
+// the addresses are uniform, so the loads go through the scalar cache and
+// are in flight while the sums are formed.
 __device__ __forceinline__ AbfPre abf_prefetch(const AbfArgs &a, int32_t w)
 {
     AbfPre r{};
@@ -103,14 +95,19 @@ __device__ __forceinline__ AbfPre abf_prefetch(const AbfArgs &a, int32_t w)
     return r;
 }
 
-// One thread, walker w, the reduced G and u and the prefetched values: solve
-// G x = u, form theta, take the bias of xi's bin, add the sample, keep the
-// momentum estimator's state, write the outputs; the bias along the CVs
-// goes to coef[0..D).
-__device__ void abf_solve_update(const AbfArgs &a, int32_t w, const double (&acc)[NA], const AbfPre &pre,
-                                 double *coef)
+// One thread, the reduced G and u and the prefetched values: solve G x = u,
+// form theta, and take the bias of xi's bin (zero outside the grid or when x
+// or theta is not finite).  A pure function of its inputs, so every
+// workgroup that evaluates it gets the same bits.
+struct AbfOut {
+    double x[MD], theta[MD], b[MD];
+    bool sample, finite;
+};
+
+__device__ AbfOut abf_solve(const AbfArgs &a, const double (&acc)[NA], const AbfPre &pre)
 {
     const int D = a.D;
+    AbfOut r{};
     // solve G x = u by Gaussian elimination with partial pivoting
     double G[MD][MD + 1];
     for (int d = 0; d < D; ++d) {
@@ -119,56 +116,60 @@ __device__ void abf_solve_update(const AbfArgs &a, int32_t w, const double (&acc
     }
     for (int col = 0; col < D; ++col) {
         int piv = col;
-        for (int r = col + 1; r < D; ++r)
-            if (fabs(G[r][col]) > fabs(G[piv][col])) piv = r;
+        for (int q = col + 1; q < D; ++q)
+            if (fabs(G[q][col]) > fabs(G[piv][col])) piv = q;
         if (piv != col)
             for (int e = 0; e <= D; ++e) {
                 double tmp = G[col][e];
                 G[col][e] = G[piv][e];
                 G[piv][e] = tmp;
             }
-        for (int r = col + 1; r < D; ++r) {
-            const double fct = G[r][col] / G[col][col];
-            for (int e = col; e <= D; ++e) G[r][e] -= fct * G[col][e];
+        for (int q = col + 1; q < D; ++q) {
+            const double fct = G[q][col] / G[col][col];
+            for (int e = col; e <= D; ++e) G[q][e] -= fct * G[col][e];
         }
     }
-    double x[MD];
     for (int d = D - 1; d >= 0; --d) {
-        double s = G[d][D];
-        for (int e = d + 1; e < D; ++e) s -= G[d][e] * x[e];
-        x[d] = s / G[d][d];
+        double sd = G[d][D];
+        for (int e = d + 1; e < D; ++e) sd -= G[d][e] * r.x[e];
+        r.x[d] = sd / G[d][d];
     }
-    double theta[MD] = {0.0, 0.0, 0.0};
-    bool sample = true;
+    r.sample = true;
     if (a.estimator == 1) {
-        sample = pre.has != 0;
-        for (int d = 0; d < D; ++d) theta[d] = pre.bprev[d] - (x[d] - pre.wpprev[d]) / a.dt;
+        r.sample = pre.has != 0;
+        for (int d = 0; d < D; ++d) r.theta[d] = pre.bprev[d] - (r.x[d] - pre.wpprev[d]) / a.dt;
     } else {
-        for (int d = 0; d < D; ++d) theta[d] = -x[d];
+        for (int d = 0; d < D; ++d) r.theta[d] = -r.x[d];
     }
-    bool finite = true;
-    for (int d = 0; d < D; ++d) finite = finite && isfinite(theta[d]) && isfinite(x[d]);
-    if (!finite) atomicOr(a.flags, kFlagNonFinite);
-    double b[MD] = {0.0, 0.0, 0.0};
-    if (pre.inr && finite) {
+    r.finite = true;
+    for (int d = 0; d < D; ++d) r.finite = r.finite && isfinite(r.theta[d]) && isfinite(r.x[d]);
+    if (pre.inr && r.finite) {
         const double den = (double)max((int64_t)pre.cnt, (int64_t)a.n_threshold);
-        for (int d = 0; d < D; ++d) b[d] = a.b_ext ? pre.bext[d] : den > 0.0 ? pre.F[d] / den : 0.0;
-        if (sample) {
-            a.N[(int64_t)w * a.nbins_total + pre.k] = pre.cnt + 1u;
-            double *Fk = a.Fsum + ((int64_t)w * a.nbins_total + pre.k) * D;
-            for (int d = 0; d < D; ++d) Fk[d] = pre.F[d] + theta[d];
-        }
+        for (int d = 0; d < D; ++d) r.b[d] = a.b_ext ? pre.bext[d] : den > 0.0 ? pre.F[d] / den : 0.0;
+    }
+    return r;
+}
+
+// Once per walker and step: add the sample to the grid, keep the momentum
+// estimator's state, write the outputs and advance the step counter.
+__device__ void abf_commit(const AbfArgs &a, int32_t w, const AbfPre &pre, const AbfOut &r)
+{
+    const int D = a.D;
+    if (!r.finite) atomicOr(a.flags, kFlagNonFinite);
+    if (pre.inr && r.finite && r.sample) {
+        a.N[(int64_t)w * a.nbins_total + pre.k] = pre.cnt + 1u;
+        double *Fk = a.Fsum + ((int64_t)w * a.nbins_total + pre.k) * D;
+        for (int d = 0; d < D; ++d) Fk[d] = pre.F[d] + r.theta[d];
     }
     if (a.estimator == 1) {  // for the next step: this step's W p and bias
         for (int d = 0; d < D; ++d) {
-            a.Wp_prev[(int64_t)w * D + d] = x[d];
-            a.b_prev[(int64_t)w * D + d] = b[d];
+            a.Wp_prev[(int64_t)w * D + d] = r.x[d];
+            a.b_prev[(int64_t)w * D + d] = r.b[d];
         }
         a.has_prev[w] = 1;
     }
     for (int d = 0; d < D; ++d) {
-        coef[d] = b[d];
-        if (a.dV_out) a.dV_out[(int64_t)w * D + d] = -b[d];
+        if (a.dV_out) a.dV_out[(int64_t)w * D + d] = -r.b[d];
         if (a.xi_out) a.xi_out[(int64_t)w * D + d] = pre.xi[d];
     }
     if (a.V_out) a.V_out[w] = 0.0;
@@ -186,21 +187,30 @@ __global__ void __launch_bounds__(kBlock) k_abf(AbfArgs a)
     for (int j = 0; j < NA; ++j) acc[j] = 0.0;
     for (int u = threadIdx.x; u < a.tabs.U; u += blockDim.x) abf_atom_terms(a, w, u, acc);
     block_sum0<NA>(acc, lds);
-    if (threadIdx.x == 0) abf_solve_update(a, w, acc, pre, s_coef);
+    if (threadIdx.x == 0) {
+        const AbfOut r = abf_solve(a, acc, pre);
+        abf_commit(a, w, pre, r);
+        for (int d = 0; d < a.D; ++d) s_coef[d] = r.b[d];
+    }
     __syncthreads();
     gather_forces(a.tabs, a.J + (int64_t)w * a.nslots * 3, w, s_coef, a.F);
 }
 
-// Walkers with many touched atoms, in three launches: (1) one lane per
-// touched atom, the terms reduced per workgroup (fixed tree) into a record
-// per (walker, block); (2) one wavefront per walker sums its records in a
-// fixed order and solves and updates as above, the bias along the CVs going
-// to a.coef; (3) the force gather, one lane per (walker, touched atom).
+// Walkers with many touched atoms, in two launches: (1) one lane per touched
+// atom, the terms reduced per workgroup (fixed tree) into a record per
+// (walker, block), and the first workgroup's first lane keeps the walker's
+// AbfPre in the workspace; (2) per (walker, block of touched atoms): the
+// first wavefront sums the walker's records in a fixed order and its first
+// lane solves from them and the kept AbfPre -- every workgroup the same bits
+// -- the first workgroup alone commits the sample, and every workgroup
+// gathers the forces of its atoms.  The grid is read in (1) and written in
+// (2) by one lane, so no workgroup reads it while it changes.
 __global__ void __launch_bounds__(kBlock) k_abf_part(AbfArgs a)
 {
     __shared__ double lds[NA * (kBlock / 64)];
     const int32_t w = blockIdx.y;
     const int u = blockIdx.x * kBlock + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.pre[w] = abf_prefetch(a, w);
     double acc[NA];
 #pragma unroll
     for (int j = 0; j < NA; ++j) acc[j] = 0.0;
@@ -213,22 +223,32 @@ __global__ void __launch_bounds__(kBlock) k_abf_part(AbfArgs a)
     }
 }
 
-__global__ void __launch_bounds__(64) k_abf_solve(AbfArgs a)
+__global__ void __launch_bounds__(kBlock) k_abf_finish(AbfArgs a)
 {
-    const int32_t w = blockIdx.x;
-    const AbfPre pre = abf_prefetch(a, w);
-    double acc[NA];
+    __shared__ double s_coef[kMaxCv];
+    const int32_t w = blockIdx.y;
+    if (threadIdx.x < 64) {  // the first wavefront
+        const AbfPre pre = a.pre[w];
+        double acc[NA];
 #pragma unroll
-    for (int j = 0; j < NA; ++j) acc[j] = 0.0;
-    for (int b = threadIdx.x; b < a.nblk; b += 64) {
-        const double *r = a.part + ((int64_t)w * a.nblk + b) * NA;
+        for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+        for (int b = threadIdx.x; b < a.nblk; b += 64) {
+            const double *r = a.part + ((int64_t)w * a.nblk + b) * NA;
 #pragma unroll
-        for (int j = 0; j < NA; ++j) acc[j] += r[j];
+            for (int j = 0; j < NA; ++j) acc[j] += r[j];
+        }
+#pragma unroll
+        for (int j = 0; j < NA; ++j)
+            for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
+        if (threadIdx.x == 0) {
+            const AbfOut r = abf_solve(a, acc, pre);
+            if (blockIdx.x == 0) abf_commit(a, w, pre, r);
+            for (int d = 0; d < a.D; ++d) s_coef[d] = r.b[d];
+        }
     }
-#pragma unroll
-    for (int j = 0; j < NA; ++j)
-        for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
-    if (threadIdx.x == 0) abf_solve_update(a, w, acc, pre, a.coef + (int64_t)w * a.D);
+    __syncthreads();
+    const int u = blockIdx.x * kBlock + threadIdx.x;
+    if (u < a.tabs.U) gather_atom(a.tabs, a.J + (int64_t)w * a.nslots * 3, w, s_coef, a.F, u);
 }
 
 }  // namespace
@@ -242,10 +262,8 @@ hipError_t launch_abf(const AbfArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_abf_part, dim3((unsigned)a.nblk, (unsigned)a.tabs.W), dim3(kBlock), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_abf_solve, dim3(a.tabs.W), dim3(64), 0, s, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_gather(a.tabs, a.J, a.nslots, a.D, a.coef, 1.0, a.F, s);
+    hipLaunchKernelGGL(k_abf_finish, dim3((unsigned)a.nblk, (unsigned)a.tabs.W), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace sx

@@ -89,8 +89,8 @@ struct Plan {
     Sub w_sgFlag, w_sgRed;
     // workspace sub-buffers
     Sub w_xi, w_V, w_dV, w_J, w_part, w_cnpart;
-    int32_t abf_nblk = 0;  // ABF in three launches when > 0 (blocks of touched atoms)
-    Sub w_abfpart, w_abfcoef;
+    int32_t abf_nblk = 0;  // ABF in two launches when > 0 (blocks of touched atoms)
+    Sub w_abfpart, w_abfpre;
     Sub w_atom_off, w_tiles, w_wrec;
     Sub w_slot_atom, w_slot_cv, w_touched, w_inv_ptr, w_inv_slot;
     size_t ws_bytes = 0;
@@ -544,7 +544,7 @@ sx_status make_plan(sx_ctx *c)
     p.w_cnpart = lw.take(sizeof(double) * (size_t)p.W * p.cs.vblk_per_walker);
     p.abf_nblk = (c->method == M_ABF && p.U > kAbfSplitU) ? (p.U + kBlock - 1) / kBlock : 0;
     p.w_abfpart = lw.take(sizeof(double) * (kMaxBiasDim * kMaxBiasDim + kMaxBiasDim) * (size_t)p.W * p.abf_nblk);
-    p.w_abfcoef = lw.take(p.abf_nblk ? sizeof(double) * (size_t)p.W * p.D : 0);
+    p.w_abfpre = lw.take(p.abf_nblk ? sizeof(AbfPre) * (size_t)p.W : 0);
     p.w_atom_off = lw.take(sizeof(int64_t) * (p.W + 1));
     p.w_tiles = lw.take(sizeof(TileRec) * p.ntiles_max);
     p.w_wrec = lw.take(sizeof(WalkerRec) * p.W);
@@ -1026,7 +1026,7 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.dstep = at<int64_t>(c->state, p.s_hdr);
         a.nblk = p.abf_nblk;
         a.part = at<double>(c->ws, p.w_abfpart);
-        a.coef = at<double>(c->ws, p.w_abfcoef);
+        a.pre = at<AbfPre>(c->ws, p.w_abfpre);
         hipError_t e = launch_abf(a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "ABF kernel");
     }

@@ -136,6 +136,19 @@ struct HillArgs {
     ForceView F;
 };
 
+// What an ABF update reads before the step's sums are known (per walker):
+// xi, its bin k (inr: inside the grid), the bin's count and force sums, the
+// FUNN bias, the momentum estimator's previous bias and W p and whether there
+// was a previous step, and the device step counter (when the step is not
+// given).
+struct AbfPre {
+    double xi[kMaxBiasDim], F[kMaxBiasDim], bext[kMaxBiasDim], bprev[kMaxBiasDim], wpprev[kMaxBiasDim];
+    int64_t k, dstep;
+    uint32_t cnt;
+    int32_t has;
+    bool inr;
+};
+
 struct AbfArgs {
     int32_t D;
     const double *xi;     // W x D
@@ -166,13 +179,14 @@ struct AbfArgs {
     // FUNN: the bias is this W x D gradient of a network fitted to the mean
     // forces (null: the grid's Fsum / max(N, N_thr))
     const double *b_ext;
-    // nblk > 0: the three-launch form for walkers with many touched atoms,
-    // with W x nblk records of (D_max^2 + D_max) doubles in part and the
-    // W x D bias along the CVs in coef (workspace)
+    // nblk > 0: the two-launch form for walkers with many touched atoms,
+    // with W x nblk records of (D_max^2 + D_max) doubles in part and one
+    // AbfPre per walker in pre (workspace)
     int32_t nblk;
-    double *part, *coef;
+    double *part;
+    AbfPre *pre;
 };
-constexpr int kAbfSplitU = 2 * kBlock;  // touched atoms above which ABF takes the three-launch form
+constexpr int kAbfSplitU = 2 * kBlock;  // touched atoms above which ABF takes the two-launch form
 
 // Hill sum over one shared list at nq query points.
 // Metadynamics bias kept on a grid: V and dV/dxi of each hill list at the
