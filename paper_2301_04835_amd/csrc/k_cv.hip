@@ -4,11 +4,14 @@
 //
 //  * dihedral angle: one lane per (walker, dihedral), FP64 arithmetic;
 //  * radius of gyration: one workgroup per (walker, CV), two passes in FP64;
-//  * coordination number, all pairs: a 3-D grid of member blocks x side (A
-//    or B) x (walker, CV).  L lanes own one member of their side and gather
+//  * coordination number, all pairs: member blocks x side (A or B) x
+//    (walker, CV).  L lanes own one member of their side and gather
 //    over the other group staged in LDS, so every sum has exactly one writer
 //    (no atomics); a one-wavefront kernel sums the CV value's per-block
 //    records in a fixed order (bitwise deterministic).
+//
+// All three run in one launch (k_cv_values), each workgroup in one role, so
+// the kinds overlap on the device instead of following one another.
 #include "dev_cv.h"
 
 namespace sx {
@@ -22,11 +25,12 @@ __device__ __forceinline__ void st_slot(float *J, int64_t slot, double3 g)
 }
 
 // ------------------------------------------------------------------ dihedral
-// One lane per (walker, dihedral CV), FP64 (see dihedral_fp64).
-__global__ void __launch_bounds__(kBlock) k_dihedral(CvSet cs, WalkerTabs t, PosView pos, double *xi, float *J,
-                                                     int32_t ndih)
+// One lane per (walker, dihedral CV), FP64 (see dihedral_fp64); block bx of
+// the dihedral range.
+__device__ __forceinline__ void dihedral_block(const CvSet &cs, const WalkerTabs &t, const PosView &pos, double *xi,
+                                               float *J, int32_t ndih, int64_t bx)
 {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t gid = bx * blockDim.x + threadIdx.x;
     if (gid >= (int64_t)t.W * ndih) return;
     int32_t w = (int32_t)(gid / ndih), j = (int32_t)(gid % ndih);
     int c = 0, seen = 0;
@@ -71,13 +75,13 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *lds /* N * kBl
 
 // ------------------------------------------------------- radius of gyration
 // Rg = sqrt((1/n) sum |r_i - c|^2), c = (1/n) sum r_i; dRg/dr_i = (r_i - c)/(n Rg).
-__global__ void __launch_bounds__(kBlock) k_gyration(CvSet cs, WalkerTabs t, PosView pos, double *xi, float *J)
+// One workgroup per (walker w, gyration CV j); lds: 4 * kBlock / 64 doubles.
+__device__ __forceinline__ void gyration_block(const CvSet &cs, const WalkerTabs &t, const PosView &pos, double *xi,
+                                               float *J, int32_t w, int j, double *lds)
 {
-    __shared__ double lds[4 * (kBlock / 64)];
-    const int32_t w = blockIdx.y;
     int c = 0, seen = 0;
     for (; c < cs.ncv; ++c)
-        if (cs.cv[c].kind == CV_GYRATION && seen++ == (int)blockIdx.x) break;
+        if (cs.cv[c].kind == CV_GYRATION && seen++ == j) break;
     const CvDesc cv = cs.cv[c];
     const int64_t base = t.atom_off[w];
     const int n = cv.na;
@@ -137,25 +141,23 @@ __device__ __forceinline__ float min_img(double d, double L, double iL) { return
 // reduced per workgroup (fixed tree) into one value record per block, which
 // k_coord_value sums in order.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_coord_pairs(CvSet cs, WalkerTabs t, PosView pos, double *vpart, float *J,
-                                                         int32_t ncoord)
+__device__ __forceinline__ void coord_block(const CvSet &cs, const WalkerTabs &t, const PosView &pos, double *vpart,
+                                            float *J, int32_t ncoord, int bx, int side, int z, Partner *oth,
+                                            double *lds)
 {
-    __shared__ Partner oth[kCnStage];
-    __shared__ double lds[kBlock / 64];
-    const int32_t w = blockIdx.z / ncoord, k = blockIdx.z % ncoord;
+    const int32_t w = z / ncoord, k = z % ncoord;
     int c = 0, seen = 0;
     for (; c < cs.ncv; ++c)
         if (cs.cv[c].kind == CV_COORD && seen++ == k) break;
     const CvDesc cv = cs.cv[c];
-    const int side = blockIdx.y;
     const int nmine = side ? cv.nb : cv.na, noth = side ? cv.na : cv.nb;
     const int mine0 = cv.slot0 + (side ? cv.na : 0), oth0 = cv.slot0 + (side ? 0 : cv.na);
     const int L = cv.lanes, per = kBlock / L;
-    if ((int)blockIdx.x * per >= nmine) return;  // whole workgroup idle: uniform exit
+    if (bx * per >= nmine) return;  // whole workgroup idle: uniform exit
     const int64_t base = t.atom_off[w];
     const double Lb[3] = {cs.box[0], cs.box[1], cs.box[2]};
     const double iL[3] = {cs.inv_box[0], cs.inv_box[1], cs.inv_box[2]};
-    const int i = blockIdx.x * per + threadIdx.x / L, l = threadIdx.x % L;
+    const int i = bx * per + threadIdx.x / L, l = threadIdx.x % L;
     const bool live = i < nmine;
     const int32_t me = live ? t.slot_atom[mine0 + i] : -1;
     const double3 ri = live ? ld_d3<T>(pos, base + me) : make_double3(0.0, 0.0, 0.0);
@@ -208,8 +210,38 @@ __global__ void __launch_bounds__(kBlock) k_coord_pairs(CvSet cs, WalkerTabs t, 
     if (side == 0) {  // uniform per workgroup
         double v[1] = {live && l == 0 ? S : 0.0};
         block_sum<1>(v, lds);
-        if (threadIdx.x == 0) vpart[(int64_t)w * cs.vblk_per_walker + cv.vblk0 + blockIdx.x] = v[0];
+        if (threadIdx.x == 0) vpart[(int64_t)w * cs.vblk_per_walker + cv.vblk0 + bx] = v[0];
     }
+}
+
+// All CV values and Jacobians in one launch (a 1-D grid): first the pair
+// blocks of the all-pairs coordination numbers (x = member block of one
+// side, then side, then walker * ncoord + k), then one workgroup per
+// (walker, gyration CV), then the dihedral lanes.  Each workgroup takes one
+// role, so its barriers are uniform.
+struct CvGrid {
+    int32_t ncn, nrg, ndih, cn_x;  // cn_x: member blocks per (side, walker, CV)
+    int64_t cn_blocks, rg_blocks;
+};
+
+template <typename T, bool CN>
+__global__ void __launch_bounds__(kBlock) k_cv_values(CvSet cs, WalkerTabs t, PosView pos, double *xi, float *J,
+                                                       double *vpart, CvGrid g)
+{
+    __shared__ Partner oth[CN ? kCnStage : 1];
+    __shared__ double lds[4 * (kBlock / 64)];
+    int64_t b = blockIdx.x;
+    if (CN && b < g.cn_blocks) {
+        const int bx = (int)(b % g.cn_x), side = (int)((b / g.cn_x) % 2), z = (int)(b / (2 * (int64_t)g.cn_x));
+        coord_block<T>(cs, t, pos, vpart, J, g.ncn, bx, side, z, oth, lds);
+        return;
+    }
+    b -= g.cn_blocks;
+    if (b < g.rg_blocks) {
+        gyration_block(cs, t, pos, xi, J, (int32_t)(b / g.nrg), (int)(b % g.nrg), lds);
+        return;
+    }
+    dihedral_block(cs, t, pos, xi, J, g.ndih, b - g.rg_blocks);
 }
 
 // one wavefront per (walker, coordination CV): the value records of its A
@@ -235,43 +267,37 @@ __global__ void __launch_bounds__(64) k_coord_value(CvSet cs, const double *vpar
 hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *cn_vpart,
                      int64_t /*max_atoms_per_walker*/, hipStream_t s)
 {
-    int ndih = 0, nrg = 0, ncn = 0;
-    int max_blk = 0;
+    CvGrid g{};
     for (int c = 0; c < cs.ncv; ++c) {
         const CvDesc &d = cs.cv[c];
-        if (d.kind == CV_DIHEDRAL) ++ndih;
-        if (d.kind == CV_GYRATION) ++nrg;
+        if (d.kind == CV_DIHEDRAL) ++g.ndih;
+        if (d.kind == CV_GYRATION) ++g.nrg;
         if (d.kind == CV_COORD) {
-            ++ncn;
+            ++g.ncn;
             const int per = kBlock / d.lanes;
-            max_blk = max(max_blk, (max(d.na, d.nb) + per - 1) / per);
+            g.cn_x = max(g.cn_x, (max(d.na, d.nb) + per - 1) / per);
         }
     }
-    if (ndih) {
-        int64_t n = (int64_t)t.W * ndih;
-        hipLaunchKernelGGL(k_dihedral, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cs, t, pos,
-                           xi, J, ndih);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (nrg) {
-        hipLaunchKernelGGL(k_gyration, dim3(nrg, t.W), dim3(kBlock), 0, s, cs, t, pos, xi, J);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (ncn) {
-        dim3 grid((unsigned)max_blk, 2, (unsigned)t.W * ncn);
+    g.cn_blocks = (int64_t)g.cn_x * 2 * t.W * g.ncn;
+    g.rg_blocks = (int64_t)t.W * g.nrg;
+    const int64_t dih_blocks = ((int64_t)t.W * g.ndih + kBlock - 1) / kBlock;
+    const int64_t blocks = g.cn_blocks + g.rg_blocks + dih_blocks;
+    if (blocks == 0) return hipSuccess;
+    if (g.ncn) {
         if (pos.f64)
-            hipLaunchKernelGGL(k_coord_pairs<double>, grid, dim3(kBlock), 0, s, cs, t, pos, cn_vpart, J, ncn);
+            hipLaunchKernelGGL((k_cv_values<double, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos, xi,
+                               J, cn_vpart, g);
         else
-            hipLaunchKernelGGL(k_coord_pairs<float>, grid, dim3(kBlock), 0, s, cs, t, pos, cn_vpart, J, ncn);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_coord_value, dim3((unsigned)t.W * ncn), dim3(64), 0, s, cs, cn_vpart, xi, ncn);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_cv_values<float, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos, xi,
+                               J, cn_vpart, g);
+    } else {
+        hipLaunchKernelGGL((k_cv_values<float, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos, xi, J,
+                           cn_vpart, g);
     }
-    return hipSuccess;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !g.ncn) return e;
+    hipLaunchKernelGGL(k_coord_value, dim3((unsigned)t.W * g.ncn), dim3(64), 0, s, cs, cn_vpart, xi, g.ncn);
+    return hipGetLastError();
 }
 
 }  // namespace sx
