@@ -107,6 +107,35 @@ __device__ __forceinline__ uint8_t fallback_flag(const MlpArgs &a, const double 
     return (inside && a.mask[cell]) ? 0 : 1;
 }
 
+// A surrogate step's CVs (every CV a dihedral) for sample si: all D x 4
+// positions requested before any angle is formed, then each angle and its
+// gradient in FP64, xi and the Jacobian slots stored.
+template <typename T, int D>
+__device__ __forceinline__ void step_dihedrals(const MlpStep &st, int64_t si, double (&x)[D])
+{
+    const int64_t aoff = st.tabs.atom_off[si];
+    double3 r[D][4];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r[d][q] = ld_pos_t<T>(st.pos, aoff + st.cs.cv[d].atom[q]);
+    __builtin_amdgcn_sched_barrier(0);  // keep every load above the first angle's arithmetic
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const CvDesc &cv = st.cs.cv[d];
+        double3 g[4];
+        x[d] = dihedral_fp64<true>(r[d], g);
+        st.xi_ws[si * D + d] = x[d];
+        float *js = st.J + (si * st.nslots + cv.slot0) * 3;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            js[3 * q] = (float)g[q].x;
+            js[3 * q + 1] = (float)g[q].y;
+            js[3 * q + 2] = (float)g[q].z;
+        }
+    }
+}
+
 template <int H, int D, bool CVF>
 __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi, int64_t n, double *V, double *dV,
                                                      float *t_a2, float *t_dz2, float *t_y, float *t_dy,
@@ -126,27 +155,36 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
     const int row = lane & 15, kg = lane >> 4;
     const int64_t si = s0 + row;  // this lane's sample in the A operand
     const bool live = si < n;
+    // a surrogate step: this lane's layer-1 weights and layer-2 fragments
+    // requested before the CVs, so that they arrive during the position loads
+    float w1p[CVF ? KB : 1][8][F], b1p[CVF ? KB : 1][8];
+    bf16x8 w2p[CVF ? NT : 1][CVF ? KB : 1];
+    if (CVF) {
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = kb * 32 + kg * 8 + t;
+                b1p[kb][t] = bf(a.Pb, o.b1 + k);
+#pragma unroll
+                for (int q = 0; q < F; ++q) w1p[kb][t][q] = bf(a.Pb, o.W1 + k * F + q);
+            }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                w2p[nt][kb] = *reinterpret_cast<const bf16x8 *>(a.Pb + o.W2 + (nt * 16 + row) * H + kb * 32 + kg * 8);
+    }
     double x[D];
     if (CVF) {
         // the 16 lanes of row group 0 evaluate their walker's dihedrals
         // (FP64) and store xi and the Jacobian slots; a shuffle hands xi to
         // the lanes of the other row groups
         if (kg == 0 && live) {
-            const int64_t aoff = st.tabs.atom_off[si];
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const CvDesc &cv = st.cs.cv[d];
-                double3 g[4];
-                x[d] = dihedral_at<true>(cv, st.pos, aoff, g);
-                st.xi_ws[si * D + d] = x[d];
-                float *js = st.J + (si * st.nslots + cv.slot0) * 3;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    js[3 * q] = (float)g[q].x;
-                    js[3 * q + 1] = (float)g[q].y;
-                    js[3 * q + 2] = (float)g[q].z;
-                }
-            }
+            if (st.pos.f64)
+                step_dihedrals<double, D>(st, si, x);
+            else
+                step_dihedrals<float, D>(st, si, x);
         } else {
 #pragma unroll
             for (int d = 0; d < D; ++d) x[d] = 0.0;
@@ -167,13 +205,13 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int k = kb * 32 + kg * 8 + t;
-            float z = bf(a.Pb, o.b1 + k);
+            float z = CVF ? b1p[CVF ? kb : 0][t] : bf(a.Pb, o.b1 + k);
             float dz[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) dz[d] = 0.f;
 #pragma unroll
             for (int q = 0; q < F; ++q) {
-                const float w = bf(a.Pb, o.W1 + k * F + q);
+                const float w = CVF ? w1p[CVF ? kb : 0][t][q] : bf(a.Pb, o.W1 + k * F + q);
                 z = fmaf(w, f[q], z);
 #pragma unroll
                 for (int d = 0; d < D; ++d) dz[d] = fmaf(w, u[d][q], dz[d]);
@@ -206,7 +244,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
             // B operand: W2^T[k][j] = W2[j][k], 8 consecutive k of row j
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(a.Pb + o.W2 + j * H + kb * 32 + kg * 8);  // 16 B aligned
+            const bf16x8 bv = CVF ? w2p[CVF ? nt : 0][CVF ? kb : 0]
+                                  : *reinterpret_cast<const bf16x8 *>(a.Pb + o.W2 + j * H + kb * 32 + kg * 8);  // 16 B aligned
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kb], bv, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[kb], bv, acc, 0, 0, 0);
 #pragma unroll

@@ -247,3 +247,52 @@ def test_abf_many_touched_atoms_matches_oracle(gpu, estimator):
         assert int(N.sum()) == (T if estimator == 0 else T - 1)
         nz = grids[w].N > 0
         assert rel_inf(Fsum[nz], grids[w].Fsum[nz]) <= 1e-6
+
+
+@pytest.mark.parametrize("many", [False, True])
+def test_abf_graph_replay_matches_eager_steps(gpu, many):
+    """Replays of a captured 4-step graph against the same steps run eagerly
+    on a second context, bitwise (forces, bias along xi, histogram, force
+    sums), with eager work and synchronisations between the replays: the
+    one-launch form (phi/psi of two 22-atom walkers) and the two-launch form
+    (phi and Rg of 600 atoms, two 700-atom walkers)."""
+    W = 2
+    if many:
+        n = 700
+        cvs = [synth.backbone_cvs(4)[0], {"kind": "gyration", "idx": list(range(0, 600))}]
+        lo, hi, nb = [-np.pi, 1.0], [np.pi, 3.0], [16, 12]
+    else:
+        n = 22
+        cvs = synth.backbone_cvs(4)
+        lo, hi, nb = [-np.pi, -np.pi], [np.pi, np.pi], [16, 16]
+    g = np.random.default_rng(41)
+    pos = np.concatenate([synth.chain_template(n, 140 + w) for w in range(W)]).astype(np.float32)
+    fs = g.normal(0.0, 50.0, size=pos.shape).astype(np.float32)
+
+    def mk():
+        s = Sampler(0)
+        s.add_cvs(cvs)
+        s.set_walkers(np.arange(W + 1) * n)
+        s.abf(lo, hi, nb, 2)
+        s.bind()
+        return s
+
+    a, b = mk(), mk()
+    P, Fs = dev(pos), dev(fs)
+    Fa, Fb = torch.zeros_like(P), torch.zeros_like(P)
+    dVa = torch.zeros((W, 2), dtype=torch.float64, device=gpu)
+    dVb = torch.zeros_like(dVa)
+    a.graph_capture(4, P, forces=Fa, dV_out=dVa, sys_forces=Fs)
+    for rep in range(3):
+        a.graph_launch()
+        torch.cuda.synchronize()
+        for _ in range(4):
+            b.step(P, forces=Fb, dV_out=dVb, sys_forces=Fs)
+        torch.cuda.synchronize()
+        assert torch.equal(Fa, Fb) and torch.equal(dVa, dVb), rep
+    assert torch.any(dVa != 0)  # the bias is exercised (threshold 2)
+    assert a.get_step() == 12 and b.get_step() == 12
+    for w in range(W):
+        Na, Sa = a.abf_grid(w)
+        Nb, Sb = b.abf_grid(w)
+        assert int(Na.sum()) == 12 and np.array_equal(Na, Nb) and np.array_equal(Sa, Sb)
