@@ -27,6 +27,39 @@ __device__ __forceinline__ void gather_atom(const WalkerTabs &t, const float *Jw
     f[2 * F.sk] += (float)fz;
 }
 
+// Force gather from the table in kernel-argument form (SmallTabs): lane
+// u < U owns touched atom u of a walker whose atoms start at aoff and whose
+// Jacobian slots start at Jw.  small_rows requests the atom's current force,
+// the table row (the whole row: unused entries are zero, i.e. slot 0 of CV
+// 0, which exists) and every Jacobian row it names, and waits for none of
+// them; entries q >= nent are skipped where they are used.
+struct SmallGather {
+    float f0, f1, f2;
+    float *dst;
+};
+
+__device__ __forceinline__ void small_rows(const SmallTabs &st, const float *Jw, const ForceView &F, int64_t aoff,
+                                           int u, SmallGather &sg, int &nent, int32_t (&cvq)[kSmallPer],
+                                           float (&jr)[kSmallPer][3])
+{
+    nent = st.nent[u];
+    sg.dst = F.ptr + (aoff + st.touched[u]) * F.sa;
+    sg.f0 = sg.dst[0];
+    sg.f1 = sg.dst[F.sk];
+    sg.f2 = sg.dst[2 * F.sk];
+    int32_t e[kSmallPer];
+#pragma unroll
+    for (int q = 0; q < kSmallPer; ++q) e[q] = st.ent[u][q];
+#pragma unroll
+    for (int q = 0; q < kSmallPer; ++q) {
+        const int32_t slot = e[q] & 0xFFFFF;
+        cvq[q] = e[q] >> 20;
+        jr[q][0] = Jw[slot * 3 + 0];
+        jr[q][1] = Jw[slot * 3 + 1];
+        jr[q][2] = Jw[slot * 3 + 2];
+    }
+}
+
 // the whole walker, lanes of the workgroup striding over its touched atoms
 __device__ __forceinline__ void gather_forces(const WalkerTabs &t, const float *Jw, int32_t w, const double *coef,
                                               const ForceView &F)

@@ -252,41 +252,6 @@ __global__ void __launch_bounds__(kBlock) k_hill_tiles_persist(HillArgs a, CvSet
     }
 }
 
-// Force gather from the small table (kernel arguments): lane u < U owns
-// touched atom u.  Its current force is read before the bias is known so
-// that the load overlaps the partial reduction.
-struct SmallGather {
-    float f0, f1, f2;
-    float *dst;
-};
-
-// Lane u's row of the small table and the Jacobian rows it names, requested
-// together: the whole row is read (unused entries are zero, i.e. slot 0 of
-// CV 0, which exists), then every slot's row.  Entries q >= nent are left
-// in place and skipped where they are used, so nothing here waits for the
-// rows to arrive.
-__device__ __forceinline__ void small_rows(const HillArgs &a, int u, int32_t w, int64_t aoff, SmallGather &sg,
-                                           int &nent, int32_t (&cvq)[kSmallPer], float (&jr)[kSmallPer][3])
-{
-    const float *Jw = a.J + (int64_t)w * a.nslots * 3;
-    nent = a.small.nent[u];
-    sg.dst = a.F.ptr + (aoff + a.small.touched[u]) * a.F.sa;
-    sg.f0 = sg.dst[0];
-    sg.f1 = sg.dst[a.F.sk];
-    sg.f2 = sg.dst[2 * a.F.sk];
-    int32_t e[kSmallPer];
-#pragma unroll
-    for (int q = 0; q < kSmallPer; ++q) e[q] = a.small.ent[u][q];
-#pragma unroll
-    for (int q = 0; q < kSmallPer; ++q) {
-        const int32_t slot = e[q] & 0xFFFFF;
-        cvq[q] = e[q] >> 20;
-        jr[q][0] = Jw[slot * 3 + 0];
-        jr[q][1] = Jw[slot * 3 + 1];
-        jr[q][2] = Jw[slot * 3 + 2];
-    }
-}
-
 template <int D, bool FUSE>
 __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, PosView pos)
 {
@@ -307,7 +272,8 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     int nent = 0;
     int32_t cvq[kSmallPer];
     float jr[kSmallPer][3];
-    if (small_lane) small_rows(a, threadIdx.x, w, wr.aoff, sg, nent, cvq, jr);
+    if (small_lane)
+        small_rows(a.small, a.J + (int64_t)w * a.nslots * 3, a.F, wr.aoff, threadIdx.x, sg, nent, cvq, jr);
     if ((int)threadIdx.x < D) s_xi[threadIdx.x] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + threadIdx.x];
     double acc[1 + D];
 #pragma unroll
@@ -406,7 +372,7 @@ __global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs,
     double xi[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) xi[d] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + d];
-    small_rows(a, min(lane, a.small.U - 1), w, wr.aoff, sg, nent, cvq, jr);
+    small_rows(a.small, a.J + (int64_t)w * a.nslots * 3, a.F, wr.aoff, min(lane, a.small.U - 1), sg, nent, cvq, jr);
     // the record is kept or replaced by +0.0 through a bit mask, which uses
     // the loaded value on every lane (a select lets the load move under a branch)
     const long long keep = lane < wr.nt ? -1LL : 0LL;

@@ -241,6 +241,100 @@ __global__ void __launch_bounds__(kBlock) k_hill_shared_finalize_wg(SharedArgs a
     gather_forces(a.tabs, a.J + w * a.nslots * 3, (int32_t)w, s_coef, a.F);
 }
 
+// The same in one wavefront, for steps that gather forces through the
+// table in kernel-argument form: every load is requested before the first
+// wait (each lane's first chunk record -- lanes past the count re-read the
+// last one and drop it, nchunk >= 1 -- the CV values, the deposit's count
+// and step, and a table row per lane with its Jacobian rows and force; lanes
+// past U re-read row U - 1 and store nothing); the records are summed
+// lane-strided and combined by a butterfly (every lane ends with the same
+// bits); lane 0 writes the outputs and deposits, lane u < U adds atom u's
+// force.  No LDS, no barrier.
+template <int D>
+__global__ void __launch_bounds__(64) k_hill_shared_finalize_wave(SharedArgs a)
+{
+    const int64_t w = blockIdx.x, q = w;  // fallback mode: records per walker
+    const int lane = threadIdx.x;
+    if (a.fb && !a.fb[w]) return;  // uniform per workgroup
+    const int nch = a.nchunk;
+    double r0[1 + D];
+    {
+        const double *p = a.partial + ((int64_t)min(lane, nch - 1) * a.nq + q) * 4;
+#pragma unroll
+        for (int j = 0; j <= D; ++j) r0[j] = p[j];
+    }
+    double xi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xi[d] = a.xi[w * D + d];
+    const bool dep_cnt = a.deposit == 1 && a.stride > 0;
+    const int64_t dstep = dep_cnt ? *a.dstep : 0;
+    const int32_t cnt = a.deposit ? *a.count : 0;
+    SmallGather sg{0.f, 0.f, 0.f, nullptr};
+    int nent = 0;
+    int32_t cvq[kSmallPer];
+    float jr[kSmallPer][3];
+    small_rows(a.small, a.J + w * a.nslots * 3, a.F, a.tabs.atom_off[w], min(lane, a.small.U - 1), sg, nent, cvq, jr);
+    // the first record kept or replaced by +0.0 through a bit mask, which
+    // uses the loaded value on every lane (a select lets the load move
+    // under a branch)
+    const long long keep = lane < nch ? -1LL : 0LL;
+    double acc[1 + D];
+#pragma unroll
+    for (int j = 0; j <= D; ++j) acc[j] = 0.0 + __longlong_as_double(__double_as_longlong(r0[j]) & keep);
+    for (int ch = lane + 64; ch < nch; ch += 64) {  // the same order as one loop from ch = lane
+        const double *p = a.partial + ((int64_t)ch * a.nq + q) * 4;
+#pragma unroll
+        for (int j = 0; j <= D; ++j) acc[j] += p[j];
+    }
+#pragma unroll
+    for (int j = 0; j <= D; ++j)
+        for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, 64);
+    double dv[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) dv[d] = -acc[1 + d] * a.inv_sig2[d];
+    if (lane == 0) {
+        const double V = acc[0];
+        bool finite = isfinite(V);
+        if (a.V_ws) a.V_ws[w] = V;
+        if (a.V_out) a.V_out[w] = V;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            finite = finite && isfinite(dv[d]);
+            if (a.dV_ws) a.dV_ws[w * D + d] = dv[d];
+            if (a.dV_out) a.dV_out[w * D + d] = dv[d];
+            if (a.xi_out) a.xi_out[w * D + d] = xi[d];
+        }
+        if (!finite && a.flags) atomicOr(a.flags, kFlagNonFinite);
+        bool dep = a.deposit == 2;
+        if (dep_cnt) dep = (dstep - 1) % a.stride == 0;
+        if (dep) {  // as shared_finish: walker order at count + w, all or none
+            if ((int64_t)cnt + a.nq <= a.cap) {
+                const int64_t k = (int64_t)cnt + w;
+#pragma unroll
+                for (int d = 0; d < D; ++d) a.c[d][k] = (float)xi[d];
+                a.h[k] = (float)(a.inv_kdT > 0.0 ? a.height * exp(-V * a.inv_kdT) : a.height);
+            } else if (w == 0) {
+                atomicOr(a.flags, kFlagCapacity);
+            }
+        }
+    }
+    if (lane < a.small.U) {
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+        for (int qq = 0; qq < kSmallPer; ++qq) {
+            double cf = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) cf = cvq[qq] == d ? -dv[d] : cf;
+            fx += qq < nent ? cf * (double)jr[qq][0] : 0.0;
+            fy += qq < nent ? cf * (double)jr[qq][1] : 0.0;
+            fz += qq < nent ? cf * (double)jr[qq][2] : 0.0;
+        }
+        sg.dst[0] = sg.f0 + (float)fx;
+        sg.dst[a.F.sk] = sg.f1 + (float)fy;
+        sg.dst[2 * a.F.sk] = sg.f2 + (float)fz;
+    }
+}
+
 // Fallback sums of a surrogate step (the few walkers outside certified
 // cells): one workgroup per (flagged walker, chunk of kQmChunk hills), lanes
 // over hills with float4 loads all issued before use (the list is read from
@@ -329,6 +423,13 @@ __global__ void k_shared_count(SharedArgs a)
     if (dep && (int64_t)*a.count + a.nq <= a.cap) *a.count = (int32_t)(*a.count + a.nq);
 }
 
+// the one-wavefront finalize: forces through the kernel-argument table of
+// walkers (one query per walker, its records at query w)
+bool small_finalize(const SharedArgs &a)
+{
+    return a.do_forces && a.small.on && a.small.U > 0 && a.nchunk >= 1 && a.tabs.W == a.nq;
+}
+
 template <int D>
 hipError_t launch_shared_d(const SharedArgs &a, hipStream_t s)
 {
@@ -347,7 +448,10 @@ hipError_t launch_shared_d(const SharedArgs &a, hipStream_t s)
         else hipLaunchKernelGGL((k_hill_shared_qm<D, kPerMixed>), g, dim3(kBlock), 0, s, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_hill_shared_finalize_wg<D>), dim3((unsigned)a.nq), dim3(kBlock), 0, s, b);
+        if (small_finalize(b))
+            hipLaunchKernelGGL((k_hill_shared_finalize_wave<D>), dim3((unsigned)a.nq), dim3(64), 0, s, b);
+        else
+            hipLaunchKernelGGL((k_hill_shared_finalize_wg<D>), dim3((unsigned)a.nq), dim3(kBlock), 0, s, b);
         return hipGetLastError();
     }
     // queries per lane: 1 for small query sets (more workgroups), 4 for many
@@ -372,7 +476,9 @@ hipError_t launch_shared_d(const SharedArgs &a, hipStream_t s)
 #undef SX_SHARED_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (a.nchunk >= 32)
+    if (a.nchunk >= 32 && small_finalize(a))
+        hipLaunchKernelGGL((k_hill_shared_finalize_wave<D>), dim3((unsigned)a.nq), dim3(64), 0, s, a);
+    else if (a.nchunk >= 32)
         hipLaunchKernelGGL((k_hill_shared_finalize_wg<D>), dim3((unsigned)a.nq), dim3(kBlock), 0, s, a);
     else
         hipLaunchKernelGGL((k_hill_shared_finalize<D>), dim3((unsigned)((a.nq + kBlock - 1) / kBlock)), dim3(kBlock),

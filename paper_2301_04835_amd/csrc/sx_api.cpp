@@ -733,6 +733,7 @@ void set_forces(sx_ctx *c, SharedArgs &a, const float *J, float *forces, int32_t
     a.J = J;
     a.tabs = tabs_of(c);
     a.F = force_view(c, forces, layout);
+    a.small = p.small;
 }
 
 MlpArgs mlp_args(sx_ctx *c)

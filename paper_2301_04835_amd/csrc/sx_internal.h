@@ -252,8 +252,8 @@ struct SharedArgs {
     double inv_sig2[kMaxBiasDim];
     const double *xi;  // nq x D
     int64_t nq;        // queries (walkers, or evaluation points)
-    // fallback mode (fb != null): only walkers w with fb[w] = 1 are queries,
-    // in walker order; query q is the q-th of them
+    // fallback mode (fb != null): nq = W and only walkers w with fb[w] = 1
+    // are summed; walker w's records sit at query index w
     const uint8_t *fb;
     double *partial;   // nchunk x nq x 4
     int32_t chunk, nchunk;
@@ -268,6 +268,7 @@ struct SharedArgs {
     const float *J;
     WalkerTabs tabs;
     ForceView F;
+    SmallTabs small;  // the gather table in kernel-argument form (on = 0: the walker tables)
 };
 
 // What a surrogate step adds to the network's forward pass: per-walker
