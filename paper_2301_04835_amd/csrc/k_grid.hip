@@ -7,7 +7,9 @@
 //
 //   k_grid_step     one workgroup per walker: the read-back, the outputs, the
 //                   well-tempered deposit into the hill list (height from
-//                   the read-back V) and the force gather.
+//                   the read-back V) and the force gather; k_grid_step_wave
+//                   is the same in one wavefront when forces go through the
+//                   table in kernel-argument form.
 //   k_grid_add      one workgroup per grid: the hills the step appended
 //                   (FP64, list order) added to every node, then the list's
 //                   count advanced; the workgroup of grid 0 also advances
@@ -25,13 +27,11 @@ namespace {
 
 constexpr int kAddBlock = 1024;
 
-// The cell of xi and the interpolated (V, dV/dxi) of grid l; false (and
-// zeros) outside the range of a non-periodic CV.  Corner c takes node i1 of
-// CV d when bit D - 1 - d of c is set (first CV the most significant).
-__device__ bool grid_read(const GridArgs &g, int32_t l, const double *xi, double &V, double (&G)[kMaxBiasDim])
+// The cell of xi: lower and upper node per CV and the fractions t; false
+// outside the range of a non-periodic CV (its nodes are then set to 0).
+__device__ __forceinline__ bool grid_cell(const GridArgs &g, const double *xi, int32_t (&i0)[kMaxBiasDim],
+                                          int32_t (&i1)[kMaxBiasDim], double (&t)[kMaxBiasDim])
 {
-    int32_t i0[kMaxBiasDim], i1[kMaxBiasDim];
-    double t[kMaxBiasDim];
     bool inside = true;
     for (int d = 0; d < g.D; ++d) {
         const double u = (xi[d] - g.lo[d]) / g.delta[d];
@@ -57,19 +57,41 @@ __device__ bool grid_read(const GridArgs &g, int32_t l, const double *xi, double
             i1[d] = k + 1;
         }
     }
+    return inside;
+}
+
+// Corner c of the cell: its node index and multilinear weight.  Corner c
+// takes node i1 of CV d when bit D - 1 - d of c is set (first CV the most
+// significant).
+__device__ __forceinline__ int64_t grid_corner(const GridArgs &g, int c, const int32_t (&i0)[kMaxBiasDim],
+                                               const int32_t (&i1)[kMaxBiasDim], const double (&t)[kMaxBiasDim],
+                                               double &wgt)
+{
+    int64_t idx = 0;
+    wgt = 1.0;
+    for (int d = 0; d < g.D; ++d) {
+        const bool hi = (c >> (g.D - 1 - d)) & 1;
+        idx = idx * g.n[d] + (hi ? i1[d] : i0[d]);
+        wgt *= hi ? t[d] : 1.0 - t[d];
+    }
+    return idx;
+}
+
+// The interpolated (V, dV/dxi) of grid l at xi, corners summed in order;
+// false (and zeros) outside the range of a non-periodic CV.
+__device__ bool grid_read(const GridArgs &g, int32_t l, const double *xi, double &V, double (&G)[kMaxBiasDim])
+{
+    int32_t i0[kMaxBiasDim], i1[kMaxBiasDim];
+    double t[kMaxBiasDim];
+    const bool inside = grid_cell(g, xi, i0, i1, t);
     V = 0.0;
     for (int d = 0; d < kMaxBiasDim; ++d) G[d] = 0.0;
     if (!inside) return false;
     const double *Vg = g.V + (int64_t)l * g.N;
     const double *Gg = g.G + (int64_t)l * g.D * g.N;
     for (int c = 0; c < (1 << g.D); ++c) {
-        int64_t idx = 0;
-        double wgt = 1.0;
-        for (int d = 0; d < g.D; ++d) {
-            const bool hi = (c >> (g.D - 1 - d)) & 1;
-            idx = idx * g.n[d] + (hi ? i1[d] : i0[d]);
-            wgt *= hi ? t[d] : 1.0 - t[d];
-        }
+        double wgt;
+        const int64_t idx = grid_corner(g, c, i0, i1, t, wgt);
         V += wgt * Vg[idx];
         for (int d = 0; d < g.D; ++d) G[d] += wgt * Gg[(int64_t)d * g.N + idx];
     }
@@ -122,6 +144,95 @@ __global__ void __launch_bounds__(kBlock) k_grid_step(GridArgs g)
     }
     __syncthreads();
     if (g.do_forces) gather_forces(g.tabs, g.J + (int64_t)w * g.nslots * 3, w, s_coef, g.F);
+}
+
+// The same step in one wavefront, for steps that gather forces through the
+// table in kernel-argument form.  Every lane finds the cell (the same
+// values), lane c < 2^D loads corner c's V and dV/dxi, and every lane sums
+// the corner terms in corner order through shuffles (the serial order and
+// bits of grid_read); xi, the list's count and record and each lane's table
+// row with its Jacobian rows and force are requested before any wait (lanes
+// past 2^D or U re-read corner 0 or row U - 1 and drop it).  Lane 0 writes
+// the outputs and deposits, lane u < U adds atom u's force.
+__global__ void __launch_bounds__(64) k_grid_step_wave(GridArgs g)
+{
+    const int32_t w = blockIdx.x;
+    const int32_t l = g.shared ? 0 : w;
+    const int lane = threadIdx.x;
+    double xi[kMaxBiasDim] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < g.D; ++d) xi[d] = g.xi[(int64_t)w * g.D + d];
+    const bool dep_cnt = g.deposit == 1 && g.stride > 0;
+    const int64_t dstep = dep_cnt && g.step < 0 ? *g.dstep : 0;
+    const int32_t cnt = g.deposit ? g.count[l] : 0;
+    const WalkerRec wr = g.wrec[l];
+    SmallGather sg{0.f, 0.f, 0.f, nullptr};
+    int nent = 0;
+    int32_t cvq[kSmallPer];
+    float jr[kSmallPer][3];
+    small_rows(g.small, g.J + (int64_t)w * g.nslots * 3, g.F, g.tabs.atom_off[w], min(lane, g.small.U - 1), sg, nent,
+               cvq, jr);
+    int32_t i0[kMaxBiasDim], i1[kMaxBiasDim];
+    double t[kMaxBiasDim];
+    const bool inside = grid_cell(g, xi, i0, i1, t);
+    const int nc = 1 << g.D;
+    double wgt;
+    const int64_t idx = grid_corner(g, lane < nc ? lane : 0, i0, i1, t, wgt);
+    const double *Vg = g.V + (int64_t)l * g.N;
+    const double *Gg = g.G + (int64_t)l * g.D * g.N;
+    const double tv = wgt * Vg[idx];
+    double tg[kMaxBiasDim] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < g.D; ++d) tg[d] = wgt * Gg[(int64_t)d * g.N + idx];
+    double V = 0.0, G[kMaxBiasDim] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < nc; ++c) {
+        V += __shfl(tv, c, 64);
+        for (int d = 0; d < kMaxBiasDim; ++d) G[d] += __shfl(tg[d], c, 64);
+    }
+    if (!inside) {
+        V = 0.0;
+        for (int d = 0; d < kMaxBiasDim; ++d) G[d] = 0.0;
+    }
+    if (lane == 0) {
+        bool finite = isfinite(V);
+        g.V_ws[w] = V;
+        if (g.V_out) g.V_out[w] = V;
+        for (int d = 0; d < g.D; ++d) {
+            finite = finite && isfinite(G[d]);
+            g.dV_ws[(int64_t)w * g.D + d] = G[d];
+            if (g.dV_out) g.dV_out[(int64_t)w * g.D + d] = G[d];
+            if (g.xi_out) g.xi_out[(int64_t)w * g.D + d] = xi[d];
+        }
+        if (!finite) atomicOr(g.flags, kFlagNonFinite);
+        const int64_t next_step = g.step >= 0 ? g.step + 1 : dstep + 1;
+        bool dep = g.deposit == 2;
+        if (dep_cnt) dep = (next_step - 1) % g.stride == 0;
+        if (dep && (inside || g.shared)) {  // as k_grid_step
+            const double h = !inside ? 0.0 : g.inv_kdT > 0.0 ? g.height * exp(-V * g.inv_kdT) : g.height;
+            const int64_t hb = (int64_t)wr.hb4 * 4;
+            const int32_t nnew = g.shared ? g.tabs.W : 1;
+            if ((int64_t)cnt + nnew <= wr.cap) {
+                const int64_t k = hb + cnt + (g.shared ? w : 0);
+                for (int d = 0; d < g.D; ++d) g.c[d][k] = (float)xi[d];
+                g.h[k] = (float)h;
+                if (!g.shared || w == 0) g.pend[l] = nnew;
+            } else {
+                atomicOr(g.flags, kFlagCapacity);
+            }
+        }
+    }
+    if (lane < g.small.U) {
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSmallPer; ++q) {
+            double cf = 0.0;
+            for (int d = 0; d < g.D; ++d) cf = cvq[q] == d ? -G[d] : cf;
+            fx += q < nent ? cf * (double)jr[q][0] : 0.0;
+            fy += q < nent ? cf * (double)jr[q][1] : 0.0;
+            fz += q < nent ? cf * (double)jr[q][2] : 0.0;
+        }
+        sg.dst[0] = sg.f0 + (float)fx;
+        sg.dst[g.F.sk] = sg.f1 + (float)fy;
+        sg.dst[2 * g.F.sk] = sg.f2 + (float)fz;
+    }
 }
 
 // hills [k0, k1) of list l onto nodes [first, N) of its grid, node stride
@@ -215,7 +326,10 @@ hipError_t launch_scale_f64(double *x, int64_t n, double a, hipStream_t s)
 hipError_t launch_grid_step(const GridArgs &g, hipStream_t s)
 {
     if (g.tabs.W < 1 || g.L < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_grid_step, dim3(g.tabs.W), dim3(kBlock), 0, s, g);
+    if (g.do_forces && g.small.on && g.small.U > 0)
+        hipLaunchKernelGGL(k_grid_step_wave, dim3(g.tabs.W), dim3(64), 0, s, g);
+    else
+        hipLaunchKernelGGL(k_grid_step, dim3(g.tabs.W), dim3(kBlock), 0, s, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_grid_add, dim3(g.L), dim3(kAddBlock), 0, s, g);

@@ -874,6 +874,7 @@ GridArgs grid_args(sx_ctx *c, const double *xi)
     g.nslots = p.nslots;
     g.J = at<float>(c->ws, p.w_J);
     g.tabs = tabs_of(c);
+    g.small = p.small;
     return g;
 }
 

@@ -218,6 +218,7 @@ struct GridArgs {
     const float *J;
     WalkerTabs tabs;
     ForceView F;
+    SmallTabs small;  // the gather table in kernel-argument form (on = 0: the walker tables)
 };
 
 // Harmonic bias k/2 (xi - xi0_w)^2 per walker (umbrella windows) and the
