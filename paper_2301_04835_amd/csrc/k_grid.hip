@@ -159,8 +159,11 @@ __global__ void __launch_bounds__(64) k_grid_step_wave(GridArgs g)
     const int32_t w = blockIdx.x;
     const int32_t l = g.shared ? 0 : w;
     const int lane = threadIdx.x;
-    double xi[kMaxBiasDim] = {0.0, 0.0, 0.0};
-    for (int d = 0; d < g.D; ++d) xi[d] = g.xi[(int64_t)w * g.D + d];
+    // xi over the largest CV count with the index clamped to the last CV (in
+    // bounds, the extra entries unused), so the loads are issued together
+    double xi[kMaxBiasDim];
+#pragma unroll
+    for (int d = 0; d < kMaxBiasDim; ++d) xi[d] = g.xi[(int64_t)w * g.D + min(d, g.D - 1)];
     const bool dep_cnt = g.deposit == 1 && g.stride > 0;
     const int64_t dstep = dep_cnt && g.step < 0 ? *g.dstep : 0;
     const int32_t cnt = g.deposit ? g.count[l] : 0;
@@ -180,8 +183,9 @@ __global__ void __launch_bounds__(64) k_grid_step_wave(GridArgs g)
     const double *Vg = g.V + (int64_t)l * g.N;
     const double *Gg = g.G + (int64_t)l * g.D * g.N;
     const double tv = wgt * Vg[idx];
-    double tg[kMaxBiasDim] = {0.0, 0.0, 0.0};
-    for (int d = 0; d < g.D; ++d) tg[d] = wgt * Gg[(int64_t)d * g.N + idx];
+    double tg[kMaxBiasDim];
+#pragma unroll
+    for (int d = 0; d < kMaxBiasDim; ++d) tg[d] = d < g.D ? wgt * Gg[(int64_t)min(d, g.D - 1) * g.N + idx] : 0.0;
     double V = 0.0, G[kMaxBiasDim] = {0.0, 0.0, 0.0};
     for (int c = 0; c < nc; ++c) {
         V += __shfl(tv, c, 64);
