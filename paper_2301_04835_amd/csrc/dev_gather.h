@@ -60,6 +60,64 @@ __device__ __forceinline__ void small_rows(const SmallTabs &st, const float *Jw,
     }
 }
 
+// gather_atom in two halves, for kernels that know the coefficients only
+// late: atom_rows requests touched atom u's first kAtomRows entries (their
+// CVs and Jacobian rows) and its current force before the coefficients
+// exist; atom_add then sums in the same order and arithmetic as gather_atom
+// (entries past kAtomRows are read there, as gather_atom reads them).
+constexpr int kAtomRows = 4;
+struct AtomRows {
+    int32_t q0, q1;
+    int32_t cv[kAtomRows];
+    float j[kAtomRows][3];
+    float f0, f1, f2;
+    float *dst;
+};
+
+__device__ __forceinline__ void atom_rows(const WalkerTabs &t, const float *Jw, int32_t w, const ForceView &F, int u,
+                                          AtomRows &r)
+{
+    r.q0 = t.inv_ptr[u];
+    r.q1 = t.inv_ptr[u + 1];  // > q0: a touched atom has a slot
+#pragma unroll
+    for (int k = 0; k < kAtomRows; ++k) {
+        const int32_t s = t.inv_slot[min(r.q0 + k, r.q1 - 1)];
+        r.cv[k] = t.slot_cv[s];
+        r.j[k][0] = Jw[(int64_t)s * 3];
+        r.j[k][1] = Jw[(int64_t)s * 3 + 1];
+        r.j[k][2] = Jw[(int64_t)s * 3 + 2];
+    }
+    r.dst = F.ptr + (t.atom_off[w] + t.touched[u]) * F.sa;
+    r.f0 = r.dst[0];
+    r.f1 = r.dst[F.sk];
+    r.f2 = r.dst[2 * F.sk];
+}
+
+__device__ __forceinline__ void atom_add(const WalkerTabs &t, const float *Jw, const double *coef, const ForceView &F,
+                                         const AtomRows &r)
+{
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+    for (int k = 0; k < kAtomRows; ++k) {
+        const bool use = r.q0 + k < r.q1;
+        const double cf = coef[r.cv[k]];
+        fx += use ? cf * (double)r.j[k][0] : 0.0;
+        fy += use ? cf * (double)r.j[k][1] : 0.0;
+        fz += use ? cf * (double)r.j[k][2] : 0.0;
+    }
+    for (int q = r.q0 + kAtomRows; q < r.q1; ++q) {
+        const int32_t s = t.inv_slot[q];
+        const double cf = coef[t.slot_cv[s]];
+        const float *js = Jw + (int64_t)s * 3;
+        fx += cf * (double)js[0];
+        fy += cf * (double)js[1];
+        fz += cf * (double)js[2];
+    }
+    r.dst[0] = r.f0 + (float)fx;
+    r.dst[F.sk] = r.f1 + (float)fy;
+    r.dst[2 * F.sk] = r.f2 + (float)fz;
+}
+
 // the whole walker, lanes of the workgroup striding over its touched atoms
 __device__ __forceinline__ void gather_forces(const WalkerTabs &t, const float *Jw, int32_t w, const double *coef,
                                               const ForceView &F)

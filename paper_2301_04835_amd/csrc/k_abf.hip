@@ -63,11 +63,15 @@ __device__ __forceinline__ void abf_atom_terms(const AbfArgs &a, int32_t w, int 
 // are in flight while the sums are formed.
 __device__ __forceinline__ AbfPre abf_prefetch(const AbfArgs &a, int32_t w)
 {
+    // loops over the largest CV count with run-time guards: every array
+    // index is a compile-time constant, so nothing lives in scratch memory
     AbfPre r{};
     const int D = a.D;
     r.k = 0;
     r.inr = true;
-    for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int d = 0; d < MD; ++d) {
+        if (d >= D) continue;
         r.xi[d] = a.xi[(int64_t)w * D + d];
         int64_t i = (int64_t)floor((r.xi[d] - a.lo[d]) / a.delta[d]);
         if (a.periodic[d]) {
@@ -80,13 +84,18 @@ __device__ __forceinline__ AbfPre abf_prefetch(const AbfArgs &a, int32_t w)
     }
     if (r.inr) {
         r.cnt = a.N[(int64_t)w * a.nbins_total + r.k];
-        for (int d = 0; d < D; ++d) r.F[d] = a.Fsum[((int64_t)w * a.nbins_total + r.k) * D + d];
+#pragma unroll
+        for (int d = 0; d < MD; ++d)
+            if (d < D) r.F[d] = a.Fsum[((int64_t)w * a.nbins_total + r.k) * D + d];
     }
-    if (a.b_ext)
-        for (int d = 0; d < D; ++d) r.bext[d] = a.b_ext[(int64_t)w * D + d];
+#pragma unroll
+    for (int d = 0; d < MD; ++d)
+        if (d < D && a.b_ext) r.bext[d] = a.b_ext[(int64_t)w * D + d];
     if (a.estimator == 1) {
         r.has = a.has_prev[w];
-        for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int d = 0; d < MD; ++d) {
+            if (d >= D) continue;
             r.bprev[d] = a.b_prev[(int64_t)w * D + d];
             r.wpprev[d] = a.Wp_prev[(int64_t)w * D + d];
         }
@@ -106,46 +115,77 @@ struct AbfOut {
 
 __device__ AbfOut abf_solve(const AbfArgs &a, const double (&acc)[NA], const AbfPre &pre)
 {
+    // every loop runs over MD with a run-time guard (d < D), so that all
+    // array indices are compile-time constants (registers, no scratch); the
+    // operations on rows and columns below D are those of plain Gaussian
+    // elimination with partial pivoting on the D x D system, in its order
     const int D = a.D;
     AbfOut r{};
-    // solve G x = u by Gaussian elimination with partial pivoting
-    double G[MD][MD + 1];
-    for (int d = 0; d < D; ++d) {
-        for (int e = 0; e < D; ++e) G[d][e] = acc[d * MD + e];
-        G[d][D] = acc[MD * MD + d];
+    double G[MD][MD], rhs[MD];
+#pragma unroll
+    for (int d = 0; d < MD; ++d) {
+#pragma unroll
+        for (int e = 0; e < MD; ++e) G[d][e] = (d < D && e < D) ? acc[d * MD + e] : 0.0;
+        rhs[d] = d < D ? acc[MD * MD + d] : 0.0;
     }
-    for (int col = 0; col < D; ++col) {
+#pragma unroll
+    for (int col = 0; col < MD; ++col) {
+        if (col >= D) continue;
+        // pivot: the first row r >= col with the largest |G[r][col]|
         int piv = col;
-        for (int q = col + 1; q < D; ++q)
-            if (fabs(G[q][col]) > fabs(G[piv][col])) piv = q;
-        if (piv != col)
-            for (int e = 0; e <= D; ++e) {
-                double tmp = G[col][e];
-                G[col][e] = G[piv][e];
-                G[piv][e] = tmp;
+        double best = fabs(G[col][col]);
+#pragma unroll
+        for (int q = col + 1; q < MD; ++q)
+            if (q < D && fabs(G[q][col]) > best) {
+                best = fabs(G[q][col]);
+                piv = q;
             }
-        for (int q = col + 1; q < D; ++q) {
+#pragma unroll
+        for (int q = col + 1; q < MD; ++q)
+            if (q == piv) {
+#pragma unroll
+                for (int e = 0; e < MD; ++e) {
+                    const double tmp = G[col][e];
+                    G[col][e] = G[q][e];
+                    G[q][e] = tmp;
+                }
+                const double tmp = rhs[col];
+                rhs[col] = rhs[q];
+                rhs[q] = tmp;
+            }
+#pragma unroll
+        for (int q = col + 1; q < MD; ++q) {
+            if (q >= D) continue;
             const double fct = G[q][col] / G[col][col];
-            for (int e = col; e <= D; ++e) G[q][e] -= fct * G[col][e];
+#pragma unroll
+            for (int e = col; e < MD; ++e)
+                if (e < D) G[q][e] -= fct * G[col][e];
+            rhs[q] -= fct * rhs[col];
         }
     }
-    for (int d = D - 1; d >= 0; --d) {
-        double sd = G[d][D];
-        for (int e = d + 1; e < D; ++e) sd -= G[d][e] * r.x[e];
+#pragma unroll
+    for (int d = MD - 1; d >= 0; --d) {
+        if (d >= D) continue;
+        double sd = rhs[d];
+#pragma unroll
+        for (int e = d + 1; e < MD; ++e)
+            if (e < D) sd -= G[d][e] * r.x[e];
         r.x[d] = sd / G[d][d];
     }
     r.sample = true;
-    if (a.estimator == 1) {
-        r.sample = pre.has != 0;
-        for (int d = 0; d < D; ++d) r.theta[d] = pre.bprev[d] - (r.x[d] - pre.wpprev[d]) / a.dt;
-    } else {
-        for (int d = 0; d < D; ++d) r.theta[d] = -r.x[d];
-    }
+    if (a.estimator == 1) r.sample = pre.has != 0;
     r.finite = true;
-    for (int d = 0; d < D; ++d) r.finite = r.finite && isfinite(r.theta[d]) && isfinite(r.x[d]);
+#pragma unroll
+    for (int d = 0; d < MD; ++d) {
+        if (d >= D) continue;
+        r.theta[d] = a.estimator == 1 ? pre.bprev[d] - (r.x[d] - pre.wpprev[d]) / a.dt : -r.x[d];
+        r.finite = r.finite && isfinite(r.theta[d]) && isfinite(r.x[d]);
+    }
     if (pre.inr && r.finite) {
         const double den = (double)max((int64_t)pre.cnt, (int64_t)a.n_threshold);
-        for (int d = 0; d < D; ++d) r.b[d] = a.b_ext ? pre.bext[d] : den > 0.0 ? pre.F[d] / den : 0.0;
+#pragma unroll
+        for (int d = 0; d < MD; ++d)
+            if (d < D) r.b[d] = a.b_ext ? pre.bext[d] : den > 0.0 ? pre.F[d] / den : 0.0;
     }
     return r;
 }
@@ -159,19 +199,21 @@ __device__ void abf_commit(const AbfArgs &a, int32_t w, const AbfPre &pre, const
     if (pre.inr && r.finite && r.sample) {
         a.N[(int64_t)w * a.nbins_total + pre.k] = pre.cnt + 1u;
         double *Fk = a.Fsum + ((int64_t)w * a.nbins_total + pre.k) * D;
-        for (int d = 0; d < D; ++d) Fk[d] = pre.F[d] + r.theta[d];
+#pragma unroll
+        for (int d = 0; d < MD; ++d)
+            if (d < D) Fk[d] = pre.F[d] + r.theta[d];
     }
-    if (a.estimator == 1) {  // for the next step: this step's W p and bias
-        for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int d = 0; d < MD; ++d) {
+        if (d >= D) continue;
+        if (a.estimator == 1) {  // for the next step: this step's W p and bias
             a.Wp_prev[(int64_t)w * D + d] = r.x[d];
             a.b_prev[(int64_t)w * D + d] = r.b[d];
         }
-        a.has_prev[w] = 1;
-    }
-    for (int d = 0; d < D; ++d) {
         if (a.dV_out) a.dV_out[(int64_t)w * D + d] = -r.b[d];
         if (a.xi_out) a.xi_out[(int64_t)w * D + d] = pre.xi[d];
     }
+    if (a.estimator == 1) a.has_prev[w] = 1;
     if (a.V_out) a.V_out[w] = 0.0;
     if (w == 0) *a.dstep = a.step >= 0 ? a.step + 1 : pre.dstep + 1;
 }
@@ -190,7 +232,9 @@ __global__ void __launch_bounds__(kBlock) k_abf(AbfArgs a)
     if (threadIdx.x == 0) {
         const AbfOut r = abf_solve(a, acc, pre);
         abf_commit(a, w, pre, r);
-        for (int d = 0; d < a.D; ++d) s_coef[d] = r.b[d];
+#pragma unroll
+        for (int d = 0; d < MD; ++d)
+            if (d < a.D) s_coef[d] = r.b[d];
     }
     __syncthreads();
     gather_forces(a.tabs, a.J + (int64_t)w * a.nslots * 3, w, s_coef, a.F);
@@ -227,6 +271,11 @@ __global__ void __launch_bounds__(kBlock) k_abf_finish(AbfArgs a)
 {
     __shared__ double s_coef[kMaxCv];
     const int32_t w = blockIdx.y;
+    // this lane's atom: its rows and force requested before the solve
+    const int u = blockIdx.x * kBlock + threadIdx.x;
+    const float *Jw = a.J + (int64_t)w * a.nslots * 3;
+    AtomRows rows;
+    if (u < a.tabs.U) atom_rows(a.tabs, Jw, w, a.F, u, rows);
     if (threadIdx.x < 64) {  // the first wavefront
         const AbfPre pre = a.pre[w];
         double acc[NA];
@@ -243,12 +292,13 @@ __global__ void __launch_bounds__(kBlock) k_abf_finish(AbfArgs a)
         if (threadIdx.x == 0) {
             const AbfOut r = abf_solve(a, acc, pre);
             if (blockIdx.x == 0) abf_commit(a, w, pre, r);
-            for (int d = 0; d < a.D; ++d) s_coef[d] = r.b[d];
+#pragma unroll
+            for (int d = 0; d < MD; ++d)
+                if (d < a.D) s_coef[d] = r.b[d];
         }
     }
     __syncthreads();
-    const int u = blockIdx.x * kBlock + threadIdx.x;
-    if (u < a.tabs.U) gather_atom(a.tabs, a.J + (int64_t)w * a.nslots * 3, w, s_coef, a.F, u);
+    if (u < a.tabs.U) atom_add(a.tabs, Jw, s_coef, a.F, rows);
 }
 
 }  // namespace

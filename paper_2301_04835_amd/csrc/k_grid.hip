@@ -33,7 +33,9 @@ __device__ __forceinline__ bool grid_cell(const GridArgs &g, const double *xi, i
                                           int32_t (&i1)[kMaxBiasDim], double (&t)[kMaxBiasDim])
 {
     bool inside = true;
-    for (int d = 0; d < g.D; ++d) {
+#pragma unroll
+    for (int d = 0; d < kMaxBiasDim; ++d) {  // compile-time indices (registers)
+        if (d >= g.D) continue;
         const double u = (xi[d] - g.lo[d]) / g.delta[d];
         double fl = floor(u);
         t[d] = u - fl;
@@ -69,9 +71,12 @@ __device__ __forceinline__ int64_t grid_corner(const GridArgs &g, int c, const i
 {
     int64_t idx = 0;
     wgt = 1.0;
-    for (int d = 0; d < g.D; ++d) {
+#pragma unroll
+    for (int d = 0; d < kMaxBiasDim; ++d) {
+        if (d >= g.D) continue;
         const bool hi = (c >> (g.D - 1 - d)) & 1;
-        idx = idx * g.n[d] + (hi ? i1[d] : i0[d]);
+        const int32_t n0 = i0[d], n1 = i1[d];  // select values, not addresses (keeps the arrays in registers)
+        idx = idx * g.n[d] + (hi ? n1 : n0);
         wgt *= hi ? t[d] : 1.0 - t[d];
     }
     return idx;
@@ -93,7 +98,9 @@ __device__ bool grid_read(const GridArgs &g, int32_t l, const double *xi, double
         double wgt;
         const int64_t idx = grid_corner(g, c, i0, i1, t, wgt);
         V += wgt * Vg[idx];
-        for (int d = 0; d < g.D; ++d) G[d] += wgt * Gg[(int64_t)d * g.N + idx];
+#pragma unroll
+        for (int d = 0; d < kMaxBiasDim; ++d)
+            if (d < g.D) G[d] += wgt * Gg[(int64_t)d * g.N + idx];
     }
     return true;
 }
@@ -199,7 +206,9 @@ __global__ void __launch_bounds__(64) k_grid_step_wave(GridArgs g)
         bool finite = isfinite(V);
         g.V_ws[w] = V;
         if (g.V_out) g.V_out[w] = V;
-        for (int d = 0; d < g.D; ++d) {
+#pragma unroll
+        for (int d = 0; d < kMaxBiasDim; ++d) {
+            if (d >= g.D) continue;
             finite = finite && isfinite(G[d]);
             g.dV_ws[(int64_t)w * g.D + d] = G[d];
             if (g.dV_out) g.dV_out[(int64_t)w * g.D + d] = G[d];
@@ -215,7 +224,9 @@ __global__ void __launch_bounds__(64) k_grid_step_wave(GridArgs g)
             const int32_t nnew = g.shared ? g.tabs.W : 1;
             if ((int64_t)cnt + nnew <= wr.cap) {
                 const int64_t k = hb + cnt + (g.shared ? w : 0);
-                for (int d = 0; d < g.D; ++d) g.c[d][k] = (float)xi[d];
+#pragma unroll
+                for (int d = 0; d < kMaxBiasDim; ++d)
+                    if (d < g.D) g.c[d][k] = (float)xi[d];
                 g.h[k] = (float)h;
                 if (!g.shared || w == 0) g.pend[l] = nnew;
             } else {
@@ -228,7 +239,8 @@ __global__ void __launch_bounds__(64) k_grid_step_wave(GridArgs g)
 #pragma unroll
         for (int q = 0; q < kSmallPer; ++q) {
             double cf = 0.0;
-            for (int d = 0; d < g.D; ++d) cf = cvq[q] == d ? -G[d] : cf;
+#pragma unroll
+            for (int d = 0; d < kMaxBiasDim; ++d) cf = (d < g.D && cvq[q] == d) ? -G[d] : cf;
             fx += q < nent ? cf * (double)jr[q][0] : 0.0;
             fy += q < nent ? cf * (double)jr[q][1] : 0.0;
             fz += q < nent ? cf * (double)jr[q][2] : 0.0;
