@@ -1083,8 +1083,9 @@ sx_status sx_create(sx_ctx **out, int device, void *stream)
 void sx_destroy(sx_ctx *c)
 {
     if (!c) return;
-    if (c->gexec) hipGraphExecDestroy(c->gexec);
-    if (c->graph) hipGraphDestroy(c->graph);
+    // teardown: a failure to release here cannot be acted on
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     delete c;
 }
 
@@ -2373,12 +2374,13 @@ sx_status sx_graph_capture(sx_ctx *ctx, int32_t n_steps, const void *pos, int32_
     if (sx_status s = require_bound(ctx)) return s;
     SX_GUARD_BEGIN
     if (n_steps < 1) return fail(ctx, SX_EINVAL, "n_steps must be >= 1");
+    // releasing the previous graph: a failure here cannot be acted on
     if (ctx->gexec) {
-        hipGraphExecDestroy(ctx->gexec);
+        (void)hipGraphExecDestroy(ctx->gexec);
         ctx->gexec = nullptr;
     }
     if (ctx->graph) {
-        hipGraphDestroy(ctx->graph);
+        (void)hipGraphDestroy(ctx->graph);
         ctx->graph = nullptr;
     }
     hipStream_t cap;
@@ -2397,14 +2399,14 @@ sx_status sx_graph_capture(sx_ctx *ctx, int32_t n_steps, const void *pos, int32_
             ctx->graph = g;
             e2 = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
         } else if (g) {
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);  // the capture already failed; that error is reported
         }
         if (st == SX_OK && e2 != hipSuccess) st = hip_fail(ctx, e2, "graph capture");
     } else {
         st = hip_fail(ctx, e, "begin capture");
     }
     ctx->stream = saved;
-    hipStreamDestroy(cap);
+    (void)hipStreamDestroy(cap);
     return st;
     SX_GUARD_END
 }
@@ -2422,7 +2424,7 @@ sx_status sx_graph_launch(sx_ctx *ctx)
 static void drop_graph(sx_ctx *ctx)
 {
     if (ctx->gexec) {
-        hipGraphExecDestroy(ctx->gexec);
+        (void)hipGraphExecDestroy(ctx->gexec);
         ctx->gexec = nullptr;
     }
 }
@@ -2504,22 +2506,20 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
             a.deposit = 0;
             a.count_step = 0;
             a.do_forces = 0;
-            for (int r = 0; r < 3; ++r) launch_hill_private(a, p.cs, pv, g, ctx->stream);
+            hipError_t e = hipSuccess;
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_hill_private(a, p.cs, pv, g, ctx->stream);
             float ms = 1e30f;
-            for (int round = 0; round < 3 && st == SX_OK; ++round) {  // best of three rounds
-                hipEventRecord(e0, ctx->stream);
+            for (int round = 0; round < 3 && e == hipSuccess; ++round) {  // best of three rounds
+                e = hipEventRecord(e0, ctx->stream);
                 const int reps = 20;
-                for (int r = 0; r < reps; ++r) launch_hill_private(a, p.cs, pv, g, ctx->stream);
-                hipEventRecord(e1, ctx->stream);
-                hipError_t e = hipEventSynchronize(e1);
-                if (e != hipSuccess) {
-                    st = hip_fail(ctx, e, "autotune timing");
-                    break;
-                }
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_hill_private(a, p.cs, pv, g, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float m = 0;
-                hipEventElapsedTime(&m, e0, e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
                 ms = std::min(ms, m);
             }
+            if (e != hipSuccess) st = hip_fail(ctx, e, "autotune timing");
             // a persistent grid must win by 2% over one workgroup per tile
             const float handicap = g ? 1.02f : 1.0f;
             if (st == SX_OK && ms * handicap < best) {
@@ -2530,8 +2530,8 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
         }
         if (st != SX_OK) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != SX_OK) return st;
     if (sx_status s = sx_set_tuning(ctx, bt, bg)) return s;
     if (cache_path) {
@@ -2575,7 +2575,7 @@ sx_status sx_time_cell(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layo
     if (err == hipSuccess) err = hipEventSynchronize(e[3]);
     float t[3] = {0, 0, 0};
     for (int k = 0; k < 3 && err == hipSuccess; ++k) err = hipEventElapsedTime(&t[k], e[k], e[k + 1]);
-    for (auto &x : e) hipEventDestroy(x);
+    for (auto &x : e) (void)hipEventDestroy(x);
     if (err != hipSuccess) return hip_fail(ctx, err, "cell timing");
     *ms_sort = t[0] / reps;
     *ms_pairs = t[1] / reps;
@@ -2619,7 +2619,7 @@ sx_status sx_time_hill(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layo
     float m1 = 0, m2 = 0;
     if (err == hipSuccess) err = hipEventElapsedTime(&m1, e[0], e[1]);
     if (err == hipSuccess) err = hipEventElapsedTime(&m2, e[1], e[2]);
-    for (auto &ev : e) hipEventDestroy(ev);
+    for (auto &ev : e) (void)hipEventDestroy(ev);
     if (err != hipSuccess) return hip_fail(ctx, err, "hill kernel timing");
     *ms_tiles = m1 / reps;
     *ms_finalize = m2 / reps;
