@@ -27,12 +27,20 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+def _warnings(text):
+    """Compiler warnings other than the host pass's note about the packed-FP32
+    target feature (expected: the flag is meant for the device code)."""
+    return [l for l in text.splitlines() if "warning:" in l and "packed-fp32-ops" not in l]
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s%s" % (src, r.stdout, r.stderr))
+    for w in _warnings(r.stderr):
+        print(w, file=sys.stderr)
     return obj
 
 
