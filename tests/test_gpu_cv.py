@@ -135,3 +135,29 @@ def test_coordination_overlap_and_switch_near_r0(gpu):
     assert np.max(np.abs(xi.cpu().numpy()[0] - rx) / np.abs(rx)) <= 1e-6
     for d in range(3):
         assert rel_inf(Jd[d], rJ[d]) <= 1e-5
+
+
+def test_coordination_partner_group_over_several_lds_rounds(gpu):
+    """Groups of 200 and 3,000 atoms (the small side's members gather over
+    the other group staged in LDS 1,024 at a time: three rounds, the last
+    partial), all pairs and with a 1.0 nm cut, on two walkers of a 4 nm
+    periodic box; values <= 1e-6 relative and every Jacobian slot <= 1e-5 of
+    the oracle's."""
+    g = np.random.default_rng(17)
+    n, W, L = 3300, 2, np.array([4.0, 4.0, 4.0])
+    off = np.arange(W + 1, dtype=np.int64) * n
+    pos = g.uniform(0.0, 4.0, size=(W * n, 3)).astype(np.float32)
+    a, b = list(range(0, 200)), list(range(300, 3300))
+    cvs = [{"kind": "coordination", "a": a, "b": b, "r0": 0.5, "n": 6, "m": 12, "rcut": 0.0, "normalize": False},
+           {"kind": "coordination", "a": a, "b": b, "r0": 0.4, "n": 8, "m": 14, "rcut": 1.0, "normalize": True}]
+    s = cv_ctx(cvs, L, off)
+    xi, J = s.eval_cv(dev(pos))
+    xi, J = xi.cpu().numpy(), J.cpu().numpy()
+    atom, cvi = s.jac_layout()
+    for w in range(W):
+        x = pos[off[w]:off[w + 1]].astype(np.float64)
+        rx, rJ = oracle.cv_eval(x, cvs, L)
+        assert np.max(np.abs(xi[w] - rx) / np.abs(rx)) <= 1e-6
+        Jd = dense_jac(J[w], atom, cvi, n, 2)
+        for d in range(2):
+            assert rel_inf(Jd[d], rJ[d]) <= 1e-5
