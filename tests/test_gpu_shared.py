@@ -26,8 +26,13 @@ def shared_ctx(cvs, sigma, W, n_atoms, cap, stride=500, bias_factor=6.0):
     return s
 
 
-def test_shared_list_walkers_step_and_deposit(gpu):
-    W, n, K = 24, 12, 5000
+@pytest.mark.parametrize("K", [5000, 20000])
+def test_shared_list_walkers_step_and_deposit(gpu, K):
+    """K = 5,000: few chunk records per walker (one lane per walker sums
+    them); K = 20,000: more than 32 (one wavefront per walker, the force
+    table in the kernel arguments); both with the step-0 deposit and the
+    full list's capacity report."""
+    W, n = 24, 12
     cvs = synth.backbone_cvs(1)
     tmpl = synth.chain_template(n, 4)
     pos = np.concatenate([tmpl + np.random.default_rng(w).normal(0, 0.2, tmpl.shape) for w in range(W)])
