@@ -183,8 +183,9 @@ def test_momentum_estimator_matches_oracle(gpu):
 @pytest.mark.parametrize("estimator", [0, 1])
 def test_abf_many_touched_atoms_matches_oracle(gpu, estimator):
     """Walkers touching more than 512 atoms (phi and the radius of gyration
-    of 600 atoms: the per-block Gram records, the one-wavefront solve and
-    the separate force gather) on three walkers of 700 atoms, with the
+    of 600 atoms: the two-launch form -- per-block Gram records and a
+    snapshot of the update's inputs, then the sums, solve, grid update and
+    force gather) on three walkers of 700 atoms, with the
     projected-force estimator (random system forces) and the momentum
     estimator (per-atom masses, momenta drawn per step): per step the bias
     along xi and the forces, after the run the histogram (exact) and the
