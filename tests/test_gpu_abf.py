@@ -210,7 +210,7 @@ def test_abf_many_touched_atoms_matches_oracle(gpu, estimator):
         s.abf_momentum(dt, masses)
     s.bind()
     atom, _ = s.jac_layout()
-    assert len(np.unique(atom)) > 512  # the three-launch form
+    assert len(np.unique(atom)) > 512  # the two-launch form
     grids = [oracle.AbfGrid(lo, hi, nb, [True, False], thr) for _ in range(W)]
     prev = [None] * W
     Fb = torch.zeros((W * n, 3), dtype=torch.float32, device=gpu)
