@@ -1,0 +1,36 @@
+"""The benchmark's command-line contract on the CPU: it measures one GPU,
+so a request for more exits with status 2 and says why, before anything
+touches a device; the traffic record is read only while the kernel sources
+hash to the value recorded with the counters."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr or "single" in r.stderr
+    assert r.stdout == ""
+
+
+def test_traffic_record_keyed_to_sources(monkeypatch):
+    sha = bench.kernel_sources_sha()
+    assert len(sha) == 16 and all(c in "0123456789abcdef" for c in sha)
+    rec = {}
+    for line in open(os.path.join(ROOT, "profiles", "hill_tiles_walkers256_traffic.txt")):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            rec[k.strip()] = v.strip()
+    # with the recorded hash the figure is read; with any other it is not
+    monkeypatch.setattr(bench, "kernel_sources_sha", lambda: rec["kernel_sources_sha"])
+    assert bench.measured_traffic(4096) == float(rec["traffic_bytes_per_launch.tile4096"])
+    assert bench.measured_traffic(8192) is None  # no counters at that tile
+    monkeypatch.setattr(bench, "kernel_sources_sha", lambda: "0" * 16)
+    assert bench.measured_traffic(4096) is None
