@@ -20,6 +20,7 @@
 // Node sums run in FP64 in the order the hills sit in the list, so a grid
 // holds the exact hill sum at its nodes up to the rounding of exp.
 #include "sx_internal.h"
+#include "dev_cv.h"
 #include "dev_gather.h"
 
 namespace sx {
@@ -163,24 +164,82 @@ __global__ void __launch_bounds__(kBlock) k_grid_step(GridArgs g)
 // the outputs and deposits, lane u < U adds atom u's force.
 __global__ void __launch_bounds__(64) k_grid_step_wave(GridArgs g)
 {
+    __shared__ float s_J[4 * kMaxBiasDim][3];  // fused CVs: the walker's Jacobian slots
     const int32_t w = blockIdx.x;
     const int32_t l = g.shared ? 0 : w;
     const int lane = threadIdx.x;
-    // xi over the largest CV count with the index clamped to the last CV (in
-    // bounds, the extra entries unused), so the loads are issued together
-    double xi[kMaxBiasDim];
-#pragma unroll
-    for (int d = 0; d < kMaxBiasDim; ++d) xi[d] = g.xi[(int64_t)w * g.D + min(d, g.D - 1)];
     const bool dep_cnt = g.deposit == 1 && g.stride > 0;
     const int64_t dstep = dep_cnt && g.step < 0 ? *g.dstep : 0;
     const int32_t cnt = g.deposit ? g.count[l] : 0;
     const WalkerRec wr = g.wrec[l];
+    const int64_t aoff = g.tabs.atom_off[w];
     SmallGather sg{0.f, 0.f, 0.f, nullptr};
     int nent = 0;
     int32_t cvq[kSmallPer];
     float jr[kSmallPer][3];
-    small_rows(g.small, g.J + (int64_t)w * g.nslots * 3, g.F, g.tabs.atom_off[w], min(lane, g.small.U - 1), sg, nent,
-               cvq, jr);
+    double xi[kMaxBiasDim];
+    if (g.fuse_cv) {
+        // lane d < D evaluates dihedral d of the walker in FP64 (atom indices
+        // and slots selected from the kernel arguments by value); its value
+        // goes to every lane, its four gradient rows to LDS and the workspace
+        int32_t at[4], slot0 = g.cs.cv[0].slot0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) at[q] = g.cs.cv[0].atom[q];
+#pragma unroll
+        for (int d = 1; d < kMaxBiasDim; ++d)
+            if (lane == d && d < g.D) {
+                slot0 = g.cs.cv[d].slot0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) at[q] = g.cs.cv[d].atom[q];
+            }
+        double xd = 0.0;
+        if (lane < g.D) {
+            double3 r[4], gr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[q] = ld_pos(g.pos, aoff + at[q]);
+            xd = dihedral_fp64<true>(r, gr);
+            g.xi_ws[(int64_t)w * g.D + lane] = xd;
+            float *js = g.J_ws + ((int64_t)w * g.nslots + slot0) * 3;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float gx = (float)gr[q].x, gy = (float)gr[q].y, gz = (float)gr[q].z;
+                js[3 * q] = gx;
+                js[3 * q + 1] = gy;
+                js[3 * q + 2] = gz;
+                s_J[slot0 + q][0] = gx;
+                s_J[slot0 + q][1] = gy;
+                s_J[slot0 + q][2] = gz;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < kMaxBiasDim; ++d) xi[d] = __shfl(xd, min(d, g.D - 1), 64);
+        // this lane's table row and force (the Jacobian rows come from LDS)
+        const int u = min(lane, g.small.U - 1);
+        nent = g.small.nent[u];
+        sg.dst = g.F.ptr + (aoff + g.small.touched[u]) * g.F.sa;
+        sg.f0 = sg.dst[0];
+        sg.f1 = sg.dst[g.F.sk];
+        sg.f2 = sg.dst[2 * g.F.sk];
+        int32_t e[kSmallPer];
+#pragma unroll
+        for (int q = 0; q < kSmallPer; ++q) e[q] = g.small.ent[u][q];
+        __syncthreads();  // s_J written (one wavefront)
+#pragma unroll
+        for (int q = 0; q < kSmallPer; ++q) {
+            const int32_t slot = e[q] & 0xFFFFF;  // < 4 D: every CV a dihedral
+            cvq[q] = e[q] >> 20;
+            jr[q][0] = s_J[slot][0];
+            jr[q][1] = s_J[slot][1];
+            jr[q][2] = s_J[slot][2];
+        }
+    } else {
+        // xi over the largest CV count with the index clamped to the last
+        // CV (in bounds, the extra entries unused), so the loads are issued
+        // together
+#pragma unroll
+        for (int d = 0; d < kMaxBiasDim; ++d) xi[d] = g.xi[(int64_t)w * g.D + min(d, g.D - 1)];
+        small_rows(g.small, g.J + (int64_t)w * g.nslots * 3, g.F, aoff, min(lane, g.small.U - 1), sg, nent, cvq, jr);
+    }
     int32_t i0[kMaxBiasDim], i1[kMaxBiasDim];
     double t[kMaxBiasDim];
     const bool inside = grid_cell(g, xi, i0, i1, t);
@@ -342,7 +401,9 @@ hipError_t launch_scale_f64(double *x, int64_t n, double a, hipStream_t s)
 hipError_t launch_grid_step(const GridArgs &g, hipStream_t s)
 {
     if (g.tabs.W < 1 || g.L < 1) return hipErrorInvalidValue;
-    if (g.do_forces && g.small.on && g.small.U > 0)
+    const bool wave = g.do_forces && g.small.on && g.small.U > 0;
+    if (g.fuse_cv && !wave) return hipErrorInvalidValue;  // only the wavefront step evaluates CVs
+    if (wave)
         hipLaunchKernelGGL(k_grid_step_wave, dim3(g.tabs.W), dim3(64), 0, s, g);
     else
         hipLaunchKernelGGL(k_grid_step, dim3(g.tabs.W), dim3(kBlock), 0, s, g);

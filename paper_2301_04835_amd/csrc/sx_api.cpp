@@ -923,8 +923,12 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
     float *J = at<float>(c->ws, p.w_J);
     if (c->method == M_NONE) return fail(c, SX_ESTATE, "no method configured (sx_metad_config / sx_abf_config)");
     const bool fuse = c->method == M_METAD && p.all_dihedral && !c->shared && !c->sg_on && !c->mg_on;
+    // the one-wavefront grid step evaluates dihedral CVs itself (forces
+    // through the kernel-argument table)
+    const bool fuse_grid = c->method == M_METAD && c->mg_on && !c->sg_on && p.all_dihedral && p.small.on &&
+                           p.small.U > 0 && forces != nullptr && p.nslots <= 4 * kMaxBiasDim;
     if (c->sg_on) return enqueue_surrogate_step(c, pv, step, xi, J, xi_out, V_out, dVdxi_out, forces, layout);
-    if (!fuse) {
+    if (!fuse && !fuse_grid) {
         sx_status st = launch_cvs(c, pv, xi, J);
         if (st != SX_OK) return st;
     }
@@ -939,6 +943,13 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         g.step = step;
         g.do_forces = forces != nullptr;
         g.F = force_view(c, forces, layout);
+        if (fuse_grid) {
+            g.fuse_cv = 1;
+            g.cs = p.cs;
+            g.pos = pv;
+            g.xi_ws = xi;
+            g.J_ws = J;
+        }
         hipError_t e = launch_grid_step(g, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "bias-grid kernels");
         if (sx_status st = cell_forces(c, pv, g.dV_ws, -1.0, forces, layout)) return st;

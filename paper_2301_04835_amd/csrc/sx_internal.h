@@ -219,6 +219,13 @@ struct GridArgs {
     WalkerTabs tabs;
     ForceView F;
     SmallTabs small;  // the gather table in kernel-argument form (on = 0: the walker tables)
+    // fuse_cv: every CV a dihedral, evaluated by the one-wavefront step
+    // itself from the positions (values into xi_ws, gradients into J_ws)
+    int32_t fuse_cv;
+    CvSet cs;
+    PosView pos;
+    double *xi_ws;
+    float *J_ws;
 };
 
 // Harmonic bias k/2 (xi - xi0_w)^2 per walker (umbrella windows) and the
