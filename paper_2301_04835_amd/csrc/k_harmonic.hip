@@ -6,21 +6,46 @@
 // FP64 sums (count, sum D, sum D D^T), from which its mean and covariance
 // and the mean force k (xi0 - <xi>) follow.
 #include "sx_internal.h"
+#include "dev_cv.h"
 #include "dev_gather.h"
 
 namespace sx {
 namespace {
 
-// one workgroup per walker; thread 0 owns the window's bookkeeping
+// one workgroup per walker; thread 0 owns the window's bookkeeping.  With
+// fuse_cv thread d < D first evaluates dihedral d (FP64) from the positions:
+// its value into LDS and the workspace, its gradient rows into the
+// workspace's Jacobian, which the gather below reads after the barrier.
 __global__ void __launch_bounds__(kBlock) k_harmonic(HarmonicArgs a)
 {
     __shared__ double s_coef[kMaxCv];
+    __shared__ double s_xi[kMaxBiasDim];
     const int32_t w = blockIdx.x;
+    if (a.fuse_cv) {
+        if ((int)threadIdx.x < a.D) {
+            const CvDesc &cv = a.cs.cv[threadIdx.x];
+            const int64_t aoff = a.tabs.atom_off[w];
+            double3 r[4], gr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[q] = ld_pos(a.pos, aoff + cv.atom[q]);
+            const double x = dihedral_fp64<true>(r, gr);
+            s_xi[threadIdx.x] = x;
+            a.xi_ws[(int64_t)w * a.D + threadIdx.x] = x;
+            float *js = a.J_ws + ((int64_t)w * a.nslots + cv.slot0) * 3;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                js[3 * q] = (float)gr[q].x;
+                js[3 * q + 1] = (float)gr[q].y;
+                js[3 * q + 2] = (float)gr[q].z;
+            }
+        }
+        __syncthreads();  // s_xi, and the Jacobian rows the gather reads
+    }
     if (threadIdx.x == 0) {
         double Dv[kMaxBiasDim], V = 0.0;
         bool finite = true;
         for (int d = 0; d < a.D; ++d) {
-            const double x = a.xi[(int64_t)w * a.D + d];
+            const double x = a.fuse_cv ? s_xi[d] : a.xi[(int64_t)w * a.D + d];
             double t = x - a.xi0[(int64_t)w * a.D + d];
             if (a.period[d] > 0.0) t -= a.period[d] * rint(t / a.period[d]);
             Dv[d] = t;

@@ -927,8 +927,10 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
     // through the kernel-argument table)
     const bool fuse_grid = c->method == M_METAD && c->mg_on && !c->sg_on && p.all_dihedral && p.small.on &&
                            p.small.U > 0 && forces != nullptr && p.nslots <= 4 * kMaxBiasDim;
+    // the harmonic kernel evaluates dihedral CVs itself
+    const bool fuse_harmonic = c->method == M_HARMONIC && p.all_dihedral;
     if (c->sg_on) return enqueue_surrogate_step(c, pv, step, xi, J, xi_out, V_out, dVdxi_out, forces, layout);
-    if (!fuse && !fuse_grid) {
+    if (!fuse && !fuse_grid && !fuse_harmonic) {
         sx_status st = launch_cvs(c, pv, xi, J);
         if (st != SX_OK) return st;
     }
@@ -992,6 +994,13 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.step = step;
         a.do_forces = forces != nullptr;
         a.F = force_view(c, forces, layout);
+        if (fuse_harmonic) {
+            a.fuse_cv = 1;
+            a.cs = p.cs;
+            a.pos = pv;
+            a.xi_ws = xi;
+            a.J_ws = J;
+        }
         hipError_t e = launch_harmonic(a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "harmonic kernel");
         if (sx_status st = cell_forces(c, pv, a.dV_ws, -1.0, forces, layout)) return st;

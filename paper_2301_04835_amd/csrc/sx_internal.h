@@ -247,6 +247,13 @@ struct HarmonicArgs {
     const float *J;
     WalkerTabs tabs;
     ForceView F;
+    // fuse_cv: every CV a dihedral, evaluated by the kernel itself from the
+    // positions (values into xi_ws, gradients into J_ws, which J then reads)
+    int32_t fuse_cv;
+    CvSet cs;
+    PosView pos;
+    double *xi_ws;
+    float *J_ws;
 };
 
 struct SharedArgs {
