@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the one-walker hill-count sweep")
     ap.add_argument("--no-umbrella", action="store_true", help="skip the harmonic-window workload")
     ap.add_argument("--no-abf", action="store_true", help="skip the ABF workload")
+    ap.add_argument("--no-wtmd22", action="store_true", help="skip the 22-atom 1,000-step workload")
     ap.add_argument("--cn3-steps", type=int, default=50, help="timed steps of the coordination-number workload")
     ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2301_04835_amd", "tuning_mi355x.json"),
                     help="autotuner cache (JSON): an entry for this problem shape is reused, else searched and added")
@@ -179,6 +180,106 @@ def bust_leg(d, p, tile, grid, reps):
     return {"walkers": R * W, "hill_bytes": nbytes, "kernel_ms": ms_a, "finalize_kernel_ms": ms_b,
             "achieved": nbytes / (ms_a * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": nbytes / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def graph_len(steps, cap):
+    """Steps per captured graph: the largest divisor of `steps` that is at
+    most `cap`, so that exactly `steps` steps are timed in whole graphs."""
+    for g in range(max(1, min(cap, steps)), 0, -1):
+        if steps % g == 0:
+            return g
+    return 1
+
+
+def capacity_leg(d, p, tile, grid, reps, factor=4):
+    """The 256-walker hill-sum kernel with each walker's capacity reserved at
+    `factor` x its hill count (as a run that preallocates for the hills it
+    will deposit): the kernel's time follows the hills present, not the
+    space reserved."""
+    import torch
+    from paper_2301_04835_amd import Sampler
+
+    s = Sampler(0)
+    s.add_cvs(d["cvs"])
+    s.set_walkers(d["atom_off"], factor * d["n_hills"])
+    s.metad(p["sigma"], p["w"], p["T"], p["bias_factor"], p["stride"], 1)
+    s.bind()
+    hoff = d["hill_off"]
+    for w in range(p["n_walkers"]):
+        s.hills_set(w, d["centers"][hoff[w]:hoff[w + 1]], d["heights"][hoff[w]:hoff[w + 1]])
+    s.set_tuning(tile, grid)
+    pos = torch.from_numpy(d["pos"]).cuda()
+    forces = torch.zeros_like(pos)
+    ms_a, ms_b = s.time_hill(pos, forces=forces, reps=reps)
+    nbytes = int(np.sum(s.hill_counts())) * 12
+    return {"capacity_over_count": factor, "capacity_hills": int(factor * d["n_hills"].sum()),
+            "hills": int(np.sum(s.hill_counts())), "kernel_ms": ms_a, "finalize_kernel_ms": ms_b,
+            "achieved": nbytes / (ms_a * 1e-3) / 1e9, "unit": "GB/s"}
+
+
+def wtmd22_leg(args):
+    """The 22-atom workload: phi/psi of one chain, 2,000 hills whose heights
+    follow the well-tempered law (deposited one after another on the GPU),
+    sigma 0.35 rad, w 1.2 kJ/mol, bias factor 6, T 300 K, stride 500; 1,000
+    steps with fresh FP64 positions each step (template + N(0, 0.02^2) nm),
+    one library call per step as an engine makes it, returning xi, V,
+    dV/dxi and the atom forces of every step."""
+    import torch
+    from paper_2301_04835_amd import Sampler, synth
+
+    p = synth.WTMD22
+    d = synth.wtmd22_inputs()
+    s = Sampler(0)
+    s.add_cvs(d["cvs"])
+    s.metad(list(p["sigma"]), p["w"], p["T"], p["bias_factor"], p["stride"], p["n_hills"] + 8)
+    s.bind()
+    xs = torch.from_numpy(d["centers"].astype(np.float64)).cuda()
+    for k in range(p["n_hills"]):  # the well-tempered sequence: each hill sees the ones before it
+        s.deposit(xs[k:k + 1])
+    T = p["n_steps"]
+    frames = torch.from_numpy(d["frames"]).cuda()
+    F = torch.zeros((T, p["n_atoms"], 3), dtype=torch.float32, device="cuda")
+    xi = torch.zeros((T, 1, 2), dtype=torch.float64, device="cuda")
+    V = torch.zeros((T, 1), dtype=torch.float64, device="cuda")
+    dV = torch.zeros((T, 1, 2), dtype=torch.float64, device="cuda")
+    for t in range(20):  # warm-up on a scratch force buffer, no deposition
+        s.step(frames[t], forces=F[0], step=1, V_out=V[0])
+    F.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(T):
+        s.step(frames[t], forces=F[t], step=t, xi_out=xi[t], V_out=V[t], dV_out=dV[t])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.check()
+    return {"workload": "wtmd22-2000-hills-1000-steps", "atoms": p["n_atoms"], "hills": p["n_hills"],
+            "steps": T, "steps_per_s": T / el, "ms_per_step": el * 1e3 / T,
+            "calls": "one sx_step per step (fresh positions), eager", "hills_after": int(s.hill_counts()[0])}
+
+
+def wtmd22_oracle(d_unused=None):
+    """CPU oracle leg of the 22-atom workload: its 1,000 steps (CVs, hill sum
+    over 2,000 well-tempered hills, chain rule, deposits at steps 0 and 500),
+    FP64, one thread."""
+    import oracle
+    from paper_2301_04835_amd import synth
+
+    p = synth.WTMD22
+    d = synth.wtmd22_inputs()
+    kdT = oracle.KB * (p["bias_factor"] - 1.0) * p["T"]
+    C = d["centers"].astype(np.float64)
+    H = oracle.wt_sequence(C, p["w"], kdT, p["sigma"], [2 * np.pi, 2 * np.pi], round_f32=True)
+    C, H = list(C), list(H)
+    t0 = time.perf_counter()
+    for t in range(d["frames"].shape[0]):
+        o = oracle.metad_step(d["frames"][t], d["cvs"], np.array(C), np.array(H), p["sigma"], p["w"], kdT,
+                              p["stride"], t)
+        if o["deposit"] is not None:
+            C.append(o["deposit"][0])
+            H.append(o["deposit"][1])
+    el = time.perf_counter() - t0
+    return {"value": d["frames"].shape[0] / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": "all %d steps, FP64, 1 thread, %.2f s" % (d["frames"].shape[0], el)}
 
 
 def timed_graph(s, pos, forces, outs, steps, warmup, gsteps=10, sys_forces=None):
@@ -580,7 +681,7 @@ def main():
     torch.cuda.synchronize()
     s.autotune(pos, cache_path=args.tuning_cache)
     tile, grid = s.get_tuning()
-    gsteps = args.graph_steps if args.steps % args.graph_steps == 0 else 1
+    gsteps = graph_len(args.steps, args.graph_steps)
     s.graph_capture(gsteps, pos, forces=forces, xi_out=xi, V_out=V, dV_out=dV)
     for _ in range(max(1, args.warmup // gsteps)):
         s.graph_launch()
@@ -642,6 +743,9 @@ def main():
             s.L.sx_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nb, 2048,
                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
+    out["capacity_4x_count"] = capacity_leg(d, p, tile, grid, args.hill_reps)
+    if not args.no_wtmd22:
+        out["wtmd22"] = wtmd22_leg(args)
     if not args.no_bust:
         out["roofline_above_infinity_cache"] = bust_leg(d, p, tile, grid, args.hill_reps)
     if not args.no_sweep:
@@ -667,6 +771,8 @@ def main():
             out["cn3"].update(cn3_oracle(cn_data))
         if ad is not None:
             out["abf"].update(abf_oracle_check(ad))
+        if "wtmd22" in out:
+            out["wtmd22"]["cpu_oracle"] = wtmd22_oracle()
     print(json.dumps(out))
 
 

@@ -8,15 +8,17 @@
 
 namespace sx {
 
-// touched atom u of walker w; Jw: the walker's slots (s x 3 floats)
-__device__ __forceinline__ void gather_atom(const WalkerTabs &t, const float *Jw, int32_t w, const double *coef,
+// touched atom u of walker w; Jw: the walker's slots (s x 3; JT float, or
+// double on the ABF path)
+template <typename JT>
+__device__ __forceinline__ void gather_atom(const WalkerTabs &t, const JT *Jw, int32_t w, const double *coef,
                                             const ForceView &F, int u)
 {
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
         const int32_t s = t.inv_slot[q];
         const double cf = coef[t.slot_cv[s]];
-        const float *js = Jw + (int64_t)s * 3;
+        const JT *js = Jw + (int64_t)s * 3;
         fx += cf * (double)js[0];
         fy += cf * (double)js[1];
         fz += cf * (double)js[2];
@@ -66,16 +68,18 @@ __device__ __forceinline__ void small_rows(const SmallTabs &st, const float *Jw,
 // exist; atom_add then sums in the same order and arithmetic as gather_atom
 // (entries past kAtomRows are read there, as gather_atom reads them).
 constexpr int kAtomRows = 4;
+template <typename JT>
 struct AtomRows {
     int32_t q0, q1;
     int32_t cv[kAtomRows];
-    float j[kAtomRows][3];
+    JT j[kAtomRows][3];
     float f0, f1, f2;
     float *dst;
 };
 
-__device__ __forceinline__ void atom_rows(const WalkerTabs &t, const float *Jw, int32_t w, const ForceView &F, int u,
-                                          AtomRows &r)
+template <typename JT>
+__device__ __forceinline__ void atom_rows(const WalkerTabs &t, const JT *Jw, int32_t w, const ForceView &F, int u,
+                                          AtomRows<JT> &r)
 {
     r.q0 = t.inv_ptr[u];
     r.q1 = t.inv_ptr[u + 1];  // > q0: a touched atom has a slot
@@ -93,8 +97,9 @@ __device__ __forceinline__ void atom_rows(const WalkerTabs &t, const float *Jw, 
     r.f2 = r.dst[2 * F.sk];
 }
 
-__device__ __forceinline__ void atom_add(const WalkerTabs &t, const float *Jw, const double *coef, const ForceView &F,
-                                         const AtomRows &r)
+template <typename JT>
+__device__ __forceinline__ void atom_add(const WalkerTabs &t, const JT *Jw, const double *coef, const ForceView &F,
+                                         const AtomRows<JT> &r)
 {
     double fx = 0.0, fy = 0.0, fz = 0.0;
 #pragma unroll
@@ -108,7 +113,7 @@ __device__ __forceinline__ void atom_add(const WalkerTabs &t, const float *Jw, c
     for (int q = r.q0 + kAtomRows; q < r.q1; ++q) {
         const int32_t s = t.inv_slot[q];
         const double cf = coef[t.slot_cv[s]];
-        const float *js = Jw + (int64_t)s * 3;
+        const JT *js = Jw + (int64_t)s * 3;
         fx += cf * (double)js[0];
         fy += cf * (double)js[1];
         fz += cf * (double)js[2];
@@ -119,7 +124,8 @@ __device__ __forceinline__ void atom_add(const WalkerTabs &t, const float *Jw, c
 }
 
 // the whole walker, lanes of the workgroup striding over its touched atoms
-__device__ __forceinline__ void gather_forces(const WalkerTabs &t, const float *Jw, int32_t w, const double *coef,
+template <typename JT>
+__device__ __forceinline__ void gather_forces(const WalkerTabs &t, const JT *Jw, int32_t w, const double *coef,
                                               const ForceView &F)
 {
     for (int u = threadIdx.x; u < t.U; u += blockDim.x) gather_atom(t, Jw, w, coef, F, u);

@@ -1,12 +1,15 @@
-// Adaptive biasing force (Sec. 2.1.4, after Darve et al. 2008): one
-// workgroup per walker.  Per touched atom i the Jacobian rows j_d (slots of
-// one atom and one CV summed) give, in FP64 over the workgroup,
+// Adaptive biasing force (Sec. 2.1.4): one workgroup per walker.  Per
+// touched atom i the Jacobian rows j_d (FP64; slots of one atom and one CV
+// summed) give, in FP64 over the workgroup,
 //   G = sum_i m_i^-1 j_d . j_e     and   u = sum_i m_i^-1 j_d . q_i .
-// Projected-force estimator: unit masses, q = the system force, and
-// theta = -G^-1 u.  Momentum estimator: q = the momentum, G^-1 u = W p (the
-// CV-space momentum, W = (J M^-1 J^T)^-1 J M^-1), and
-// theta = b_prev - (W p - (W p)_prev) / dt, b_prev the bias of the previous
-// step (no sample on a walker's first step).  The bias of the bin of xi is
+// Momentum estimator (the one of Darve et al. that the paper cites):
+// q = the momentum, G^-1 u = W p (the CV-space momentum,
+// W = (J M^-1 J^T)^-1 J M^-1), and theta = b_prev - (W p - (W p)_prev) / dt,
+// b_prev the bias of the previous step (no sample on a walker's first step).
+// Projected-force estimator, for inputs without dynamics: unit masses,
+// q = the system force, theta = -G^-1 u; it omits the divergence term
+// k_B T div(J^T (J J^T)^-1) that the mean force of a nonlinear CV carries
+// (zero for linear CVs).  The bias of the bin of xi is
 // Fsum / max(N, N_thr) from the samples before this step (with FUNN: the
 // gradient of the network fitted to the mean forces, evaluated at xi, inside
 // the grid's range); then N += 1, Fsum += theta, and the bias force is
@@ -33,7 +36,7 @@ __device__ __forceinline__ void abf_atom_terms(const AbfArgs &a, int32_t w, int 
     for (int q = t.inv_ptr[u]; q < t.inv_ptr[u + 1]; ++q) {
         const int32_t s = t.inv_slot[q];
         const int d = t.slot_cv[s];
-        const float *js = a.J + (jb + s) * 3;
+        const double *js = a.J + (jb + s) * 3;
 #pragma unroll
         for (int dd = 0; dd < MD; ++dd)
             if (dd == d) {
@@ -273,8 +276,8 @@ __global__ void __launch_bounds__(kBlock) k_abf_finish(AbfArgs a)
     const int32_t w = blockIdx.y;
     // this lane's atom: its rows and force requested before the solve
     const int u = blockIdx.x * kBlock + threadIdx.x;
-    const float *Jw = a.J + (int64_t)w * a.nslots * 3;
-    AtomRows rows;
+    const double *Jw = a.J + (int64_t)w * a.nslots * 3;
+    AtomRows<double> rows;
     if (u < a.tabs.U) atom_rows(a.tabs, Jw, w, a.F, u, rows);
     if (threadIdx.x < 64) {  // the first wavefront
         const AbfPre pre = a.pre[w];

@@ -4,11 +4,14 @@
 //
 // Hill sum over private hill lists (one list per walker), two kernels:
 //   A  k_hill_tiles: a static table of tiles (walker, first hill), each
-//      1024 * U hills of one walker's capacity.  Hills are stored SoA in
-//      float32 (centres c[d][k], heights h[k]); every lane issues its float4
-//      loads of a batch of 4 groups before using any of them (clamped to the
-//      walker's padded capacity and masked by its count, so no branch sits
-//      between the loads), which keeps enough bytes in flight to stream HBM.
+//      1024 * U hills of one walker's capacity.  A tile at or past the
+//      walker's current hill count leaves at once, so the work follows the
+//      hills deposited so far, not the space reserved for them.  Hills are
+//      stored SoA in float32 (centres c[d][k], heights h[k]); every lane
+//      issues its float4 loads of a batch of 4 groups before using any of
+//      them (clamped to the group of the walker's last hill and masked by
+//      its count, so no branch sits between the loads), which keeps enough
+//      bytes in flight to stream HBM.
 //      When every CV is a dihedral the tile's workgroup computes its
 //      walker's xi itself (FP64) while its hill loads are in flight, so no
 //      separate CV kernel runs.  The displacement and its periodic wrap are
@@ -16,8 +19,8 @@
 //      math), the Gaussian in FP32 with the hardware exp2, the sums in FP64
 //      per group of 4 hills.  Each tile writes its partial (V, sum e D_d) to
 //      its own record.
-//   B  k_hill_finalize: one workgroup per walker reduces that walker's tile
-//      records in tile order (bitwise deterministic whatever the schedule),
+//   B  k_hill_finalize: one workgroup per walker reduces that walker's live
+//      tile records in tile order (bitwise deterministic whatever the schedule),
 //      forms dV/dxi, writes the outputs, deposits the well-tempered hill and
 //      gathers the force onto the walker's atoms.  The kernel boundary is the
 //      only cross-workgroup synchronisation: no fences, no atomics.
@@ -157,14 +160,22 @@ __device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, co
         const int64_t aoff = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(tr.aoff_hi) << 32) |
                                        (uint32_t)__builtin_amdgcn_readfirstlane(tr.aoff_lo));
         const int32_t w = tr.w;
+        const int32_t n = ld_uniform(a.count + w);
+        // a tile at or past the walker's hill count has nothing to add and
+        // leaves on a uniform branch (kernel B reads only the live tiles);
+        // the first tile always runs: it also evaluates fused CVs
+        if (tr.h0 > 0 && tr.h0 >= n) return;
         const int64_t hb = (int64_t)tr.hb4 * 4;
         const float4 *cb[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) cb[d] = reinterpret_cast<const float4 *>(a.c[d] + hb);
         const float4 *hp = reinterpret_cast<const float4 *>(a.h + hb);
         const uint32_t q0 = (uint32_t)(tr.h0 / kHillsPerLoad) + threadIdx.x;
-        const uint32_t qlast = (uint32_t)(tr.klast / kHillsPerLoad);
-        const int32_t n = ld_uniform(a.count + w);
+        // loads are clamped to the float4 group of the last live hill (group
+        // 0 of an empty list), so no lane streams the empty capacity; the
+        // tile record's klast bounds the walker's capacity
+        const uint32_t qlast = min((uint32_t)(tr.klast / kHillsPerLoad),
+                                   n > 0 ? (uint32_t)(n - 1) / kHillsPerLoad : 0u);
         // fused CVs: lane d of wave 0 requests the positions of dihedral d
         // before the hill loads, computes the angle (FP64) while those are
         // in flight, and meets the other waves at the barrier below
@@ -252,6 +263,15 @@ __global__ void __launch_bounds__(kBlock) k_hill_tiles_persist(HillArgs a, CvSet
     }
 }
 
+// Tiles of a walker that kernel A ran: those starting below its hill count
+// (at least the first).  Kernel A saw the same count: nothing changes it
+// between the two kernels.
+__device__ __forceinline__ int32_t live_tiles(const HillArgs &a, const WalkerRec &wr, int32_t cnt)
+{
+    const int32_t T = a.tile_units * kTileUnit;
+    return min(wr.nt, max(1, (cnt + T - 1) / T));
+}
+
 template <int D, bool FUSE>
 __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, PosView pos)
 {
@@ -263,7 +283,8 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     // values thread 0 needs after the reduction, requested up front; the
     // step counter was set by kernel A and is constant during this kernel
     const int64_t next_step = a.deposit == 1 ? ld_uniform(a.dstep) : 0;
-    const int32_t cnt0 = a.deposit ? a.count[w] : 0;
+    const int32_t cnt0 = ld_uniform(a.count + w);
+    const int32_t nlive = live_tiles(a, wr, cnt0);
     // small gather table: lane u < U requests its atom's force and the
     // Jacobian rows it will combine before the reduction, so that only the
     // multiply-adds and the stores follow the barrier
@@ -278,7 +299,7 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     double acc[1 + D];
 #pragma unroll
     for (int j = 0; j <= D; ++j) acc[j] = 0.0;
-    for (int i = threadIdx.x; i < wr.nt; i += kBlock) {
+    for (int i = threadIdx.x; i < nlive; i += kBlock) {
         const double *p = a.partial + (int64_t)(wr.t0 + i) * 4;
 #pragma unroll
         for (int j = 0; j <= D; ++j) acc[j] += p[j];
@@ -351,15 +372,16 @@ __global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs,
     const int lane = threadIdx.x;
     const WalkerRec wr = ld_uniform(a.wrec + w);
     const int64_t next_step = a.deposit == 1 ? ld_uniform(a.dstep) : 0;
-    const int32_t cnt0 = a.deposit ? ld_uniform(a.count + w) : 0;  // scalar: no vector wait
+    const int32_t cnt0 = ld_uniform(a.count + w);  // scalar: no vector wait
+    const int32_t nlive = live_tiles(a, wr, cnt0);
     const bool small_lane = lane < a.small.U;  // launched only when forces are gathered
     SmallGather sg{0.f, 0.f, 0.f, nullptr};
     int nent = 0;
     int32_t cvq[kSmallPer];
     float jr[kSmallPer][3];
     // requested before anything waits, with no branch between the loads:
-    // the first tile record of each lane (lanes past the walker's count
-    // re-read its last one, nt >= 1, and drop it), the CV values, and a
+    // the first tile record of each lane (lanes past the walker's live tiles
+    // re-read a record inside its table, nt >= 1, and drop it), the CV values, and a
     // small-table row per lane (lanes past U re-read row U - 1 and store
     // nothing)
     double acc[1 + D];
@@ -375,10 +397,10 @@ __global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs,
     small_rows(a.small, a.J + (int64_t)w * a.nslots * 3, a.F, wr.aoff, min(lane, a.small.U - 1), sg, nent, cvq, jr);
     // the record is kept or replaced by +0.0 through a bit mask, which uses
     // the loaded value on every lane (a select lets the load move under a branch)
-    const long long keep = lane < wr.nt ? -1LL : 0LL;
+    const long long keep = lane < nlive ? -1LL : 0LL;
 #pragma unroll
     for (int j = 0; j <= D; ++j) acc[j] = 0.0 + __longlong_as_double(__double_as_longlong(r0[j]) & keep);
-    for (int i = lane + 64; i < wr.nt; i += 64) {  // the same order as one loop from i = lane
+    for (int i = lane + 64; i < nlive; i += 64) {  // the same order as one loop from i = lane
         const double *p = a.partial + (int64_t)(wr.t0 + i) * 4;
 #pragma unroll
         for (int j = 0; j <= D; ++j) acc[j] += p[j];

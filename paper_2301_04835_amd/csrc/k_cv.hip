@@ -17,18 +17,27 @@
 namespace sx {
 namespace {
 
+// Jacobian slot store: float for the hill-sum paths, double for ABF, whose
+// Gram matrix and J.F are formed from the rows as computed
 __device__ __forceinline__ void st_slot(float *J, int64_t slot, double3 g)
 {
     J[slot * 3 + 0] = (float)g.x;
     J[slot * 3 + 1] = (float)g.y;
     J[slot * 3 + 2] = (float)g.z;
 }
+__device__ __forceinline__ void st_slot(double *J, int64_t slot, double3 g)
+{
+    J[slot * 3 + 0] = g.x;
+    J[slot * 3 + 1] = g.y;
+    J[slot * 3 + 2] = g.z;
+}
 
 // ------------------------------------------------------------------ dihedral
 // One lane per (walker, dihedral CV), FP64 (see dihedral_fp64); block bx of
 // the dihedral range.
+template <typename JT>
 __device__ __forceinline__ void dihedral_block(const CvSet &cs, const WalkerTabs &t, const PosView &pos, double *xi,
-                                               float *J, int32_t ndih, int64_t bx)
+                                               JT *J, int32_t ndih, int64_t bx)
 {
     int64_t gid = bx * blockDim.x + threadIdx.x;
     if (gid >= (int64_t)t.W * ndih) return;
@@ -76,8 +85,9 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *lds /* N * kBl
 // ------------------------------------------------------- radius of gyration
 // Rg = sqrt((1/n) sum |r_i - c|^2), c = (1/n) sum r_i; dRg/dr_i = (r_i - c)/(n Rg).
 // One workgroup per (walker w, gyration CV j); lds: 4 * kBlock / 64 doubles.
+template <typename JT>
 __device__ __forceinline__ void gyration_block(const CvSet &cs, const WalkerTabs &t, const PosView &pos, double *xi,
-                                               float *J, int32_t w, int j, double *lds)
+                                               JT *J, int32_t w, int j, double *lds)
 {
     int c = 0, seen = 0;
     for (; c < cs.ncv; ++c)
@@ -140,9 +150,9 @@ __device__ __forceinline__ float min_img(double d, double L, double iL) { return
 // first writes the Jacobian slot.  On the A side the members' switch sums are
 // reduced per workgroup (fixed tree) into one value record per block, which
 // k_coord_value sums in order.
-template <typename T>
+template <typename T, typename JT>
 __device__ __forceinline__ void coord_block(const CvSet &cs, const WalkerTabs &t, const PosView &pos, double *vpart,
-                                            float *J, int32_t ncoord, int bx, int side, int z, Partner *oth,
+                                            JT *J, int32_t ncoord, int bx, int side, int z, Partner *oth,
                                             double *lds)
 {
     const int32_t w = z / ncoord, k = z % ncoord;
@@ -224,8 +234,8 @@ struct CvGrid {
     int64_t cn_blocks, rg_blocks;
 };
 
-template <typename T, bool CN>
-__global__ void __launch_bounds__(kBlock) k_cv_values(CvSet cs, WalkerTabs t, PosView pos, double *xi, float *J,
+template <typename T, bool CN, typename JT>
+__global__ void __launch_bounds__(kBlock) k_cv_values(CvSet cs, WalkerTabs t, PosView pos, double *xi, JT *J,
                                                        double *vpart, CvGrid g)
 {
     __shared__ Partner oth[CN ? kCnStage : 1];
@@ -233,7 +243,7 @@ __global__ void __launch_bounds__(kBlock) k_cv_values(CvSet cs, WalkerTabs t, Po
     int64_t b = blockIdx.x;
     if (CN && b < g.cn_blocks) {
         const int bx = (int)(b % g.cn_x), side = (int)((b / g.cn_x) % 2), z = (int)(b / (2 * (int64_t)g.cn_x));
-        coord_block<T>(cs, t, pos, vpart, J, g.ncn, bx, side, z, oth, lds);
+        coord_block<T, JT>(cs, t, pos, vpart, J, g.ncn, bx, side, z, oth, lds);
         return;
     }
     b -= g.cn_blocks;
@@ -262,10 +272,9 @@ __global__ void __launch_bounds__(64) k_coord_value(CvSet cs, const double *vpar
     if (threadIdx.x == 0) xi[(int64_t)w * cs.D + cv.d] = v * (double)cv.scale;
 }
 
-}  // namespace
-
-hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *cn_vpart,
-                     int64_t /*max_atoms_per_walker*/, hipStream_t s)
+template <typename JT>
+hipError_t launch_cv_t(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, JT *J, double *cn_vpart,
+                       hipStream_t s)
 {
     CvGrid g{};
     for (int c = 0; c < cs.ncv; ++c) {
@@ -285,19 +294,28 @@ hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *
     if (blocks == 0) return hipSuccess;
     if (g.ncn) {
         if (pos.f64)
-            hipLaunchKernelGGL((k_cv_values<double, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos, xi,
-                               J, cn_vpart, g);
+            hipLaunchKernelGGL((k_cv_values<double, true, JT>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos,
+                               xi, J, cn_vpart, g);
         else
-            hipLaunchKernelGGL((k_cv_values<float, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos, xi,
-                               J, cn_vpart, g);
+            hipLaunchKernelGGL((k_cv_values<float, true, JT>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos,
+                               xi, J, cn_vpart, g);
     } else {
-        hipLaunchKernelGGL((k_cv_values<float, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos, xi, J,
-                           cn_vpart, g);
+        hipLaunchKernelGGL((k_cv_values<float, false, JT>), dim3((unsigned)blocks), dim3(kBlock), 0, s, cs, t, pos, xi,
+                           J, cn_vpart, g);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !g.ncn) return e;
     hipLaunchKernelGGL(k_coord_value, dim3((unsigned)t.W * g.ncn), dim3(64), 0, s, cs, cn_vpart, xi, g.ncn);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *J64,
+                     double *cn_vpart, hipStream_t s)
+{
+    if (J64) return launch_cv_t<double>(cs, t, pos, xi, J64, cn_vpart, s);
+    return launch_cv_t<float>(cs, t, pos, xi, J, cn_vpart, s);
 }
 
 }  // namespace sx

@@ -88,7 +88,7 @@ struct Plan {
     Sub w_sgX, w_sgVt, w_sgGt, w_sgVn, w_sgGn, w_sgA2, w_sgDz2, w_sgY, w_sgDy, w_sgGpart, w_sgGsum, w_sgLoss;
     Sub w_sgFlag, w_sgRed;
     // workspace sub-buffers
-    Sub w_xi, w_V, w_dV, w_J, w_part, w_cnpart;
+    Sub w_xi, w_V, w_dV, w_J, w_J64, w_part, w_cnpart;
     int32_t abf_nblk = 0;  // ABF in two launches when > 0 (blocks of touched atoms)
     Sub w_abfpart, w_abfpre;
     Sub w_atom_off, w_tiles, w_wrec;
@@ -540,6 +540,8 @@ sx_status make_plan(sx_ctx *c)
     p.w_V = lw.take(sizeof(double) * p.W);
     p.w_dV = lw.take(sizeof(double) * p.W * p.D);
     p.w_J = lw.take(sizeof(float) * 3 * (size_t)p.W * p.nslots);
+    // ABF keeps the Jacobian rows in FP64 (its Gram matrix and J.F)
+    p.w_J64 = lw.take(c->method == M_ABF ? sizeof(double) * 3 * (size_t)p.W * p.nslots : 0);
     p.w_part = lw.take(sizeof(double) * 4 * (size_t)std::max<int64_t>(p.ntiles_max, p.shared_records));
     p.w_cnpart = lw.take(sizeof(double) * (size_t)p.W * p.cs.vblk_per_walker);
     p.abf_nblk = (c->method == M_ABF && p.U > kAbfSplitU) ? (p.U + kBlock - 1) / kBlock : 0;
@@ -762,7 +764,7 @@ MlpArgs mlp_args(sx_ctx *c)
     return a;
 }
 
-sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J);
+sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J, double *J64 = nullptr);
 sx_status cell_forces(sx_ctx *c, const PosView &pv, const double *coef, double sign, float *out, int32_t layout);
 
 // the surrogate's step: network for every walker (outputs, certification
@@ -892,10 +894,10 @@ CellArgs cell_args(sx_ctx *c)
     return a;
 }
 
-sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J)
+sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J, double *J64)
 {
     const Plan &p = c->plan;
-    hipError_t e = launch_cv(p.cs, tabs_of(c), pv, xi, J, at<double>(c->ws, p.w_cnpart), 0, c->stream);
+    hipError_t e = launch_cv(p.cs, tabs_of(c), pv, xi, J, J64, at<double>(c->ws, p.w_cnpart), c->stream);
     if (e == hipSuccess && p.cell.ncn) e = launch_cell_cv(cell_args(c), p.cs, pv, xi, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "CV kernels");
     return SX_OK;
@@ -930,8 +932,9 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
     // the harmonic kernel evaluates dihedral CVs itself
     const bool fuse_harmonic = c->method == M_HARMONIC && p.all_dihedral;
     if (c->sg_on) return enqueue_surrogate_step(c, pv, step, xi, J, xi_out, V_out, dVdxi_out, forces, layout);
+    double *J64 = c->method == M_ABF ? at<double>(c->ws, p.w_J64) : nullptr;
     if (!fuse && !fuse_grid && !fuse_harmonic) {
-        sx_status st = launch_cvs(c, pv, xi, J);
+        sx_status st = launch_cvs(c, pv, xi, J64 ? nullptr : J, J64);
         if (st != SX_OK) return st;
     }
     if (c->method == M_METAD && !c->sg_on && c->stride > 0) c->sg_certified = false;  // may deposit
@@ -1010,7 +1013,7 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         AbfArgs a{};
         a.D = p.D;
         a.xi = xi;
-        a.J = J;
+        a.J = J64;
         a.nslots = p.nslots;
         a.tabs = tabs_of(c);
         pos_view(c, sys_forces, SX_F32, layout, a.Fsys);

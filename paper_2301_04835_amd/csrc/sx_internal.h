@@ -152,7 +152,7 @@ struct AbfPre {
 struct AbfArgs {
     int32_t D;
     const double *xi;     // W x D
-    const float *J;       // W x nslots x 3
+    const double *J;      // W x nslots x 3 (FP64 rows: the Gram matrix and J.F see them as computed)
     int32_t nslots;
     WalkerTabs tabs;
     PosView Fsys;         // system forces (float)
@@ -354,8 +354,10 @@ struct MlpArgs {
 
 // ---------------------------------------------------------------- launchers
 // Each returns the hipError_t of its launch.
-hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *cn_part,
-                     int64_t max_atoms_per_walker, hipStream_t s);
+// Jacobian rows into J (float) or, when J64 is given, into J64 (double; the
+// ABF path); J may be null when only the values are wanted
+hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *J64,
+                     double *cn_part, hipStream_t s);
 // which: 1 = tiles (kernel A), 2 = finalize (kernel B), 3 = both
 hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s,
                                int which = 3);

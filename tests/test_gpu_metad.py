@@ -164,6 +164,58 @@ def test_ragged_walkers_all_tilings(gpu, tile, grid):
     assert torch.equal(F, F2) and torch.equal(V, V2)
 
 
+@pytest.mark.parametrize("tile,grid", [(1024, 0), (4096, 5)])
+def test_growing_lists_capacity_8x_count(gpu, tile, grid):
+    """Hill lists that grow during the run inside capacity reserved at 8x
+    their count (Sec. 2.1.5: hills are deposited cumulatively): every step
+    deposits one hill per walker (stride 1), counts start just below tile
+    boundaries so live tiles appear during the run, and the tiles past the
+    count leave at once.  Per step and walker: xi, V, dV/dxi and forces
+    against the oracle replaying the same deposits (float32 storage)."""
+    counts = [0, 1, 1020, 2045, 4093, 700]
+    caps = [8 * max(c, 64) for c in counts]
+    W, T = len(counts), 12
+    cvs = synth.backbone_cvs(1)
+    sig = [0.35, 0.3]
+    pos0, off, hills = _walkers(counts, caps, 23)
+    s = make_metad(cvs, sig, 1.2, 300.0, 6.0, 1, atom_off=off, hill_capacity=caps, tile=tile, grid=grid)
+    for w, (c, h) in enumerate(hills):
+        s.hills_set(w, c, h)
+    g = np.random.default_rng(24)
+    frames = [(pos0 + g.normal(0, 0.01, size=pos0.shape)).astype(np.float32) for _ in range(T)]
+    Cr = [c.astype(np.float64).tolist() for c, _ in hills]
+    Hr = [h.astype(np.float64).tolist() for _, h in hills]
+    worst = {"V": 0.0, "dV": 0.0, "F": 0.0}
+    for t in range(T):
+        P = dev(frames[t])
+        F = torch.zeros_like(P)
+        xi = torch.zeros((W, 2), dtype=torch.float64, device=gpu)
+        V = torch.zeros(W, dtype=torch.float64, device=gpu)
+        dV = torch.zeros((W, 2), dtype=torch.float64, device=gpu)
+        s.step(P, forces=F, step=t, xi_out=xi, V_out=V, dV_out=dV)
+        Fh, xh, Vh, dVh = F.cpu().numpy(), xi.cpu().numpy(), V.cpu().numpy(), dV.cpu().numpy()
+        for w in range(W):
+            o = oracle.metad_step(frames[t][off[w]:off[w + 1]], cvs, np.array(Cr[w]).reshape(-1, 2),
+                                  np.array(Hr[w]), sig, 1.2, KDT, 1, t)
+            assert np.max(np.abs(xh[w] - o["xi"])) <= 1e-9
+            if len(Hr[w]) == 0:
+                assert Vh[w] == 0.0 and np.all(dVh[w] == 0.0) and np.all(Fh[off[w]:off[w + 1]] == 0.0)
+            else:
+                worst["V"] = max(worst["V"], abs(Vh[w] - o["V"]) / abs(o["V"]))
+                worst["dV"] = max(worst["dV"], rel_inf(dVh[w], o["dV"]))
+                worst["F"] = max(worst["F"], rel_inf(Fh[off[w]:off[w + 1]], o["F"]))
+            Cr[w].append(np.float32(o["deposit"][0]).astype(np.float64).tolist())
+            Hr[w].append(float(np.float32(o["deposit"][1])))
+    s.check()
+    print("worst errors:", worst)
+    assert worst["V"] <= 1e-6 and worst["dV"] <= 1e-5 and worst["F"] <= 1e-5
+    for w in range(W):
+        c, h = s.hills_get(w)
+        assert c.shape[0] == counts[w] + T
+        assert np.array_equal(c.astype(np.float64), np.array(Cr[w], dtype=np.float32).astype(np.float64))
+        assert rel_inf(h, np.array(Hr[w])) <= 1e-6
+
+
 def test_walkers_256_full_size(gpu):
     """The batched-walker workload at its full size: 256 walkers, atoms
     log-uniform in [22, 5000], 1k-50k private hills each."""

@@ -4,7 +4,9 @@ the surrogate step against the exact hill sum.
 Parity of the network kernels (oracle on the same bf16-rounded weights,
 activations rounded as bf16 hi + lo pairs where the GPU feeds the matrix
 cores):
-  forward   V, dV/dxi   <= 2e-5 of the batch's largest |y|, |dy| (FP32 math)
+  forward   V, dV/dxi   <= 2e-5 of the batch's largest |y|, |dy| (FP32 math);
+            against the oracle with unrounded activations, per sample within
+            the first-order bound of the 2^-16 pair rounding plus that 2e-5
   reverse   loss <= 1e-5 relative; gradients <= 1e-4 of each parameter
             block's largest entry (FP32 per-workgroup partials)
   Adam      one and two steps against the update rule on the oracle's
@@ -102,6 +104,30 @@ def test_forward_matches_oracle(gpu, D):
     # bf16 rounding would be visibly further away
     y1, _, _ = mlp.forward(bf16_dict(P, H, D), xi, periodic, mu, sd, act_round=mlp.round_bf16)
     assert np.max(np.abs(3.0 + 1.7 * y1 - V.cpu().numpy())) > 5 * np.max(np.abs(V.cpu().numpy() - Vr))
+    # against the plain FP64 network (the same bf16 weights, activations not
+    # rounded): the pair hi + lo carries an activation a to |a - hi - lo| <=
+    # 2^-8 |a - hi| <= 2^-16 |a| (bf16 keeps 8 significant bits; a is first
+    # rounded to float32), so to first order the rounding moves
+    #   y    by <= u sum_i |w3_i| (1 - a2_i^2) sum_j |W2_ij| |a1_j|
+    #   dy_d by <= u sum_i |w3_i| [(1 - a2_i^2) sum_j |W2_ij| |da1_dj|
+    #                              + 2 |a2_i| |dz2_di| (1 - a2_i^2) sum_j |W2_ij| |a1_j|]
+    # with u = 2^-16 + 2^-24; the kernel's FP32 arithmetic adds the 2e-5 above
+    Pb = bf16_dict(P, H, D)
+    yp, dyp, c = mlp.forward(Pb, xi, periodic, mu, sd)
+    u = 2.0 ** -16 + 2.0 ** -24
+    W2a, w3a = np.abs(Pb["W2"]), np.abs(Pb["w3"])
+    s2 = 1.0 - c["a2"] ** 2
+    za = np.abs(c["a1"]) @ W2a.T
+    by = u * (s2 * za) @ w3a
+    errV = np.abs(V.cpu().numpy() - (3.0 + 1.7 * yp))
+    assert np.all(errV <= 1.7 * (1.01 * by + 2e-5 * np.max(np.abs(y)))), np.max(errV / (1.7 * by))
+    for d in range(D):
+        zd = np.abs(c["da1"][d]) @ W2a.T
+        bdy = u * (s2 * zd + 2.0 * np.abs(c["a2"]) * np.abs(c["dz2"][d]) * s2 * za) @ w3a
+        errd = np.abs(dV.cpu().numpy()[:, d] - 1.7 * dyp[:, d])
+        assert np.all(errd <= 1.7 * (1.01 * bdy + 2e-5 * np.max(np.abs(dy[:, d])))), (d, np.max(errd / (1.7 * bdy)))
+    print(f"D={D} H={H}: vs the unrounded network, largest error / derived bound: V "
+          f"{np.max(errV / (1.7 * by)):.2f}")
 
 
 @pytest.mark.parametrize("D", [2, 3])
