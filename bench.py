@@ -191,6 +191,33 @@ def graph_len(steps, cap):
     return 1
 
 
+def stream_probe(nbytes, reps=200):
+    """The plain streaming-read probe (non-temporal float4 loads, the hill
+    kernel's kind) over the same number of bytes, 2,048 workgroups: the
+    practical ceiling of a read-bound kernel of this size, in GB/s."""
+    import ctypes
+    import torch
+    from paper_2301_04835_amd import _lib
+
+    M = _lib.load_measure()
+    nb = nbytes // 16 * 16
+    src = torch.ones(nb // 4, device="cuda")
+    sink = torch.zeros(2048, device="cuda")
+    st = torch.cuda.current_stream()
+    call = lambda: M.sx_probe_read(ctypes.c_void_p(src.data_ptr()), nb, ctypes.c_void_p(sink.data_ptr()), 2048, 1,
+                                   ctypes.c_void_p(st.cuda_stream))
+    for _ in range(10):
+        call()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        call()
+    e1.record(st)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    return {"bytes": nb, "us": us, "achieved": nb / us / 1e3, "unit": "GB/s", "loads": "non-temporal float4"}
+
+
 def capacity_leg(d, p, tile, grid, reps, factor=4):
     """The 256-walker hill-sum kernel with each walker's capacity reserved at
     `factor` x its hill count (as a run that preallocates for the hills it
@@ -707,6 +734,8 @@ def main():
     # launches on the context's stream (same configuration as the step;
     # no deposition), tile kernel (A) and finalize kernel (B) separately
     ms_a, ms_b = s.time_hill(pos, forces=forces, reps=args.hill_reps)
+    # the two as a step runs them, and what a launch in a graph costs alone
+    ms_pair, ms_noop = s.time_hill_step(pos, forces=forces, reps=args.hill_reps)
     bytes_per_launch = counts_total * 12  # 2 float32 centres + 1 float32 height per hill
     achieved = bytes_per_launch / (ms_a * 1e-3) / 1e9
     traffic = measured_traffic(tile)
@@ -732,17 +761,21 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_hill_tiles%s<2,%d,fused,float>" % ("_persist" if grid else "", tile // 1024),
                      "kernel_ms": ms_a,
-                     "finalize_kernel_ms": ms_b, "bytes_per_launch": bytes_per_launch},
+                     "finalize_kernel_ms": ms_b, "pair_ms": ms_pair, "noop_launch_ms": ms_noop,
+                     "bytes_per_launch": bytes_per_launch},
     }
     if args.probe_copy_mb:
         import ctypes
+        from paper_2301_04835_amd import _lib
+        M = _lib.load_measure()
         nb = args.probe_copy_mb << 20
         src = torch.ones(nb // 4, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
-            s.L.sx_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nb, 2048,
-                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            M.sx_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nb, 2048,
+                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
+    out["stream_probe"] = stream_probe(bytes_per_launch)
     out["capacity_4x_count"] = capacity_leg(d, p, tile, grid, args.hill_reps)
     if not args.no_wtmd22:
         out["wtmd22"] = wtmd22_leg(args)

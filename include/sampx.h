@@ -203,6 +203,17 @@ sx_status sx_abf_momentum(sx_ctx *ctx, double dt, const double *masses, int64_t 
  * simulation temperature (ignored for plain metadynamics).  F_out (device,
  * n); not shifted.  Stream-ordered.  ESTATE: no metadynamics. */
 sx_status sx_fes_metad(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double temperature, double *F_out);
+/* The same free energy on an analysis grid, shifted to min 0 (Sec. 2.1.5):
+ * per CV d the nodes lo[d] + i (hi[d] - lo[d]) / nbins[d], i < nbins[d] for
+ * a periodic CV (the range wraps), i <= nbins[d] otherwise; row-major, the
+ * first CV slowest.  nodes (host, D; may be NULL) receives the node count
+ * per CV.  F_host NULL: only that size query.  Otherwise F_host (host,
+ * n_nodes = the product of the node counts) receives F - min F.  lo, hi,
+ * nbins: host, D.  Allocates temporary device memory for the nodes and
+ * synchronises the stream (an analysis call, not part of a step).  EINVAL:
+ * lo >= hi, nbins < 1, n_nodes not the node count. */
+sx_status sx_fes_metad_grid(sx_ctx *ctx, int32_t walker, const double *lo, const double *hi, const int32_t *nbins,
+                            double temperature, int32_t *nodes, double *F_host, int64_t n_nodes);
 /* Free energy A from `walker`'s ABF grid (Sec. 2.1.4) at the bin centres:
  * the mean forces g = Fsum / N of the visited bins integrated by least
  * squares over pairs of neighbouring visited bins along each CV,
@@ -384,8 +395,9 @@ sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
  * themselves (all-dihedral sets) are timed as in the step; with NULL the
  * CV values of the last step are used.  Nothing is deposited and no force
  * is written.  cache_path (may be NULL): a JSON file of earlier choices
- * keyed by the problem shape; read first, updated after a search.  Uses
- * hipEvents; synchronous. */
+ * keyed by the problem shape; read first, updated after a search.  Each
+ * candidate runs as a captured graph of 20 launches of the step's two
+ * kernels, timed with hipEvents (best of three replays); synchronous. */
 sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const char *cache_path);
 
 /* ------------------------------------------------- bias surrogate */
@@ -470,35 +482,6 @@ sx_status sx_surrogate_enable(sx_ctx *ctx, int32_t on);
 /* Walkers that took the exact fallback in the last surrogate step (host
  * int32; synchronous). */
 sx_status sx_surrogate_fallback_count(sx_ctx *ctx, int32_t *count);
-
-/* ------------------------------------------------- measurement probes */
-/* Average duration of the step's two hill-sum kernels: `reps` back-to-back
- * launches of the tile kernel, then `reps` of the finalize kernel, bracketed
- * by hipEvents on the context's stream, with the step's configuration (CVs
- * from pos as sx_step evaluates them; tiling as tuned).  Nothing is
- * deposited and the step counter is untouched; if forces (device, layout of
- * pos) is not NULL the bias force is added to it `reps` times.
- * Synchronous.  ms_tiles / ms_finalize: host, milliseconds per launch. */
-sx_status sx_time_hill(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
-                       float *ms_tiles, float *ms_finalize);
-/* Average duration of the cell-list kernels on the bound state, `reps`
- * launches each, bracketed by hipEvents on the context's stream: the cell
- * sort, the pair pass (CV values and the members' gradients, with its
- * finalize), and the vector-Jacobian gather adding -dV/dxi (of the last
- * step) times those gradients to forces (device, layout of pos; may be
- * NULL: not timed).  Positions as sx_step receives them.  Synchronous.
- * ms_sort / ms_pairs / ms_vjp: host, ms per launch. */
-sx_status sx_time_cell(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
-                       float *ms_sort, float *ms_pairs, float *ms_vjp);
-
-/* Plain streaming read of `bytes` (multiple of 16) from device memory src
- * with `grid` workgroups; each workgroup writes one float to sink[grid]
- * (device).  Enqueued on `stream` (hipStream_t).  Used to calibrate the
- * traffic counters and to measure the achievable read rate. */
-sx_status sx_probe_read(const void *src, size_t bytes, float *sink, int32_t grid, void *stream);
-/* Plain copy of `bytes` (multiple of 16) from src to dst (device, not
- * overlapping) with `grid` workgroups, enqueued on `stream`. */
-sx_status sx_probe_copy(void *dst, const void *src, size_t bytes, int32_t grid, void *stream);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,9 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsampx.so")
+MEASURE_LIB_PATH = os.path.join(HERE, "libsampx_measure.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sampx.h")
+MEASURE_HEADER = os.path.join(os.path.dirname(HERE), "include", "sampx_measure.h")
 
 SX_OK, SX_EINVAL, SX_ENOMEM, SX_ECAPACITY, SX_ENONFINITE, SX_EDEVICE, SX_ESTATE = range(7)
 SX_F32, SX_F64 = 0, 1
@@ -62,10 +64,10 @@ SIGNATURES = {
     "sx_set_tuning": (i32, [P, i32, i32]),
     "sx_get_tuning": (i32, [P, P, P]),
     "sx_autotune": (i32, [P, P, i32, i32, ctypes.c_char_p]),
-    "sx_time_hill": (i32, [P, P, i32, i32, P, i32, P, P]),
     "sx_metad_grid": (i32, [P, P, P, P]),
     "sx_harmonic_config": (i32, [P, P, P, i32]),
     "sx_fes_metad": (i32, [P, i32, P, ctypes.c_int64, f64, P]),
+    "sx_fes_metad_grid": (i32, [P, i32, P, P, P, f64, P, P, i64]),
     "sx_abf_fes": (i32, [P, i32, P]),
     "sx_abf_momentum": (i32, [P, f64, P, ctypes.c_int64]),
     "sx_funn_fit": (i32, [P, i32, i32, i32, f64, f64, P, P]),
@@ -76,9 +78,6 @@ SIGNATURES = {
     "sx_grid_nodes": (ctypes.c_int64, [P]),
     "sx_grid_eval": (i32, [P, i32, P, ctypes.c_int64, P, P]),
     "sx_grid_get": (i32, [P, i32, P, P, ctypes.c_int64]),
-    "sx_time_cell": (i32, [P, P, i32, i32, P, i32, P, P, P]),
-    "sx_probe_read": (i32, [P, sz, P, i32, P]),
-    "sx_probe_copy": (i32, [P, P, sz, i32, P]),
     "sx_set_cell_lists": (i32, [P, i32]),
     "sx_cell_list_cvs": (i32, [P]),
     "sx_surrogate_config": (i32, [P, i32, i64, i32, i32, f64]),
@@ -98,14 +97,49 @@ SIGNATURES = {
     "sx_surrogate_fallback_count": (i32, [P, P]),
 }
 
+# the measurement library (include/sampx_measure.h): hooks exported by
+# libsampx.so, timing and probes in libsampx_measure.so
+MEASURE_HOOKS = {
+    "sxm_stream": (P, [P]),
+    "sxm_enqueue_hill": (i32, [P, P, P, i32, i32, P, i32]),
+    "sxm_enqueue_cell": (i32, [P, P, P, i32, i32, P, i32]),
+}
+MEASURE_SIGNATURES = {
+    "sx_time_hill": (i32, [P, P, i32, i32, P, i32, P, P]),
+    "sx_time_cell": (i32, [P, P, i32, i32, P, i32, P, P, P]),
+    "sx_time_hill_step": (i32, [P, P, i32, i32, P, i32, P, P]),
+    "sx_probe_noop": (i32, [P]),
+    "sx_probe_read": (i32, [P, sz, P, i32, i32, P]),
+    "sx_probe_copy": (i32, [P, P, sz, i32, P]),
+}
+
 _lib = None
+_mlib = None
+
+
+def load_measure(path=MEASURE_LIB_PATH):
+    """Load libsampx_measure.so (after libsampx.so, which it links) and
+    attach the signatures of the timing and probe calls."""
+    global _mlib
+    if _mlib is not None:
+        return _mlib
+    load()
+    if not os.path.exists(path):
+        raise RuntimeError("libsampx_measure.so not built at %s: run paper_2301_04835_amd/build.py" % path)
+    M = ctypes.CDLL(path)
+    for name, (res, args) in MEASURE_SIGNATURES.items():
+        fn = getattr(M, name)
+        fn.restype = res
+        fn.argtypes = args
+    _mlib = M
+    return M
 
 
 def header_symbols(path=HEADER):
     """Names of the functions include/sampx.h declares."""
     text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sx_[A-Za-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sxm?_[A-Za-z0-9_]+)\s*\(", text)))
 
 
 def load(path=LIB_PATH):

@@ -174,16 +174,18 @@ class Sampler:
         """Free energy of the metadynamics bias at the nodes of an analysis
         grid (per CV nbins nodes over a periodic range, nbins + 1 up to hi
         otherwise; row-major), shifted to min 0; host array of the grid's
-        shape.  See sx_fes_metad."""
-        periodic = self._periodic()
-        axes = [np.linspace(l, h, n, endpoint=False) if p else np.linspace(l, h, n + 1)
-                for l, h, n, p in zip(lo, hi, nbins, periodic)]
-        mesh = np.meshgrid(*axes, indexing="ij")
-        X = torch.from_numpy(np.stack([m.reshape(-1) for m in mesh], 1)).to(self.device)
-        F = torch.empty(X.shape[0], dtype=torch.float64, device=self.device)
-        self._check(self.L.sx_fes_metad(self.h, int(walker), _ptr(X), X.shape[0], float(temperature), _ptr(F)))
-        F = F.cpu().numpy()
-        return (F - F.min()).reshape([len(a) for a in axes])
+        shape.  See sx_fes_metad_grid."""
+        D = self.D
+        l, pl = _host(lo, np.float64)
+        h, ph = _host(hi, np.float64)
+        nb, pn = _host(nbins, np.int32)
+        nodes = np.zeros(D, dtype=np.int32)
+        pnodes = nodes.ctypes.data_as(ctypes.c_void_p)
+        self._check(self.L.sx_fes_metad_grid(self.h, int(walker), pl, ph, pn, float(temperature), pnodes, None, 0))
+        F = np.empty(int(np.prod(nodes)), dtype=np.float64)
+        self._check(self.L.sx_fes_metad_grid(self.h, int(walker), pl, ph, pn, float(temperature), pnodes,
+                                             F.ctypes.data_as(ctypes.c_void_p), F.size))
+        return F.reshape([int(k) for k in nodes])
 
     def abf_fes(self, walker=0):
         """Free energy at the ABF bin centres (see sx_abf_fes): host array of
@@ -470,17 +472,31 @@ class Sampler:
         return t.value, g.value
 
     def time_cell(self, pos, forces=None, reps=20, layout="aos3"):
-        """ms per launch of the cell sort, the pair pass and the VJP gather."""
+        """ms per launch of the cell sort, the pair pass and the VJP gather
+        (graph-replayed launches; the measurement library's sx_time_cell)."""
         a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
-        self._check(self.L.sx_time_cell(self.h, _ptr(pos), _pos_dtype(pos), _LAYOUTS[layout], _ptr(forces), int(reps),
-                                        ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        M = _lib.load_measure()
+        self._check(M.sx_time_cell(self.h, _ptr(pos), _pos_dtype(pos), _LAYOUTS[layout], _ptr(forces), int(reps),
+                                   ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
     def time_hill(self, pos, forces=None, reps=100, layout="aos3"):
-        """(ms per tile-kernel launch, ms per finalize-kernel launch) measured
-        with hipEvents on the context's stream (see sx_time_hill)."""
+        """(ms per tile-kernel launch, ms per finalize-kernel launch): `reps`
+        launches of each captured in a graph and replayed between hipEvents
+        on the context's stream (the measurement library's sx_time_hill)."""
         m1, m2 = ctypes.c_float(), ctypes.c_float()
-        self._check(self.L.sx_time_hill(self.h, _ptr(pos), _pos_dtype(pos), _LAYOUTS[layout], _ptr(forces), int(reps),
+        M = _lib.load_measure()
+        self._check(M.sx_time_hill(self.h, _ptr(pos), _pos_dtype(pos), _LAYOUTS[layout], _ptr(forces), int(reps),
+                                   ctypes.byref(m1), ctypes.byref(m2)))
+        return m1.value, m2.value
+
+    def time_hill_step(self, pos, forces=None, reps=100, layout="aos3"):
+        """(ms per (tile kernel, finalize kernel) pair in a graph, ms per
+        launch of a graph of empty one-workgroup kernels): see
+        sx_time_hill_step."""
+        m1, m2 = ctypes.c_float(), ctypes.c_float()
+        M = _lib.load_measure()
+        self._check(M.sx_time_hill_step(self.h, _ptr(pos), _pos_dtype(pos), _LAYOUTS[layout], _ptr(forces), int(reps),
                                         ctypes.byref(m1), ctypes.byref(m2)))
         return m1.value, m2.value
 

@@ -104,4 +104,31 @@ __device__ __forceinline__ void switch_fn(float r2, const CvDesc &c, float &s, f
     f = r > 0.f ? dsdx * c.inv_r0 / r : 0.f;
 }
 
+// The same switch in FP64 (IEEE division and square root), for the pair
+// terms of a Jacobian kept in FP64.
+__device__ __forceinline__ void switch_fn(double r2, const CvDesc &c, double &s, double &f)
+{
+    const double ir = c.inv_r0d;
+    if (c.n == 6 && c.m == 12) {
+        const double x2 = r2 * (ir * ir), x4 = x2 * x2;
+        const double sv = 1.0 / (1.0 + x4 * x2);
+        s = sv;
+        f = -6.0 * x4 * sv * sv * (ir * ir);
+        return;
+    }
+    const double r = sqrt(r2), x = r * ir;
+    double pn = 0.0, dpn = 0.0, pm = 0.0, dpm = 0.0;
+    for (int i = c.n - 1; i >= 0; --i) {
+        dpn = fma(dpn, x, pn);
+        pn = fma(pn, x, 1.0);
+    }
+    for (int i = c.m - 1; i >= 0; --i) {
+        dpm = fma(dpm, x, pm);
+        pm = fma(pm, x, 1.0);
+    }
+    s = pn / pm;
+    const double dsdx = (dpn * pm - pn * dpm) / (pm * pm);
+    f = r > 0.0 ? dsdx * ir / r : 0.0;
+}
+
 }  // namespace sx

@@ -8,8 +8,8 @@
 //      walker's current hill count leaves at once, so the work follows the
 //      hills deposited so far, not the space reserved for them.  Hills are
 //      stored SoA in float32 (centres c[d][k], heights h[k]); every lane
-//      issues its float4 loads of a batch of 4 groups before using any of
-//      them (clamped to the group of the walker's last hill and masked by
+//      issues its non-temporal float4 loads of a batch of 4 groups before
+//      using any of them (clamped to the group of the walker's last hill and masked by
 //      its count, so no branch sits between the loads), which keeps enough
 //      bytes in flight to stream HBM.
 //      When every CV is a dihedral the tile's workgroup computes its
@@ -49,6 +49,16 @@ __device__ __forceinline__ float hill_term(const double (&xi)[D], const float (&
         q = fmaf(dl[d] * a.a2[d], dl[d], q);
     }
     return h * __builtin_amdgcn_exp2f(-q);
+}
+
+// Streaming load of one float4 group of a hill list: non-temporal, so the
+// list (read once per step, far larger than the L2) does not displace the
+// small tables, records and positions that the step's kernels reuse.
+typedef float nt_f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_stream(const float4 *p)
+{
+    const nt_f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f32x4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
 }
 
 __device__ __forceinline__ float comp(const float4 &v, int i)
@@ -194,8 +204,8 @@ __device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, co
             for (int q = 0; q < UB; ++q) {
                 const uint32_t qi = min(q0 + (uint32_t)((ub + q) * kBlock), qlast);
 #pragma unroll
-                for (int d = 0; d < D; ++d) cv[q][d] = cb[d][qi];
-                hv[q] = hp[qi];
+                for (int d = 0; d < D; ++d) cv[q][d] = ld_stream(&cb[d][qi]);
+                hv[q] = ld_stream(&hp[qi]);
             }
             __builtin_amdgcn_sched_barrier(0);
             if (ub == 0) {

@@ -14,6 +14,8 @@
 // the kinds overlap on the device instead of following one another.
 #include "dev_cv.h"
 
+#include <type_traits>
+
 namespace sx {
 namespace {
 
@@ -136,8 +138,9 @@ __device__ __forceinline__ double3 ld_d3(const PosView &p, int64_t i)
     return make_double3((double)q[0], (double)q[p.sk], (double)q[2 * p.sk]);
 }
 
-// minimum-image component in FP64, rounded once to float
+// minimum-image component in FP64, rounded once to float (or kept in FP64)
 __device__ __forceinline__ float min_img(double d, double L, double iL) { return (float)fma(-L, rint(d * iL), d); }
+__device__ __forceinline__ double min_img_d(double d, double L, double iL) { return fma(-L, rint(d * iL), d); }
 
 // grid: x = block of kBlock / L members of one side, y = side (0: A gathers
 // over B, 1: B gathers over A), z = walker * ncoord + k (k-th coordination
@@ -146,7 +149,8 @@ __device__ __forceinline__ float min_img(double d, double L, double iL) { return
 // ... of each round.  The pair difference and its minimum image are taken in
 // FP64 (exact for float inputs up to the final rounding), the switching
 // function in FP32, its sums in FP32 over each eight of a lane's partners and
-// in FP64 beyond; the member's lanes combine in a fixed butterfly and the
+// in FP64 beyond (for a Jacobian kept in FP64, JT = double, every pair term
+// is FP64); the member's lanes combine in a fixed butterfly and the
 // first writes the Jacobian slot.  On the A side the members' switch sums are
 // reduced per workgroup (fixed tree) into one value record per block, which
 // k_coord_value sums in order.
@@ -182,6 +186,24 @@ __device__ __forceinline__ void coord_block(const CvSet &cs, const WalkerTabs &t
         }
         __syncthreads();
         if (!live) continue;
+        if (std::is_same<JT, double>::value) {  // FP64 pair terms: ABF's Gram matrix and J.F
+            for (int j = l; j < jn; j += L) {
+                const Partner o = oth[j];
+                const double dx = min_img_d(ri.x - o.x, Lb[0], iL[0]);
+                const double dy = min_img_d(ri.y - o.y, Lb[1], iL[1]);
+                const double dz = min_img_d(ri.z - o.z, Lb[2], iL[2]);
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                const bool use = (o.idx != me) && (cv.rcut <= 0.0 || r2 < cv.rcut * cv.rcut);
+                double sv, f;
+                switch_fn(r2, cv, sv, f);
+                S += use ? sv : 0.0;
+                f = use ? f : 0.0;
+                gx = fma(f, dx, gx);
+                gy = fma(f, dy, gy);
+                gz = fma(f, dz, gz);
+            }
+            continue;
+        }
         for (int j = l; j < jn; j += 8 * L) {
             float s8 = 0.f, x8 = 0.f, y8 = 0.f, z8 = 0.f;
 #pragma unroll

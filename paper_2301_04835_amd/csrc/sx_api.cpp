@@ -391,6 +391,8 @@ sx_status make_plan(sx_ctx *c)
             ds.m = cv.m;
             ds.r0 = (float)cv.r0;
             ds.inv_r0 = (float)(1.0 / cv.r0);
+            ds.inv_r0d = 1.0 / cv.r0;
+            ds.rcut = cv.rcut;
             ds.rcut2 = cv.rcut > 0 ? (float)(cv.rcut * cv.rcut) : 0.f;
             ds.scale = cv.normalize ? (float)(1.0 / cv.a.size()) : 1.f;
             // lanes per member: 64, halved while the pair grid would still
@@ -2229,6 +2231,57 @@ sx_status sx_fes_metad(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n,
     return SX_OK;
 }
 
+sx_status sx_fes_metad_grid(sx_ctx *ctx, int32_t walker, const double *lo, const double *hi, const int32_t *nbins,
+                            double temperature, int32_t *nodes, double *F_host, int64_t n_nodes)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
+    const int D = ctx->plan.D;
+    if (!lo || !hi || !nbins) return fail(ctx, SX_EINVAL, "lo, hi and nbins are needed");
+    // analysis nodes per CV: a periodic CV's nbins nodes lo + i delta wrap,
+    // a non-periodic one has nbins + 1 up to hi
+    int32_t nn[kMaxBiasDim] = {1, 1, 1};
+    int64_t n = 1;
+    for (int d = 0; d < D; ++d) {
+        if (!(hi[d] > lo[d]) || nbins[d] < 1) return fail(ctx, SX_EINVAL, "need lo < hi and nbins >= 1 per CV");
+        nn[d] = nbins[d] + (cv_periodic(ctx->cvs[d]) ? 0 : 1);
+        n *= nn[d];
+        if (nodes) nodes[d] = nn[d];
+    }
+    if (!F_host) return SX_OK;  // size query
+    if (n_nodes != n) return fail(ctx, SX_EINVAL, "F_host must hold " + std::to_string(n) + " values");
+    std::vector<double> X((size_t)n * D);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t r = i;
+        for (int d = D - 1; d >= 0; --d) {  // row-major, the first CV slowest
+            const int64_t k = r % nn[d];
+            r /= nn[d];
+            X[(size_t)i * D + d] = lo[d] + (double)k * (hi[d] - lo[d]) / nbins[d];
+        }
+    }
+    // temporary device copies of the nodes and values: an analysis call,
+    // synchronous, off the step path
+    double *dx = nullptr, *dF = nullptr;
+    hipError_t e = hipMalloc(&dx, sizeof(double) * X.size());
+    if (e == hipSuccess) e = hipMalloc(&dF, sizeof(double) * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dx, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, ctx->stream);
+    sx_status st = e == hipSuccess ? sx_fes_metad(ctx, walker, dx, n, temperature, dF) : hip_fail(ctx, e, "analysis buffers");
+    if (st == SX_OK) {
+        e = hipMemcpyAsync(F_host, dF, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = hip_fail(ctx, e, "analysis copy");
+    }
+    if (dx) (void)hipFree(dx);  // release; a failure here cannot change the result
+    if (dF) (void)hipFree(dF);
+    if (st != SX_OK) return st;
+    double fmin = std::numeric_limits<double>::infinity();
+    for (int64_t i = 0; i < n; ++i) fmin = std::min(fmin, F_host[i]);
+    for (int64_t i = 0; i < n; ++i) F_host[i] -= fmin;
+    return SX_OK;
+    SX_GUARD_END
+}
+
 sx_status sx_abf_fes(sx_ctx *ctx, int32_t walker, double *A)
 {
     if (sx_status s = require_bound(ctx)) return s;
@@ -2512,6 +2565,12 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
     const int gmul[] = {0, 2, 4, 8};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ctx, SX_EDEVICE, "events");
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(ctx, SX_EDEVICE, "capture stream");
+    }
     float best = 1e30f;
     int bt = 4096, bg = 0;
     double *xi = at<double>(ctx->ws, p.w_xi);
@@ -2522,26 +2581,39 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
             const int g = gm ? gm * ncu : 0;
             if (g && g >= ctx->ntiles) continue;
             // the step's hill kernels without side effects: no deposit, no
-            // step count, no forces; CVs fused exactly as in sx_step
+            // step count, no forces; CVs fused exactly as in sx_step.  20
+            // launches of the pair are captured in a graph and replayed (as
+            // a step runs), so host launch cost stays out of the timing
             HillArgs a = hill_args(ctx, xi);
             a.fuse = fuse;
             a.xi_save = xi;  // fused kernels rewrite the same CV values here
             a.deposit = 0;
             a.count_step = 0;
             a.do_forces = 0;
-            hipError_t e = hipSuccess;
-            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_hill_private(a, p.cs, pv, g, ctx->stream);
+            const int reps = 20;
+            hipGraph_t gr = nullptr;
+            hipGraphExec_t gx = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+            hipError_t el = hipSuccess;
+            if (e == hipSuccess) {
+                for (int r = 0; r < reps && el == hipSuccess; ++r) el = launch_hill_private(a, p.cs, pv, g, cap);
+                e = hipStreamEndCapture(cap, &gr);
+                if (e == hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipGraphLaunch(gx, ctx->stream);  // warm
             float ms = 1e30f;
-            for (int round = 0; round < 3 && e == hipSuccess; ++round) {  // best of three rounds
+            for (int round = 0; round < 3 && e == hipSuccess; ++round) {  // best of three replays
                 e = hipEventRecord(e0, ctx->stream);
-                const int reps = 20;
-                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_hill_private(a, p.cs, pv, g, ctx->stream);
+                if (e == hipSuccess) e = hipGraphLaunch(gx, ctx->stream);
                 if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float m = 0;
                 if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
                 ms = std::min(ms, m);
             }
+            if (gx) (void)hipGraphExecDestroy(gx);  // teardown: the timing is already taken or failed
+            if (gr) (void)hipGraphDestroy(gr);
             if (e != hipSuccess) st = hip_fail(ctx, e, "autotune timing");
             // a persistent grid must win by 2% over one workgroup per tile
             const float handicap = g ? 1.02f : 1.0f;
@@ -2555,6 +2627,7 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(cap);
     if (st != SX_OK) return st;
     if (sx_status s = sx_set_tuning(ctx, bt, bg)) return s;
     if (cache_path) {
@@ -2571,81 +2644,65 @@ sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layou
     SX_GUARD_END
 }
 
-sx_status sx_time_cell(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
-                       float *ms_sort, float *ms_pairs, float *ms_vjp)
+// ----------------------------------------------------- measurement hooks
+// Kernel-level enqueue primitives for the measurement library
+// (libsampx_measure: graph-captured timing of single kernels); declared in
+// include/sampx_measure.h, not part of the biasing-path boundary.
+void *sxm_stream(const sx_ctx *ctx) { return ctx ? ctx->stream : nullptr; }
+
+sx_status sxm_enqueue_hill(sx_ctx *ctx, void *stream, const void *pos, int32_t dtype, int32_t layout, float *forces,
+                           int32_t which)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (ctx->method != M_METAD || ctx->shared || ctx->mg_on)
+        return fail(ctx, SX_ESTATE, "no private hill lists summed by tiles on this context");
+    if (which < 0 || which > 2) return fail(ctx, SX_EINVAL, "which: 0 prepare, 1 tile kernel, 2 finalize kernel");
+    const Plan &p = ctx->plan;
+    PosView pv;
+    if (!pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
+    hipStream_t saved = ctx->stream;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    const bool fuse = p.all_dihedral;
+    double *xi = at<double>(ctx->ws, p.w_xi);
+    sx_status st = SX_OK;
+    if (which == 0 && !fuse) st = launch_cvs(ctx, pv, xi, at<float>(ctx->ws, p.w_J));
+    if (st == SX_OK) {
+        HillArgs a = hill_args(ctx, xi);
+        a.fuse = fuse;
+        a.xi_save = xi;
+        a.deposit = 0;
+        a.count_step = 0;
+        a.do_forces = forces != nullptr;
+        a.F = force_view(ctx, forces, layout);
+        hipError_t e = launch_hill_private(a, p.cs, pv, ctx->grid, ctx->stream, which == 2 ? 2 : 1);
+        if (e != hipSuccess) st = hip_fail(ctx, e, "hill kernels");
+    }
+    ctx->stream = saved;
+    return st;
+    SX_GUARD_END
+}
+
+sx_status sxm_enqueue_cell(sx_ctx *ctx, void *stream, const void *pos, int32_t dtype, int32_t layout, float *forces,
+                           int32_t which)
 {
     if (sx_status s = require_bound(ctx)) return s;
     SX_GUARD_BEGIN
     const Plan &p = ctx->plan;
     if (!p.cell.ncn) return fail(ctx, SX_ESTATE, "no cell-list coordination numbers in this plan");
+    if (which < 0 || which > 3) return fail(ctx, SX_EINVAL, "which: 0 prepare, 1 sort, 2 pair pass, 3 VJP gather");
+    if (which == 3 && !forces) return fail(ctx, SX_EINVAL, "the VJP gather needs a force buffer");
     PosView pv;
     if (!pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
-    if (reps < 1 || !ms_sort || !ms_pairs || !ms_vjp) return fail(ctx, SX_EINVAL, "reps must be >= 1, outputs non-NULL");
     const CellArgs ca = cell_args(ctx);
     double *xi = at<double>(ctx->ws, p.w_xi), *coef = at<double>(ctx->ws, p.w_dV);
-    hipEvent_t e[4];
-    for (auto &x : e)
-        if (hipEventCreate(&x) != hipSuccess) return fail(ctx, SX_EDEVICE, "events");
-    hipError_t err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream);  // warm
-    if (err == hipSuccess) err = hipEventRecord(e[0], ctx->stream);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream, 1);
-    if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_cell_cv(ca, p.cs, pv, xi, ctx->stream, 2);
-    if (err == hipSuccess) err = hipEventRecord(e[2], ctx->stream);
-    for (int r = 0; r < reps && err == hipSuccess && forces; ++r)
-        err = launch_cell_vjp(ca, p.cs, pv, coef, -1.0, force_view(ctx, forces, layout), ctx->stream);
-    if (err == hipSuccess) err = hipEventRecord(e[3], ctx->stream);
-    if (err == hipSuccess) err = hipEventSynchronize(e[3]);
-    float t[3] = {0, 0, 0};
-    for (int k = 0; k < 3 && err == hipSuccess; ++k) err = hipEventElapsedTime(&t[k], e[k], e[k + 1]);
-    for (auto &x : e) (void)hipEventDestroy(x);
-    if (err != hipSuccess) return hip_fail(ctx, err, "cell timing");
-    *ms_sort = t[0] / reps;
-    *ms_pairs = t[1] / reps;
-    *ms_vjp = forces ? t[2] / reps : 0.f;
-    return SX_OK;
-    SX_GUARD_END
-}
-
-sx_status sx_time_hill(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
-                       float *ms_tiles, float *ms_finalize)
-{
-    if (sx_status s = require_bound(ctx)) return s;
-    SX_GUARD_BEGIN
-    if (ctx->method != M_METAD || ctx->shared) return fail(ctx, SX_ESTATE, "no private hill lists on this context");
-    if (reps < 1 || !ms_tiles || !ms_finalize) return fail(ctx, SX_EINVAL, "reps >= 1 and both outputs needed");
-    const Plan &p = ctx->plan;
-    PosView pv;
-    if (!pos_view(ctx, pos, dtype, layout, pv)) return fail(ctx, SX_EINVAL, "bad positions, dtype or layout");
-    const bool fuse = p.all_dihedral;
-    double *xi = at<double>(ctx->ws, p.w_xi);
-    if (!fuse) {
-        if (sx_status st = launch_cvs(ctx, pv, xi, at<float>(ctx->ws, p.w_J))) return st;
-    }
-    HillArgs a = hill_args(ctx, xi);
-    a.fuse = fuse;
-    a.xi_save = xi;
-    a.deposit = 0;
-    a.count_step = 0;
-    a.do_forces = forces != nullptr;
-    a.F = force_view(ctx, forces, layout);
-    hipEvent_t e[3];
-    for (auto &ev : e)
-        if (hipEventCreate(&ev) != hipSuccess) return fail(ctx, SX_EDEVICE, "events");
-    hipError_t err = launch_hill_private(a, p.cs, pv, ctx->grid, ctx->stream, 1);  // warm: J and xi for kernel B
-    if (err == hipSuccess) err = hipEventRecord(e[0], ctx->stream);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_hill_private(a, p.cs, pv, ctx->grid, ctx->stream, 1);
-    if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_hill_private(a, p.cs, pv, ctx->grid, ctx->stream, 2);
-    if (err == hipSuccess) err = hipEventRecord(e[2], ctx->stream);
-    if (err == hipSuccess) err = hipEventSynchronize(e[2]);
-    float m1 = 0, m2 = 0;
-    if (err == hipSuccess) err = hipEventElapsedTime(&m1, e[0], e[1]);
-    if (err == hipSuccess) err = hipEventElapsedTime(&m2, e[1], e[2]);
-    for (auto &ev : e) (void)hipEventDestroy(ev);
-    if (err != hipSuccess) return hip_fail(ctx, err, "hill kernel timing");
-    *ms_tiles = m1 / reps;
-    *ms_finalize = m2 / reps;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (which == 0) e = launch_cell_cv(ca, p.cs, pv, xi, s);
+    if (which == 1) e = launch_cell_cv(ca, p.cs, pv, xi, s, 1);
+    if (which == 2) e = launch_cell_cv(ca, p.cs, pv, xi, s, 2);
+    if (which == 3) e = launch_cell_vjp(ca, p.cs, pv, coef, -1.0, force_view(ctx, forces, layout), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cell-list kernels");
     return SX_OK;
     SX_GUARD_END
 }

@@ -51,6 +51,7 @@ struct CvDesc {
     int32_t ga, gb;   // cell-list coordination: the two atom groups
     int32_t cn;       // cell-list coordination: index among those CVs
     double rcut;      // the cut (FP64), for decisions at its edge
+    double inv_r0d;   // 1 / r0 in FP64 (the FP64 pair terms of ABF's Jacobian)
 };
 
 struct CvSet {

@@ -15,6 +15,31 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / den) if den > 0 else float(np.max(np.abs(a - b)))
 
 
+def hill_v_rel_bound(xi, C, H, sigma, period, base=1e-6):
+    """Relative error bound of a float32 hill sum V = sum_k h_k g_k at xi.
+    The kernel rounds each wrapped displacement to float32 (relative u =
+    2^-24) and forms the exponent in float32, so a term with exponent
+    q_k = sum_d D_kd^2 / (2 sigma_d^2) carries a relative error of about
+    6 u q_k, i.e. 3 u sum_d D_kd^2 / sigma_d^2; V's terms are all positive,
+    so V's relative error is their e-weighted mean, plus `base` for the
+    exponential, the products and the sums.  Near hills dominate V in a
+    converged bias and this stays ~1e-7; a walker whose only hills are far
+    away (D ~ pi at sigma 0.3) sees a few 1e-6."""
+    xi = np.asarray(xi, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64).reshape(-1, len(xi))
+    H = np.asarray(H, dtype=np.float64)
+    if len(H) == 0:
+        return base
+    dl = xi[None, :] - C
+    for d, p in enumerate(period):
+        if p > 0:
+            dl[:, d] -= p * np.rint(dl[:, d] / p)
+    r = np.sum(dl ** 2 / np.asarray(sigma, dtype=np.float64) ** 2, axis=1)
+    e = H * np.exp(-0.5 * r)
+    V = np.sum(e)
+    return base + (3.0 * 2.0 ** -24 * np.sum(e * r) / V if V > 0 else 0.0)
+
+
 def dense_jac(J_slots, atom, cv, n_atoms, D):
     """Sum sparse Jacobian slots (n_slots x 3) into a dense D x n_atoms x 3."""
     out = np.zeros((D, n_atoms, 3))

@@ -34,6 +34,19 @@ def test_library_exports_every_declared_symbol(lib):
     assert not missing
 
 
+def test_measurement_library_exports_its_header(lib):
+    """include/sampx_measure.h: the sxm_* hooks come from libsampx.so, the
+    timing and probe calls from libsampx_measure.so; the binding knows each."""
+    names = _lib.header_symbols(_lib.MEASURE_HEADER)
+    names = [n for n in names if n not in _lib.header_symbols()]
+    assert set(names) == set(_lib.MEASURE_HOOKS) | set(_lib.MEASURE_SIGNATURES)
+    assert all(hasattr(lib, n) for n in _lib.MEASURE_HOOKS)
+    M = _lib.load_measure()
+    assert all(hasattr(M, n) for n in _lib.MEASURE_SIGNATURES)
+    # the measurement calls are not part of the biasing-path boundary
+    assert not set(_lib.MEASURE_SIGNATURES) & set(_lib.header_symbols())
+
+
 def test_status_strings_and_null_handling(lib):
     assert lib.sx_status_string(0) == b"ok"
     assert lib.sx_status_string(3) == b"hill capacity exceeded"

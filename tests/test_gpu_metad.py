@@ -18,7 +18,7 @@ import oracle
 from paper_2301_04835_amd import synth
 from paper_2301_04835_amd.api import SxError
 
-from gpu_util import TWO_PI, dense_jac, dev, make_metad, rel_inf
+from gpu_util import TWO_PI, dense_jac, dev, hill_v_rel_bound, make_metad, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -171,7 +171,9 @@ def test_growing_lists_capacity_8x_count(gpu, tile, grid):
     deposits one hill per walker (stride 1), counts start just below tile
     boundaries so live tiles appear during the run, and the tiles past the
     count leave at once.  Per step and walker: xi, V, dV/dxi and forces
-    against the oracle replaying the same deposits (float32 storage)."""
+    against the oracle replaying the same deposits (float32 storage); V within
+    the bound its float32 terms allow (hill_v_rel_bound: 1e-6 when near
+    hills dominate, more for a walker whose few hills are all far away)."""
     counts = [0, 1, 1020, 2045, 4093, 700]
     caps = [8 * max(c, 64) for c in counts]
     W, T = len(counts), 12
@@ -185,7 +187,7 @@ def test_growing_lists_capacity_8x_count(gpu, tile, grid):
     frames = [(pos0 + g.normal(0, 0.01, size=pos0.shape)).astype(np.float32) for _ in range(T)]
     Cr = [c.astype(np.float64).tolist() for c, _ in hills]
     Hr = [h.astype(np.float64).tolist() for _, h in hills]
-    worst = {"V": 0.0, "dV": 0.0, "F": 0.0}
+    worst = {"V": 0.0, "V/bound": 0.0, "dV": 0.0, "F": 0.0}
     for t in range(T):
         P = dev(frames[t])
         F = torch.zeros_like(P)
@@ -201,14 +203,17 @@ def test_growing_lists_capacity_8x_count(gpu, tile, grid):
             if len(Hr[w]) == 0:
                 assert Vh[w] == 0.0 and np.all(dVh[w] == 0.0) and np.all(Fh[off[w]:off[w + 1]] == 0.0)
             else:
-                worst["V"] = max(worst["V"], abs(Vh[w] - o["V"]) / abs(o["V"]))
+                eV = abs(Vh[w] - o["V"]) / abs(o["V"])
+                bV = hill_v_rel_bound(o["xi"], Cr[w], Hr[w], sig, [TWO_PI, TWO_PI])
+                worst["V"] = max(worst["V"], eV)
+                worst["V/bound"] = max(worst["V/bound"], eV / bV)
                 worst["dV"] = max(worst["dV"], rel_inf(dVh[w], o["dV"]))
                 worst["F"] = max(worst["F"], rel_inf(Fh[off[w]:off[w + 1]], o["F"]))
             Cr[w].append(np.float32(o["deposit"][0]).astype(np.float64).tolist())
             Hr[w].append(float(np.float32(o["deposit"][1])))
     s.check()
     print("worst errors:", worst)
-    assert worst["V"] <= 1e-6 and worst["dV"] <= 1e-5 and worst["F"] <= 1e-5
+    assert worst["V/bound"] <= 1.0 and worst["dV"] <= 1e-5 and worst["F"] <= 1e-5
     for w in range(W):
         c, h = s.hills_get(w)
         assert c.shape[0] == counts[w] + T
