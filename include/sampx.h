@@ -355,6 +355,18 @@ sx_status sx_deposit(sx_ctx *ctx, const double *xi);
  * step's sum; evaluated in batches of 65536 points.  Used for surrogate
  * training labels and certification. */
 sx_status sx_bias_eval(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double *V_out, double *dVdxi_out);
+/* sx_bias_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same kernels and results, with their partial sums in a fixed 16 MiB array
+ * inside the library (one per GPU, held until the process ends; its address
+ * is looked up in sx_create) instead of the bound workspace.  Allocates
+ * nothing and calls no allocating routine.  The caller passes xi, V_out and
+ * dVdxi_out (device) as for sx_bias_eval.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (two streams, two contexts) race.
+ * ENOMEM when a batch's partial sums would exceed the array (not reached by
+ * the 65536-point batches: at most 8 chunks x 65536 points x 32 B). */
+sx_status sx_bias_eval_noalloc(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double *V_out,
+                               double *dVdxi_out);
 
 /* ------------------------------------------------------------ state I/O */
 /* Host copies, synchronous.  Walker -1 (or any walker) addresses the shared

@@ -52,6 +52,7 @@ SIGNATURES = {
     "sx_hillsum": (i32, [P, P, P, P]),
     "sx_deposit": (i32, [P, P]),
     "sx_bias_eval": (i32, [P, i32, P, i64, P, P]),
+    "sx_bias_eval_noalloc": (i32, [P, i32, P, i64, P, P]),
     "sx_hills_set": (i32, [P, i32, P, P, i64]),
     "sx_hills_get": (i32, [P, i32, P, P, i64, P]),
     "sx_abf_grid_get": (i32, [P, i32, P, P]),

@@ -301,6 +301,12 @@ class Sampler:
         self._check(self.L.sx_bias_eval(self.h, int(walker), _ptr(xi.contiguous()), n, _ptr(V), _ptr(dV)))
         return V, dV
 
+    def bias_eval_noalloc(self, xi, V, dV=None, walker=0):
+        """bias_eval into caller-given outputs V (n) and dV (n x D, or None),
+        through the entry point that allocates nothing (its partial sums in
+        the library's fixed scratch)."""
+        self._check(self.L.sx_bias_eval_noalloc(self.h, int(walker), _ptr(xi), xi.shape[0], _ptr(V), _ptr(dV)))
+
     def grid_eval(self, xi, walker=0, grad=True):
         """The bias grid's read-back (multilinear interpolation) at points xi
         (n x D, device float64)."""

@@ -1097,6 +1097,9 @@ sx_status sx_create(sx_ctx **out, int device, void *stream)
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SX_EDEVICE;
+    // the no-allocation entry point's fixed scratch: its address on this
+    // device, looked up once per device
+    if (noalloc_setup(device) != hipSuccess) return SX_EDEVICE;
     sx_ctx *c = new (std::nothrow) sx_ctx;
     if (!c) return SX_ENOMEM;
     c->device = device;
@@ -1748,6 +1751,35 @@ sx_status sx_bias_eval(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n,
     for (int64_t i0 = 0; i0 < n; i0 += kEvalBatch) {
         const int64_t m = std::min<int64_t>(kEvalBatch, n - i0);
         SharedArgs a = shared_args(ctx, wl, xi + i0 * D, m);
+        a.V_out = V_out ? V_out + i0 : nullptr;
+        a.dV_out = dVdxi_out ? dVdxi_out + i0 * D : nullptr;
+        hipError_t e = launch_hill_shared(a, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "bias evaluation kernels");
+    }
+    return SX_OK;
+    SX_GUARD_END
+}
+
+sx_status sx_bias_eval_noalloc(sx_ctx *ctx, int32_t walker, const double *xi, int64_t n, double *V_out,
+                               double *dVdxi_out)
+{
+    if (sx_status s = require_bound(ctx)) return s;
+    SX_GUARD_BEGIN
+    if (ctx->method != M_METAD) return fail(ctx, SX_ESTATE, "no metadynamics bias on this context");
+    const int wl = walker_list(ctx, walker);
+    if (wl < 0 || wl >= ctx->plan.W) return fail(ctx, SX_EINVAL, "walker out of range");
+    if (n < 0 || (n > 0 && !xi)) return fail(ctx, SX_EINVAL, "bad query points");
+    double *scr = noalloc_scratch(ctx->device);
+    if (!scr) return fail(ctx, SX_EDEVICE, "the fixed scratch has no address on this device");
+    const int64_t max_records = (int64_t)(noalloc_scratch_bytes() / (4 * sizeof(double)));
+    const int D = ctx->plan.D;
+    for (int64_t i0 = 0; i0 < n; i0 += kEvalBatch) {
+        const int64_t m = std::min<int64_t>(kEvalBatch, n - i0);
+        SharedArgs a = shared_args(ctx, wl, xi + i0 * D, m);
+        if ((int64_t)a.nchunk * m > max_records)
+            return fail(ctx, SX_ENOMEM, "partial sums of " + std::to_string((int64_t)a.nchunk * m) +
+                                            " records exceed the fixed scratch of " + std::to_string(max_records));
+        a.partial = scr;  // every (chunk, query) record has one writer: nothing to clear
         a.V_out = V_out ? V_out + i0 : nullptr;
         a.dV_out = dVdxi_out ? dVdxi_out + i0 * D : nullptr;
         hipError_t e = launch_hill_shared(a, ctx->stream);

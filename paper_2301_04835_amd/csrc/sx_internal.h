@@ -418,4 +418,11 @@ hipError_t launch_gather(const WalkerTabs &t, const float *J, int32_t nslots, in
 hipError_t launch_copy_xi(const double *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_zero_bytes(void *p, int64_t nbytes, hipStream_t s);
 
+// The fixed device scratch of the no-allocation entry point: its size, the
+// once-per-device look-up of its address (with that device made current for
+// the call), and that address (null before the look-up).
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_setup(int device);
+double *noalloc_scratch(int device);
+
 }  // namespace sx
