@@ -15,9 +15,11 @@
 //               against W2 in bf16, FP32 accumulation, so 2 (1 + D) products
 //               share every W2 fragment.  y and dy/dxi are reduced across
 //               the 16 output lanes of each sample with shuffles.
-//   k_mlp_bwd   (VALU, training): reverse mode over the forward and its
-//               tangents for a Sobolev loss on (V, dV/dxi); 16 samples per
-//               workgroup in LDS; per-workgroup parameter gradients.
+//   k_mlp_bwd   (training): reverse mode over the forward and its tangents
+//               for a Sobolev loss on (V, dV/dxi); 16 samples per workgroup
+//               (8 at H = 128) in LDS; the two H x H products (back through
+//               W2, and the W2 gradient) on the matrix cores with bf16-pair
+//               operands, the rest on VALU; per-workgroup gradients.
 //   k_mlp_adam  sums the workgroup gradients in order (FP64) and applies
 //               Adam (Kingma & Ba 2015) to the FP32 master weights, then
 //               refreshes their bf16 copies.
@@ -362,6 +364,31 @@ __host__ __device__ constexpr int bwd_samples()
     return H >= 128 ? 8 : 16;
 }
 
+// the bf16 pair (hi, lo) of eight consecutive FP32 values, the form in
+// which an FP32 operand enters the bf16 matrix product
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8 &hi, bf16x8 &lo)
+{
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const __bf16 h = (__bf16)v[t];
+        hi[t] = h;
+        lo[t] = (__bf16)(v[t] - (float)h);
+    }
+}
+
+// The reverse pass: per workgroup S samples, their value row and D tangent
+// rows stacked (row c S + sl: c = 0 the value, c = d + 1 tangent d; rows
+// padded with zeros to a multiple of 32).  The two H x H products run on
+// the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation), every
+// FP32 operand entering as a bf16 pair:
+//   a1b rows  = z2b rows . W2        (M = rows, K = H, N = H; W2 exact bf16,
+//                                     staged transposed in LDS)
+//   dL/dW2    = z2b rows^T . act rows (M = H, K = rows, N = H; act = the
+//                                     forward's bf16-pair activations a1r,
+//                                     da1r_d; hi.hi + hi.lo + lo.hi)
+// the rest (features, tanh derivatives, the small layers, the loss) on the
+// vector units in FP32.  Every gradient entry has one owning lane (no
+// atomics); the workgroup's partial gradient and loss go to gpart[blockIdx].
 template <int H, int D>
 __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi, const double *Vl, const double *Gl,
                                                      int64_t n, float inv_b, float alpha, float beta,
@@ -370,17 +397,23 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
 {
     constexpr int F = 2 * D;
     constexpr int S = bwd_samples<H>();
+    constexpr int R = (1 + D) * S;          // stacked rows
+    constexpr int MP = (R + 31) / 32 * 32;  // rows padded to the product depth
+    constexpr int HP = H + 4;               // LDS row stride (floats): strided column reads spread over banks
+    constexpr int HT = H + 8;               // row stride of the transposed W2 (bf16)
     constexpr POff o = poff(H, F);
     __shared__ float s_f[S][F], s_u[S][D][F];
     __shared__ float s_yb[S], s_dyb[S][D];
-    __shared__ float s_z2b[S][H], s_dz2b[D][S][H];
-    __shared__ float s_a1r[S][H], s_da1r[D][S][H];
-    __shared__ float s_x[S][H], s_dx[D][S][H];  // a2, da2 (phase 1); then z1b, dz1b (phase 2)
+    __shared__ float s_zx[MP][HP];  // z2b, dz2b_d
+    __shared__ float s_ac[MP][HP];  // a1r, da1r_d (the forward's matrix-core inputs)
+    __shared__ float s_x[MP][HP];   // a2, da2_d (phase 1); a1b, da1b_d (phase 2b); z1b, dz1b_d (phase 2c)
+    __shared__ __bf16 s_w2t[H][HT];  // s_w2t[k][j] = W2[j][k]
     __shared__ float s_loss[kBlock / 64];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t b0 = (int64_t)blockIdx.x * S;
-    float* gp = gpart + (int64_t)blockIdx.x * (o.P + 1);
-    // phase 0: features and the loss adjoints of y and dy
+    float *gp = gpart + (int64_t)blockIdx.x * (o.P + 1);
+    // phase 0: features and the loss adjoints of y and dy; W2 staged
+    // transposed; padding rows zeroed
     float lossp = 0.f;
     if (tid < S) {
         const int64_t s = b0 + tid;
@@ -408,6 +441,15 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
             lossp += beta * r1 * r1;
         }
     }
+    for (int e = tid; e < H * H; e += kBlock) {
+        const int j = e / H, k = e % H;
+        s_w2t[k][j] = reinterpret_cast<const __bf16 *>(a.Pb)[o.W2 + e];
+    }
+    for (int e = tid; e < (MP - R) * H; e += kBlock) {
+        const int m = R + e / H, k = e % H;
+        s_zx[m][k] = 0.f;
+        s_ac[m][k] = 0.f;
+    }
     __syncthreads();
     // phase 1 (sample sl, output unit j): y = w3.a2 + b3, dy_d = w3.da2_d,
     // da2_d = (1 - a2^2) dz2_d  ->  adjoints of z2 and of the tangents dz2_d
@@ -424,10 +466,10 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
             const float dz2 = live ? t_dz2[((int64_t)d * a.nmax + s) * H + j] : 0.f;
             const float da2b = s_dyb[sl][d] * w3;
             a2b += da2b * (-2.f * a2 * dz2);
-            s_dz2b[d][sl][j] = da2b * g2;
-            s_dx[d][sl][j] = g2 * dz2;  // da2_d
+            s_zx[(d + 1) * S + sl][j] = da2b * g2;
+            s_x[(d + 1) * S + sl][j] = g2 * dz2;  // da2_d
         }
-        s_z2b[sl][j] = a2b * g2;
+        s_zx[sl][j] = a2b * g2;
         s_x[sl][j] = a2;
     }
     __syncthreads();
@@ -435,10 +477,10 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
     for (int j = tid; j < H; j += kBlock) {
         float gb2 = 0.f, gw3 = 0.f;
         for (int sl = 0; sl < S; ++sl) {
-            gb2 += s_z2b[sl][j];
+            gb2 += s_zx[sl][j];
             gw3 += s_yb[sl] * s_x[sl][j];
 #pragma unroll
-            for (int d = 0; d < D; ++d) gw3 += s_dyb[sl][d] * s_dx[d][sl][j];
+            for (int d = 0; d < D; ++d) gw3 += s_dyb[sl][d] * s_x[(d + 1) * S + sl][j];
         }
         gp[o.b2 + j] = gb2;
         gp[o.w3 + j] = gw3;
@@ -448,9 +490,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
         for (int sl = 0; sl < S; ++sl) gb3 += s_yb[sl];
         gp[o.b3] = gb3;
     }
-    __syncthreads();
-    // phase 2 (sample sl, input unit k): through W2 (a1b = z2b W2, tangents
-    // alike) and layer 1 (recomputed); keeps a1r, da1r for the W2 gradient
+    // phase 2a (sample sl, input unit k): layer 1 recomputed, the forward's
+    // matrix-core inputs a1r and da1r_d kept
     for (int idx = tid; idx < S * H; idx += kBlock) {
         const int sl = idx / H, k = idx % H;
         float z = bf(a.Pb, o.b1 + k), dz1[D];
@@ -464,38 +505,88 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
             for (int d = 0; d < D; ++d) dz1[d] = fmaf(w, s_u[sl][d][q], dz1[d]);
         }
         const float a1 = tanh_fast(z), g1 = 1.f - a1 * a1;
-        s_a1r[sl][k] = round_bf2(a1);
-        float a1b = 0.f, da1b[D];
+        s_ac[sl][k] = round_bf2(a1);
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            s_da1r[d][sl][k] = round_bf2(g1 * dz1[d]);
-            da1b[d] = 0.f;
+        for (int d = 0; d < D; ++d) s_ac[(d + 1) * S + sl][k] = round_bf2(g1 * dz1[d]);
+    }
+    __syncthreads();  // phase 1b has read s_x; s_zx and s_w2t complete
+    // phase 2b (matrix cores): s_x rows = s_zx rows . W2, 16 x 16 tiles dealt
+    // to the four wavefronts
+    {
+        const int r16 = lane & 15, kg = lane >> 4;
+        for (int t = wave; t < (MP / 16) * (H / 16); t += kBlock / 64) {
+            const int mt = t / (H / 16), nt = t % (H / 16);
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < H / 32; ++kb) {
+                const int j0 = kb * 32 + kg * 8;
+                float v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = s_zx[mt * 16 + r16][j0 + q];
+                bf16x8 hi, lo;
+                split8(v, hi, lo);
+                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(&s_w2t[nt * 16 + r16][j0]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, bw, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, bw, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_x[mt * 16 + kg * 4 + i][nt * 16 + r16] = acc[i];
         }
-        for (int j = 0; j < H; ++j) {
-            const float w = bf(a.Pb, o.W2 + j * H + k);
-            a1b = fmaf(s_z2b[sl][j], w, a1b);
-#pragma unroll
-            for (int d = 0; d < D; ++d) da1b[d] = fmaf(s_dz2b[d][sl][j], w, da1b[d]);
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d) a1b += da1b[d] * (-2.f * a1 * dz1[d]);
-        // (phase 1b is done with a2 / da2: their buffers now hold z1b / dz1b)
-        s_x[sl][k] = a1b * g1;
-#pragma unroll
-        for (int d = 0; d < D; ++d) s_dx[d][sl][k] = da1b[d] * g1;
     }
     __syncthreads();
-    // phase 3: W2 gradient (H*H entries), W1 and b1 gradients (lane-owned)
-    for (int e = tid; e < H * H; e += kBlock) {
-        const int j = e / H, k = e % H;
-        float g = 0.f;
-        for (int sl = 0; sl < S; ++sl) {
-            g = fmaf(s_z2b[sl][j], s_a1r[sl][k], g);
+    // phase 2c (sample sl, input unit k): through tanh of layer 1:
+    // a1b = a1b' + sum_d da1b_d (-2 a1 dz1_d), z1b = a1b g1, dz1b_d = da1b_d g1
+    for (int idx = tid; idx < S * H; idx += kBlock) {
+        const int sl = idx / H, k = idx % H;
+        float z = bf(a.Pb, o.b1 + k), dz1[D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) g = fmaf(s_dz2b[d][sl][j], s_da1r[d][sl][k], g);
+        for (int d = 0; d < D; ++d) dz1[d] = 0.f;
+#pragma unroll
+        for (int q = 0; q < F; ++q) {
+            const float w = bf(a.Pb, o.W1 + k * F + q);
+            z = fmaf(w, s_f[sl][q], z);
+#pragma unroll
+            for (int d = 0; d < D; ++d) dz1[d] = fmaf(w, s_u[sl][d][q], dz1[d]);
         }
-        gp[o.W2 + e] = g;
+        const float a1 = tanh_fast(z), g1 = 1.f - a1 * a1;
+        float a1b = s_x[sl][k];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const float da1b = s_x[(d + 1) * S + sl][k];
+            a1b += da1b * (-2.f * a1 * dz1[d]);
+            s_x[(d + 1) * S + sl][k] = da1b * g1;
+        }
+        s_x[sl][k] = a1b * g1;
     }
+    // phase 3a (matrix cores): dL/dW2[j][k] = sum over rows m of
+    // s_zx[m][j] s_ac[m][k]; 16 x 16 tiles of (j, k) dealt to the wavefronts
+    {
+        const int r16 = lane & 15, kg = lane >> 4;
+        for (int t = wave; t < (H / 16) * (H / 16); t += kBlock / 64) {
+            const int jt = t / (H / 16), kt = t % (H / 16);
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < MP / 32; ++kb) {
+                const int m0 = kb * 32 + kg * 8;
+                float va[8], vb[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    va[q] = s_zx[m0 + q][jt * 16 + r16];
+                    vb[q] = s_ac[m0 + q][kt * 16 + r16];
+                }
+                bf16x8 ah, al, bh, bl;
+                split8(va, ah, al);
+                split8(vb, bh, bl);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gp[o.W2 + (jt * 16 + kg * 4 + i) * H + kt * 16 + r16] = acc[i];
+        }
+    }
+    __syncthreads();  // phase 2c's z1b, dz1b complete
+    // phase 3b: W1 and b1 gradients (lane-owned)
     for (int e = tid; e < H * (F + 1); e += kBlock) {
         const int k = e / (F + 1), q = e % (F + 1);
         float g = 0.f;
@@ -505,7 +596,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_bwd(MlpArgs a, const double *xi,
             } else {
                 g = fmaf(s_x[sl][k], s_f[sl][q], g);
 #pragma unroll
-                for (int d = 0; d < D; ++d) g = fmaf(s_dx[d][sl][k], s_u[sl][d][q], g);
+                for (int d = 0; d < D; ++d) g = fmaf(s_x[(d + 1) * S + sl][k], s_u[sl][d][q], g);
             }
         }
         if (q == F)
