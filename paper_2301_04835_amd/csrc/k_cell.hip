@@ -25,11 +25,13 @@
 //                  one lane per member (groups identical or disjoint: one
 //                  writer per atom).
 
-// In x and y cells have edge >= the cutoff and there are >= 3 of them; in z
-// there are rz sub-cells per such cell (>= 3 rz in all), so the 3 x 3 x
-// (2 rz + 1) neighbour cells of a cell are distinct and hold exactly the one
+// Cut-length cells (edge >= the cutoff, >= 3 per dimension) are cut into rxy
+// sub-cells in x and y and rz in z, so the (2 rxy + 1)^2 (2 rz + 1)
+// neighbour sub-cells of a sub-cell are distinct and hold exactly the one
 // image of every partner within the cutoff.  The sub-cells shrink the
-// partners a home atom visits from 27 cut-length cubes to 9 (2 rz + 1) / rz.
+// partners a home atom visits from 27 cut-length cubes to
+// ((2 rxy + 1) / rxy)^2 (2 rz + 1) / rz: 14.1 at rxy = 2, rz = 4 (5.8 cut
+// spheres' worth of volume down to 3.4).
 #include "sx_internal.h"
 #include "dev_cv.h"
 
@@ -74,11 +76,12 @@ __global__ void __launch_bounds__(kBuildBlock) k_cell_build(CellArgs c, PosView 
         atomicAdd(&s_off[cell], 1);  // counts only: the placement below is ordered
     }
     __syncthreads();
-    // exclusive scan of the counts: 4 cells per thread, then across threads
-    int32_t loc[4], sum = 0;
+    // exclusive scan of the counts: kScanPer cells per thread, then across threads
+    constexpr int kScanPer = kCellTotal / kBuildBlock;
+    int32_t loc[kScanPer], sum = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int cc = tid * 4 + q;
+    for (int q = 0; q < kScanPer; ++q) {
+        const int cc = tid * kScanPer + q;
         loc[q] = cc < c.ncell ? s_off[cc] : 0;
         sum += loc[q];
     }
@@ -92,8 +95,8 @@ __global__ void __launch_bounds__(kBuildBlock) k_cell_build(CellArgs c, PosView 
     }
     int32_t run = s_tot[tid] - sum;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int cc = tid * 4 + q;
+    for (int q = 0; q < kScanPer; ++q) {
+        const int cc = tid * kScanPer + q;
         if (cc < c.ncell) {
             s_off[cc] = run;
             cst[cc] = run;
@@ -173,10 +176,11 @@ __device__ __forceinline__ const CvDesc &cell_cv(const CvSet &cs, int k)
 }
 
 // Stage the members of group gp in the region of column block (cx, cy, z0):
-// the 3 x 3 x (czb + 2 rz) cells around it, slice by slice (z offset -rz ..
-// czb + rz - 1), each slice in (x, y) order, so that the neighbour cells of
-// the block's k-th home cell (z offsets -rz .. rz around it) are the
-// contiguous range s_seg[9 k] .. s_seg[9 (k + 2 rz + 1)].  Positions
+// the n x n x (czb + 2 rz) sub-cells around it (n = 2 rxy + 1), slice by
+// slice (z offset -rz .. czb + rz - 1), each slice in (x, y) order, so that
+// the neighbour sub-cells of the block's k-th home sub-cell (z offsets
+// -rz .. rz around it) are the contiguous range s_seg[n^2 k] ..
+// s_seg[n^2 (k + 2 rz + 1)].  Positions
 // relative to the origin of cell (cx, cy, z0), times sc; entries
 // [r0, r0 + kColStage) of the region, followed by kStride atoms far outside
 // any cut (index -1), so a lane reading four partners kLpa apart from any
@@ -185,50 +189,83 @@ constexpr int kJacBlock = 256;
 constexpr int kLpa = 8;                     // lanes per home atom
 constexpr int kApp = kJacBlock / kLpa;      // home atoms per pass
 constexpr int kStride = 4 * kLpa;           // partners per lane step
-constexpr int kColStage = 1280;             // partner atoms staged per round (20 KB)
-constexpr int kRegMax = 9 * (kCzMax + 2 * kZReach);
+constexpr int kColStage = 1536;             // partner atoms staged per round (24 KB)
+constexpr int kRegMax = (2 * kXYReach + 1) * (2 * kXYReach + 1) * (kCzMax + 2 * kZReach);
+
+constexpr int kRegPer = (kRegMax + kJacBlock - 1) / kJacBlock;  // region sub-cells per thread
 
 __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, int cx, int cy, int z0, int czb, int r0,
-                                            float sc, float4 *s_p, int32_t *s_seg, int32_t *s_first, float *s_sh)
+                                            float sc, float4 *s_p, int32_t *s_seg, int32_t *s_first, int32_t *s_wsum)
 {
     const int32_t *cst = c.cstart + ((int64_t)w * c.G + gp) * (c.ncell + 1);
     const float4 *srt = c.sorted + (int64_t)w * c.gtotal + c.goff[gp];
-    const int nreg = 9 * (czb + 2 * c.rz);
-    for (int t = threadIdx.x; t < nreg; t += blockDim.x) {
-        const int sl = t / 9, xy = t % 9;
-        const int ox = xy / 3 - 1, oy = xy % 3 - 1, oz = sl - c.rz;
+    const int side = 2 * c.rxy + 1, nxy = side * side;
+    const int nreg = nxy * (czb + 2 * c.rz);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // thread tid owns region sub-cells [tid kRegPer, (tid + 1) kRegPer): their
+    // first sorted member to s_first and, until the scan below, their member
+    // count to s_seg (one at a time: few registers live)
+    int loc = 0;
+#pragma unroll 1
+    for (int q = 0; q < kRegPer; ++q) {
+        const int t = tid * kRegPer + q;
+        if (t >= nreg) break;
+        const int sl = t / nxy, xy = t % nxy;
+        const int ox = xy / side - c.rxy, oy = xy % side - c.rxy, oz = sl - c.rz;
         const int nx = (cx + ox + c.nc[0]) % c.nc[0], ny = (cy + oy + c.nc[1]) % c.nc[1];
         const int nz = (z0 + oz + c.nc[2]) % c.nc[2];
         const int nb = (nx * c.nc[1] + ny) * c.nc[2] + nz;
-        s_first[t] = cst[nb];
-        s_seg[t + 1] = cst[nb + 1] - cst[nb];
-        s_sh[3 * t] = (float)(ox * c.clen[0]);
-        s_sh[3 * t + 1] = (float)(oy * c.clen[1]);
-        s_sh[3 * t + 2] = (float)(oz * c.clen[2]);
+        const int f = cst[nb], n = cst[nb + 1] - f;
+        s_first[t] = f;
+        s_seg[t] = n;
+        loc += n;
     }
-    if (threadIdx.x == 0) s_seg[0] = 0;
+    // exclusive scan of the counts over the workgroup: inclusive scan inside
+    // each wavefront, then the wavefronts' totals in order
+    int x = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wsum[wave] = x;
     __syncthreads();
-    if (threadIdx.x == 0)
-        for (int t = 1; t <= nreg; ++t) s_seg[t] += s_seg[t - 1];
+    int base = x - loc, total = 0;
+#pragma unroll
+    for (int wv = 0; wv < kJacBlock / 64; ++wv) {
+        const int ws = s_wsum[wv];
+        base += wv < wave ? ws : 0;
+        total += ws;
+    }
+#pragma unroll 1
+    for (int q = 0; q < kRegPer; ++q) {
+        const int t = tid * kRegPer + q;
+        if (t >= nreg) break;
+        const int n = s_seg[t];  // this thread's own count
+        s_seg[t] = base;
+        base += n;
+    }
+    if (tid == 0) s_seg[nreg] = total;
     __syncthreads();
-    const int m = min(kColStage, s_seg[nreg] - r0);
-    const int mp = m + kStride;  // s_p holds kColStage + kStride entries
-    for (int j = threadIdx.x; j < mp; j += blockDim.x) {
-        float4 v = make_float4(1e6f, 1e6f, 1e6f, __int_as_float(-1));
-        if (j < m) {
-            const int e = r0 + j;
-            int lo = 0, hi = nreg - 1;  // the cell t with s_seg[t] <= e < s_seg[t + 1]
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_seg[mid] <= e) lo = mid; else hi = mid - 1;
-            }
-            v = srt[s_first[lo] + (e - s_seg[lo])];
-            v.x = (v.x + s_sh[3 * lo]) * sc;
-            v.y = (v.y + s_sh[3 * lo + 1]) * sc;
-            v.z = (v.z + s_sh[3 * lo + 2]) * sc;
+    // the window [r0, r0 + m) of the region, sub-cell by sub-cell: each
+    // member shifted by its sub-cell's offset from the block origin
+    const int m = min(kColStage, total - r0);
+    for (int t = tid; t < nreg; t += blockDim.x) {
+        const int sg = s_seg[t];
+        const int e0 = max(sg, r0), e1 = min(s_seg[t + 1], r0 + m);
+        if (e0 >= e1) continue;
+        const int f = s_first[t];
+        const int sl = t / nxy, xy = t % nxy;
+        const int ox = xy / side - c.rxy, oy = xy % side - c.rxy, oz = sl - c.rz;
+        const float shx = (float)(ox * c.clen[0]), shy = (float)(oy * c.clen[1]), shz = (float)(oz * c.clen[2]);
+        for (int e = e0; e < e1; ++e) {
+            float4 v = srt[f + (e - sg)];
+            v.x = (v.x + shx) * sc;
+            v.y = (v.y + shy) * sc;
+            v.z = (v.z + shz) * sc;
+            s_p[e - r0] = v;
         }
-        s_p[j] = v;
     }
+    for (int j = m + tid; j < m + kStride; j += blockDim.x) s_p[j] = make_float4(1e6f, 1e6f, 1e6f, __int_as_float(-1));
     __syncthreads();
     return m;
 }
@@ -297,12 +334,11 @@ __device__ __forceinline__ void pair4(const float4 *s_p, int j, int b1, float3 o
     }
 }
 
-template <bool S612>
+template <bool S612, int RXY>
 __global__ void __launch_bounds__(kJacBlock, 5) k_cell_jac(CellArgs c, CvSet cs, PosView pos)
 {
     __shared__ float4 s_p[kColStage + kStride];
-    __shared__ int32_t s_seg[kRegMax + 1], s_first[kRegMax];
-    __shared__ float s_sh[3 * kRegMax];
+    __shared__ int32_t s_seg[kRegMax + 1], s_first[kRegMax], s_wsum[kJacBlock / 64];
     __shared__ double s_red[kJacBlock / 64];
     __shared__ int32_t s_home[kCzMax + 1];  // sorted position of the block's home cells
     const int blk = blockIdx.x, g = blockIdx.y, w = blockIdx.z;
@@ -317,7 +353,8 @@ __global__ void __launch_bounds__(kJacBlock, 5) k_cell_jac(CellArgs c, CvSet cs,
     __syncthreads();
     const int a0 = s_home[0], a1 = s_home[czb];
     const int64_t aoff = c.atom_off[w];
-    const int nreg = 9 * (czb + 2 * c.rz), span = 9 * (2 * c.rz + 1);
+    constexpr int nxy = (2 * RXY + 1) * (2 * RXY + 1);  // RXY = c.rxy
+    const int nreg = nxy * (czb + 2 * c.rz), span = nxy * (2 * c.rz + 1);
     for (int u = 0; u < c.ninv[g]; ++u) {
         const CvDesc &cv = cs.cv[c.inv_cv[g][u]];
         const bool sideA = c.inv_side[g][u] == 0;
@@ -328,15 +365,18 @@ __global__ void __launch_bounds__(kJacBlock, 5) k_cell_jac(CellArgs c, CvSet cs,
         const float rc2 = cv.rcut2 * sc * sc, bandc = 1e-5f * rc2, gsc = S612 ? -6.0f * cv.inv_r0 : 1.0f;
         double ssum = 0.0;  // this lane's switch sums (A side), over its home atoms
         for (int r0 = 0;; r0 += kColStage) {
-            const int m = stage_column(c, w, c.inv_p[g][u], cx, cy, z0, czb, r0, sc, s_p, s_seg, s_first, s_sh);
+            const int m = stage_column(c, w, c.inv_p[g][u], cx, cy, z0, czb, r0, sc, s_p, s_seg, s_first, s_wsum);
             for (int h0 = a0; h0 + (64 / kLpa) * wave < a1; h0 += kApp) {  // uniform per wavefront
                 const int i = h0 + tid / kLpa;
                 const bool live = i < a1;
                 const float4 pi = sg[live ? i : a0];
-                int k = 0;  // this atom's home cell within the block
-                while (k + 1 < czb && i >= s_home[k + 1]) ++k;
+                int k = 0;  // this atom's home cell within the block: the last k with s_home[k] <= i
+                for (int hi = czb - 1; k < hi;) {
+                    const int mid = (k + hi + 1) >> 1;
+                    if (s_home[mid] <= i) k = mid; else hi = mid - 1;
+                }
                 // this atom's partners in the staged window
-                const int b0 = max(0, s_seg[9 * k] - r0), b1 = live ? min(m, s_seg[9 * k + span] - r0) : 0;
+                const int b0 = max(0, s_seg[nxy * k] - r0), b1 = live ? min(m, s_seg[nxy * k + span] - r0) : 0;
                 // home atoms are stored relative to their own cell: the k-th
                 // cell of the block sits k cell edges above the block origin
                 const float3 o = make_float3(pi.x * sc, pi.y * sc, (pi.z + (float)(k * c.clen[2])) * sc);
@@ -452,10 +492,15 @@ hipError_t launch_cell_cv(const CellArgs &c, const CvSet &cs, const PosView &pos
     for (int d = 0; d < cs.ncv; ++d)
         if (cs.cv[d].kind == CV_COORD_CELL) all612 = all612 && cs.cv[d].n == 6 && cs.cv[d].m == 12;
     const dim3 grid(c.nblk, c.G, c.W);
-    if (all612)
-        hipLaunchKernelGGL(k_cell_jac<true>, grid, dim3(kJacBlock), 0, s, c, cs, pos);
+    if (c.rxy != 1 && c.rxy != 2) return hipErrorInvalidValue;
+    if (all612 && c.rxy == 2)
+        hipLaunchKernelGGL((k_cell_jac<true, 2>), grid, dim3(kJacBlock), 0, s, c, cs, pos);
+    else if (all612)
+        hipLaunchKernelGGL((k_cell_jac<true, 1>), grid, dim3(kJacBlock), 0, s, c, cs, pos);
+    else if (c.rxy == 2)
+        hipLaunchKernelGGL((k_cell_jac<false, 2>), grid, dim3(kJacBlock), 0, s, c, cs, pos);
     else
-        hipLaunchKernelGGL(k_cell_jac<false>, grid, dim3(kJacBlock), 0, s, c, cs, pos);
+        hipLaunchKernelGGL((k_cell_jac<false, 1>), grid, dim3(kJacBlock), 0, s, c, cs, pos);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cn_cell_fin, dim3(c.ncn, c.W), dim3(kBlock), 0, s, c, cs, xi);

@@ -40,6 +40,26 @@ def hill_v_rel_bound(xi, C, H, sigma, period, base=1e-6):
     return base + (3.0 * 2.0 ** -24 * np.sum(e * r) / V if V > 0 else 0.0)
 
 
+def hill_grad_bound(xi, C, H, sigma, period, hess, xi_tol, rel=1e-5):
+    """Per-CV bound on |dV/dxi_gpu - dV/dxi_ref| for a hill sum whose
+    gradient cancels: rel times the larger of max |dV/dxi| and the term scale
+    S_d = sum_k h_k g_k |D_kd| / sigma_d^2 (the survey's force bound for
+    cancelling sums), plus what the CV tolerance xi_tol (per CV) moves the
+    gradient through the bias's Hessian `hess` (D x D)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64).reshape(-1, len(xi))
+    H = np.asarray(H, dtype=np.float64)
+    sig2 = np.asarray(sigma, dtype=np.float64) ** 2
+    dl = xi[None, :] - C
+    for d, p in enumerate(period):
+        if p > 0:
+            dl[:, d] -= p * np.rint(dl[:, d] / p)
+    e = H * np.exp(-0.5 * np.sum(dl ** 2 / sig2, axis=1))
+    S = np.sum(e[:, None] * np.abs(dl), axis=0) / sig2
+    g = -np.sum(e[:, None] * dl, axis=0) / sig2
+    return rel * np.maximum(np.max(np.abs(g)), S) + np.abs(np.asarray(hess)) @ np.asarray(xi_tol, dtype=np.float64)
+
+
 def dense_jac(J_slots, atom, cv, n_atoms, D):
     """Sum sparse Jacobian slots (n_slots x 3) into a dense D x n_atoms x 3."""
     out = np.zeros((D, n_atoms, 3))

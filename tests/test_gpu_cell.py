@@ -78,6 +78,27 @@ def test_cell_values_and_vjp_against_oracle(gpu, self_cn):
         assert rel_inf(pb[off[w]:off[w + 1]], ref) <= 1e-5
 
 
+def test_cell_values_dense_groups_several_staging_rounds(gpu):
+    """Groups of 2,000 in a 4 nm box (31 atoms per nm^3): a column block's
+    partner region holds ~3,300 members, more than one LDS staging round
+    (1,536), so the pair pass restages and adds later rounds to the earlier
+    ones; values and VJP against the brute-force oracle."""
+    W, n, L = 2, 2000, 4.0
+    pos, off, cvs = small_system(W, n, L, 22)
+    s = ctx(cvs, L, off, 1)
+    assert s.cell_list_cvs() == 3
+    P = dev(pos)
+    xi = s.eval_cv(P)[0].cpu().numpy()
+    xb = np.random.default_rng(4).normal(size=(W, 3))
+    pb = torch.zeros_like(P)
+    s.cv_vjp(P, dev(xb), pb)
+    pb = pb.cpu().numpy()
+    for w in range(W):
+        xr, J = oracle_walker(pos[off[w]:off[w + 1]], cvs, L)
+        assert np.max(np.abs(xi[w] - xr) / np.abs(xr)) <= 1e-6
+        assert rel_inf(pb[off[w]:off[w + 1]], np.tensordot(xb[w], J, axes=1)) <= 1e-5
+
+
 def test_cell_mode_rules(gpu):
     W, n, L = 2, 300, 4.0
     pos, off, cvs = small_system(W, n, L, 5)
@@ -153,6 +174,76 @@ def test_cn3_full_size_sampled(gpu):
     pbw = pb.cpu().numpy()
     assert rel_inf(pbw[off[w]:off[w + 1]], np.tensordot(xb[w], J, axes=1)) <= 1e-5
     assert np.all(pbw[:off[w]] == 0) and np.all(pbw[off[w + 1]:] == 0)
+
+
+def test_cn3_full_size_step_sampled_walkers(gpu):
+    """The full-size step: 512 walkers of 60,000 atoms, three cell-list CNs
+    over 20,000-atom groups, one shared list of 10^6 three-dimensional hills
+    (sigma 0.2, centres around the expected CN), the forces as the VJP of
+    dV/dxi, as the benchmark runs it.  Eight walkers spread over the batch
+    against the oracle (brute force over all pairs for xi and J, the FP64
+    hill sum over the 10^6 hills at the oracle's xi): xi 1e-6, V within its
+    float32-term bound; dV/dxi and the forces within their derived bounds:
+    the walkers sit inside the hill cloud, where dV/dxi is a small remainder
+    of large terms of both signs and the bias is steep, so the bound is 1e-5
+    of the term scale (the survey's bound for cancelling sums) plus what the
+    CV tolerance of 1e-6 moves the gradient through the oracle's Hessian
+    (central differences); the forces add J's 1e-5.  Every walker's V finite
+    and positive."""
+    import concurrent.futures as cf
+
+    from gpu_util import hill_grad_bound, hill_v_rel_bound
+
+    p = synth.CN3
+    W, n, K = 512, p["n_group"], 1000000
+    cvs = synth.cn3_cvs(n, p["r0"], p["rcut"])
+    pos, off = synth.cn3_positions(W, n, p["box"])
+    C, H = synth.cn3_hills(K, mean=p["cn_mean"], sd=p["hill_sd"])
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    s.set_box([p["box"]] * 3)
+    s.set_walkers(off, [K + 64 * W], shared=True)
+    s.metad([p["sigma"]] * 3, 1.0, 300.0, 6.0, 0, K + 64 * W)
+    s.bind()
+    assert s.cell_list_cvs() == 3
+    s.hills_set(0, C, H)
+    P = dev(pos)
+    F = torch.zeros_like(P)
+    xi = torch.zeros((W, 3), dtype=torch.float64, device=gpu)
+    V = torch.zeros(W, dtype=torch.float64, device=gpu)
+    dV = torch.zeros((W, 3), dtype=torch.float64, device=gpu)
+    s.step(P, forces=F, step=1, xi_out=xi, V_out=V, dV_out=dV)
+    s.check()
+    xi, V, dV, F = (t.cpu().numpy() for t in (xi, V, dV, F))
+    assert np.all(np.isfinite(V)) and np.all(V > 0)
+    ws = [0, 73, 146, 219, 292, 365, 438, 511]
+    with cf.ThreadPoolExecutor(8) as ex:
+        ref = list(ex.map(lambda w: oracle_walker(pos[off[w]:off[w + 1]], cvs, p["box"]), ws))
+    xr = np.array([r[0] for r in ref])
+    Cd, Hd, sig, per = C.astype(np.float64), H.astype(np.float64), [p["sigma"]] * 3, [0.0] * 3
+    Vr, dVr = oracle.hillsum_batch(xr, None, Cd, Hd, sig, per, nthreads=8)
+    # the oracle's Hessian of V at its xi: central differences of dV/dxi
+    hstep = 1e-4
+    shifts = np.concatenate([xr[:, None, :] + hstep * s_ * np.eye(3)[None] for s_ in (1.0, -1.0)], axis=1)
+    _, dVs = oracle.hillsum_batch(shifts.reshape(-1, 3), None, Cd, Hd, sig, per, nthreads=8)
+    dVs = dVs.reshape(len(ws), 6, 3)
+    hess = (dVs[:, :3, :] - dVs[:, 3:, :]).transpose(0, 2, 1) / (2 * hstep)  # [w][d][e] = d2V/dxi_d dxi_e
+    worst = {"xi": 0.0, "V/bound": 0.0, "dV/bound": 0.0, "F/bound": 0.0, "dV_rel": 0.0, "F_rel": 0.0}
+    for i, w in enumerate(ws):
+        worst["xi"] = max(worst["xi"], np.max(np.abs(xi[w] - xr[i]) / xr[i]))
+        bV = hill_v_rel_bound(xr[i], C, H, sig, per)
+        worst["V/bound"] = max(worst["V/bound"], abs(V[w] - Vr[i]) / Vr[i] / bV)
+        bdV = hill_grad_bound(xr[i], C, H, sig, per, hess[i], 1e-6 * np.abs(xr[i]))
+        worst["dV/bound"] = max(worst["dV/bound"], np.max(np.abs(dV[w] - dVr[i]) / bdV))
+        J = ref[i][1]
+        Fr = methods.chain_rule(-dVr[i], J)
+        bF = np.sum((bdV + 1e-5 * np.abs(dVr[i])) * np.max(np.abs(J), axis=(1, 2)))
+        worst["F/bound"] = max(worst["F/bound"], np.max(np.abs(F[off[w]:off[w + 1]] - Fr)) / bF)
+        worst["dV_rel"] = max(worst["dV_rel"], rel_inf(dV[w], dVr[i]))
+        worst["F_rel"] = max(worst["F_rel"], rel_inf(F[off[w]:off[w + 1]], Fr))
+    print("worst over the sampled walkers:", worst)
+    assert worst["xi"] <= 1e-6 and worst["V/bound"] <= 1.0
+    assert worst["dV/bound"] <= 1.0 and worst["F/bound"] <= 1.0
 
 
 def test_cell_surrogate_step(gpu):
