@@ -42,11 +42,13 @@ sx_status sxm_enqueue_cell(sx_ctx *ctx, void *stream, const void *pos, int32_t d
 /* ---------------------------------- libsampx_measure.so: timing, probes */
 /* Average duration of the step's two hill-sum kernels: `reps` launches of
  * the tile kernel captured in one HIP graph, then `reps` of the finalize
- * kernel in another, each graph replayed between hipEvents on the
- * context's stream (the stream the kernels run on); per launch, so the
- * figure includes the graph's gap between consecutive launches.  Nothing is
+ * kernel in another, each graph replayed twice to warm up, then five
+ * times between hipEvents on the context's stream (the stream the kernels
+ * run on); the median replay per launch, so the figure includes the
+ * graph's gap between consecutive launches.  Nothing is
  * deposited and the step counter is untouched; if forces is not NULL the
- * bias force is added to it `reps` times per replay.  Synchronous.
+ * bias force is added to it `reps` times per replay (seven replays).
+ * Synchronous.
  * ms_tiles / ms_finalize: host, milliseconds per launch. */
 sx_status sx_time_hill(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, float *forces, int32_t reps,
                        float *ms_tiles, float *ms_finalize);

@@ -1,19 +1,23 @@
 // Kernel-level timing of the biasing-force path (libsampx_measure.so):
 // `reps` launches of one kernel are captured into a HIP graph through the
-// hooks libsampx exports (sxm_enqueue_*), the graph is replayed once to
-// warm up and once more between hipEvents on the context's stream, and the
-// elapsed time is divided by reps.  Replaying a graph keeps host launch
-// cost out of the figure: the kernels run back to back on the device.
+// hooks libsampx exports (sxm_enqueue_*), the graph is replayed twice to
+// warm up and then kTrials times, each replay between hipEvents on the
+// context's stream; the median replay divided by reps is the figure.
+// Replaying a graph keeps host launch cost out of it: the kernels run back
+// to back on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <functional>
 
 #include "../../include/sampx_measure.h"
 
 namespace {
 
+constexpr int kWarm = 2, kTrials = 5;
+
 // capture reps calls of enq(stream) into a graph, replay it between events
-// on `run`; ms per call into *ms
+// on `run`; median ms per call into *ms
 sx_status time_graph(hipStream_t run, int32_t reps, const std::function<sx_status(hipStream_t)> &enq, float *ms)
 {
     hipStream_t cap = nullptr;
@@ -21,27 +25,31 @@ sx_status time_graph(hipStream_t run, int32_t reps, const std::function<sx_statu
     sx_status st = SX_OK;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t ev[kTrials + 1] = {};
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
         for (int r = 0; r < reps && st == SX_OK; ++r) st = enq(cap);
         e = hipStreamEndCapture(cap, &g);
     }
     if (st == SX_OK && e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    if (st == SX_OK && e == hipSuccess) e = hipEventCreate(&e0);
-    if (st == SX_OK && e == hipSuccess) e = hipEventCreate(&e1);
-    if (st == SX_OK && e == hipSuccess) e = hipGraphLaunch(ge, run);  // warm
-    if (st == SX_OK && e == hipSuccess) e = hipEventRecord(e0, run);
-    if (st == SX_OK && e == hipSuccess) e = hipGraphLaunch(ge, run);
-    if (st == SX_OK && e == hipSuccess) e = hipEventRecord(e1, run);
-    if (st == SX_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-    float t = 0.f;
-    if (st == SX_OK && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    for (int i = 0; i <= kTrials && st == SX_OK && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (int i = 0; i < kWarm && st == SX_OK && e == hipSuccess; ++i) e = hipGraphLaunch(ge, run);
+    if (st == SX_OK && e == hipSuccess) e = hipEventRecord(ev[0], run);
+    for (int i = 1; i <= kTrials && st == SX_OK && e == hipSuccess; ++i) {
+        e = hipGraphLaunch(ge, run);
+        if (e == hipSuccess) e = hipEventRecord(ev[i], run);
+    }
+    if (st == SX_OK && e == hipSuccess) e = hipEventSynchronize(ev[kTrials]);
+    float t[kTrials] = {};
+    for (int i = 0; i < kTrials && st == SX_OK && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ev[i], ev[i + 1]);
     if (st == SX_OK && e != hipSuccess) st = SX_EDEVICE;
-    if (st == SX_OK) *ms = t / reps;
+    if (st == SX_OK) {
+        std::sort(t, t + kTrials);
+        *ms = t[kTrials / 2] / reps;
+    }
     // teardown: failures here cannot change the result
-    if (e1) (void)hipEventDestroy(e1);
-    if (e0) (void)hipEventDestroy(e0);
+    for (int i = 0; i <= kTrials; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
     if (ge) (void)hipGraphExecDestroy(ge);
     if (g) (void)hipGraphDestroy(g);
     (void)hipStreamDestroy(cap);
