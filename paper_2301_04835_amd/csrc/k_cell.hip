@@ -194,12 +194,20 @@ constexpr int kRegMax = (2 * kXYReach + 1) * (2 * kXYReach + 1) * (kCzMax + 2 * 
 
 constexpr int kRegPer = (kRegMax + kJacBlock - 1) / kJacBlock;  // region sub-cells per thread
 
+// i + o wrapped into [0, n) for -n <= i + o < 2n (no division)
+__device__ __forceinline__ int wrap_cell(int v, int n)
+{
+    v += v < 0 ? n : 0;
+    return v >= n ? v - n : v;
+}
+
+template <int RXY>
 __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, int cx, int cy, int z0, int czb, int r0,
                                             float sc, float4 *s_p, int32_t *s_seg, int32_t *s_first, int32_t *s_wsum)
 {
     const int32_t *cst = c.cstart + ((int64_t)w * c.G + gp) * (c.ncell + 1);
     const float4 *srt = c.sorted + (int64_t)w * c.gtotal + c.goff[gp];
-    const int side = 2 * c.rxy + 1, nxy = side * side;
+    constexpr int side = 2 * RXY + 1, nxy = side * side;  // RXY = c.rxy: divisions by constants
     const int nreg = nxy * (czb + 2 * c.rz);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // thread tid owns region sub-cells [tid kRegPer, (tid + 1) kRegPer): their
@@ -211,9 +219,10 @@ __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, in
         const int t = tid * kRegPer + q;
         if (t >= nreg) break;
         const int sl = t / nxy, xy = t % nxy;
-        const int ox = xy / side - c.rxy, oy = xy % side - c.rxy, oz = sl - c.rz;
-        const int nx = (cx + ox + c.nc[0]) % c.nc[0], ny = (cy + oy + c.nc[1]) % c.nc[1];
-        const int nz = (z0 + oz + c.nc[2]) % c.nc[2];
+        const int ox = xy / side - RXY, oy = xy % side - RXY, oz = sl - c.rz;
+        // |ox|, |oy| <= rxy < nc and -rz <= z0 + oz < nc2 + rz with rz <= nc2
+        const int nx = wrap_cell(cx + ox, c.nc[0]), ny = wrap_cell(cy + oy, c.nc[1]);
+        const int nz = wrap_cell(z0 + oz, c.nc[2]);
         const int nb = (nx * c.nc[1] + ny) * c.nc[2] + nz;
         const int f = cst[nb], n = cst[nb + 1] - f;
         s_first[t] = f;
@@ -255,7 +264,7 @@ __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, in
         if (e0 >= e1) continue;
         const int f = s_first[t];
         const int sl = t / nxy, xy = t % nxy;
-        const int ox = xy / side - c.rxy, oy = xy % side - c.rxy, oz = sl - c.rz;
+        const int ox = xy / side - RXY, oy = xy % side - RXY, oz = sl - c.rz;
         const float shx = (float)(ox * c.clen[0]), shy = (float)(oy * c.clen[1]), shz = (float)(oz * c.clen[2]);
         for (int e = e0; e < e1; ++e) {
             float4 v = srt[f + (e - sg)];
@@ -280,58 +289,85 @@ __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, in
 // member and use (the VJP reads it).  A group's own CV counts its self pair
 // (r = 0: s = 1 exactly, zero gradient), so the A-side sum drops 1 per atom
 // instead of testing every pair.
-// Four partners s_p[j], s_p[j + kLpa], ... of one home atom (o): the cut
-// decision, the switch sum and the gradient sum.  In the (6, 12) form the
-// coordinates are in units of r0 (x^2 = r^2 / r0^2 directly) and the
-// gradient term is x^4 s^2 (r_i - r_j) / r0, the factor -6 / r0 applied
+// Four partners p[0], p[kLpa], p[2 kLpa], p[3 kLpa] of one home atom (o):
+// the cut decision, the switch sum and the gradient sum.  In the (6, 12)
+// form the coordinates are in units of r0 (x^2 = r^2 / r0^2 directly) and
+// the gradient term is x^4 s^2 (r_i - r_j) / r0, the factor -6 / r0 applied
 // once per atom; otherwise plain units and f of switch_fn.  TAIL: partners
-// at or past b1 do not count.
-template <bool S612, bool TAIL>
-__device__ __forceinline__ void pair4(const float4 *s_p, int j, int b1, float3 o, float rc2, float bandc,
-                                      const CvDesc &cv, const CellArgs &c, const PosView &pos, int64_t aoff,
-                                      int32_t me, float &sA, float &gx, float &gy, float &gz)
+// at or past pe do not count.  SIDEA: the switch sum is wanted (the A side
+// of the CV); on the B side only the gradient is.
+//
+// The cut enters the (6, 12) switch without a select: t = (r^2 - rc^2) 2^100
+// (one fma; scaling by a power of two keeps the rounding of r^2 - rc^2, so
+// the decision and its band are those of the unscaled difference), and
+// s = 1 / max(1 + x^6, t).  Inside the cut t < 0 and s is the switch; a
+// partner decided outside has t >= 2^100 * 1e-5 rc^2 > 1e25, so s < 1e-25
+// and x^4 s^2 underflows to zero: it adds nothing to the gradient and less
+// than 1e-25 to the switch sum, far below the sum's last bit.  Partners that
+// do not count (tail, exact decision outside) get t = +inf, s = 0.
+constexpr float kTScale = 0x1p100f;
+
+template <bool S612, bool TAIL, bool SIDEA>
+__device__ __forceinline__ void pair4(const float4 *p, const float4 *pe, float3 o, float rc2s, float bandcs,
+                                      float rc2, const CvDesc &cv, const CellArgs &c, const PosView &pos,
+                                      int64_t aoff, int32_t me, float &sA, float &gx, float &gy, float &gz)
 {
-    // t = r^2 - rc^2 decides (inside iff t < 0); partners that do not count
-    // get t = +inf, and within the band the exact decision overwrites t
     float dx[4], dy[4], dz[4], r2[4], t[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float4 pj = s_p[j + q * kLpa];  // < b1 + kStride <= m + kStride: padded
+        const float4 pj = p[q * kLpa];  // < pe + kStride: padded
         dx[q] = o.x - pj.x;
         dy[q] = o.y - pj.y;
         dz[q] = o.z - pj.z;
         r2[q] = fmaf(dx[q], dx[q], fmaf(dy[q], dy[q], dz[q] * dz[q]));
-        t[q] = r2[q] - rc2;
-        if (TAIL && j + q * kLpa >= b1) t[q] = __builtin_inff();
+        t[q] = S612 ? fmaf(r2[q], kTScale, -rc2s) : r2[q] - rc2;
+        if (TAIL && p + q * kLpa >= pe) t[q] = __builtin_inff();
     }
     const float tmin = fminf(fminf(fabsf(t[0]), fabsf(t[1])), fminf(fabsf(t[2]), fabsf(t[3])));
-    if (tmin <= bandc) {  // rare: the edge of the cut
+    if (tmin <= bandcs) {  // rare: the edge of the cut
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (fabsf(t[q]) <= bandc)
-                t[q] = cut_exact(pos, aoff, me, __float_as_int(s_p[j + q * kLpa].w), c.L[0], c.L[1], c.L[2], cv.rcut)
+            if (fabsf(t[q]) <= bandcs)
+                t[q] = cut_exact(pos, aoff, me, __float_as_int(p[q * kLpa].w), c.L[0], c.L[1], c.L[2], cv.rcut)
                            ? -1.0f
-                           : 1.0f;
+                           : __builtin_inff();
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const bool in = t[q] < 0.f;
         float f;
         if (S612) {
             const float x4 = r2[q] * r2[q];
-            const float sv = in ? __builtin_amdgcn_rcpf(fmaf(x4, r2[q], 1.0f)) : 0.f;
-            sA += sv;
+            // max(1 + x^6, t) on the bit patterns: 1 + x^6 is positive, so
+            // the signed-integer order agrees with the float order here
+            const float den = __int_as_float(max(__float_as_int(fmaf(x4, r2[q], 1.0f)), __float_as_int(t[q])));
+            const float sv = __builtin_amdgcn_rcpf(den);
+            if (SIDEA) sA += sv;
             f = x4 * sv * sv;
         } else {
+            const bool in = t[q] < 0.f;
             float sv;
             switch_fn(r2[q], cv, sv, f);
-            sA += in ? sv : 0.f;
+            if (SIDEA) sA += in ? sv : 0.f;
             f = in ? f : 0.f;
         }
         gx = fmaf(f, dx[q], gx);
         gy = fmaf(f, dy[q], gy);
         gz = fmaf(f, dz[q], gz);
     }
+}
+
+// One home atom's partners [p, pe) of the staged window, every kLpa-th from
+// this lane's start, four per step; pe3 = max(pe - 3 kLpa, window start):
+// a step starting below pe3 reads only partners below pe.
+template <bool S612, bool SIDEA>
+__device__ __forceinline__ void home_pairs(const float4 *p, const float4 *pe, const float4 *pe3, float3 o,
+                                           float rc2s, float bandcs, float rc2, const CvDesc &cv, const CellArgs &c,
+                                           const PosView &pos, int64_t aoff, int32_t me, float &sA, float &gx,
+                                           float &gy, float &gz)
+{
+    for (; p < pe3; p += kStride)
+        pair4<S612, false, SIDEA>(p, pe, o, rc2s, bandcs, rc2, cv, c, pos, aoff, me, sA, gx, gy, gz);
+    if (p < pe) pair4<S612, true, SIDEA>(p, pe, o, rc2s, bandcs, rc2, cv, c, pos, aoff, me, sA, gx, gy, gz);
 }
 
 template <bool S612, int RXY>
@@ -363,9 +399,11 @@ __global__ void __launch_bounds__(kJacBlock, 5) k_cell_jac(CellArgs c, CvSet cs,
         // coordinate scale, squared cut, its band, and the gradient factor
         const float sc = S612 ? cv.inv_r0 : 1.0f;
         const float rc2 = cv.rcut2 * sc * sc, bandc = 1e-5f * rc2, gsc = S612 ? -6.0f * cv.inv_r0 : 1.0f;
+        // the cut test's difference and band in the units of pair4's t
+        const float rc2s = S612 ? rc2 * kTScale : rc2, bandcs = S612 ? bandc * kTScale : bandc;
         double ssum = 0.0;  // this lane's switch sums (A side), over its home atoms
         for (int r0 = 0;; r0 += kColStage) {
-            const int m = stage_column(c, w, c.inv_p[g][u], cx, cy, z0, czb, r0, sc, s_p, s_seg, s_first, s_wsum);
+            const int m = stage_column<RXY>(c, w, c.inv_p[g][u], cx, cy, z0, czb, r0, sc, s_p, s_seg, s_first, s_wsum);
             for (int h0 = a0; h0 + (64 / kLpa) * wave < a1; h0 += kApp) {  // uniform per wavefront
                 const int i = h0 + tid / kLpa;
                 const bool live = i < a1;
@@ -382,10 +420,12 @@ __global__ void __launch_bounds__(kJacBlock, 5) k_cell_jac(CellArgs c, CvSet cs,
                 const float3 o = make_float3(pi.x * sc, pi.y * sc, (pi.z + (float)(k * c.clen[2])) * sc);
                 const int32_t me = __float_as_int(pi.w);
                 float sA = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-                int j = b0 + sub;
-                for (; j + 3 * kLpa < b1; j += kStride)
-                    pair4<S612, false>(s_p, j, b1, o, rc2, bandc, cv, c, pos, aoff, me, sA, gx, gy, gz);
-                if (j < b1) pair4<S612, true>(s_p, j, b1, o, rc2, bandc, cv, c, pos, aoff, me, sA, gx, gy, gz);
+                const float4 *const p0 = s_p + (b0 + sub), *const pe = s_p + b1;
+                const float4 *const pe3 = s_p + max(b1 - 3 * kLpa, 0);
+                if (sideA)
+                    home_pairs<S612, true>(p0, pe, pe3, o, rc2s, bandcs, rc2, cv, c, pos, aoff, me, sA, gx, gy, gz);
+                else
+                    home_pairs<S612, false>(p0, pe, pe3, o, rc2s, bandcs, rc2, cv, c, pos, aoff, me, sA, gx, gy, gz);
 #pragma unroll
                 for (int o = 1; o < kLpa; o <<= 1) {
                     sA += __shfl_xor(sA, o, 64);
