@@ -1,9 +1,14 @@
 """ctypes binding of the FP64 C oracle (``oracle.c``); test infrastructure only.
 
-The shared object is (re)built with gcc next to the source whenever it is
-missing or older than the source.  No fast-math: ``-O2 -fno-fast-math``.
+The shared object is built with gcc next to the source by ``build()`` (the
+package build calls it every time); ``lib()`` rebuilds it only when it is
+missing or was built from other source text (a sha256 of ``oracle.c`` is
+kept beside it), so copying the tree, which may reorder file times, never
+starts a compiler in a process that only checks results.  No fast-math:
+``-O2 -fno-fast-math``.
 """
 import ctypes
+import hashlib
 import os
 import subprocess
 
@@ -12,19 +17,36 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_STAMP = _LIB + ".src-sha256"
 
 KB = 0.008314462618  # kJ/(mol K): R/1000, CODATA 2018 (exact)
 
 
+def _src_sha():
+    with open(_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _built_from_current_source():
+    if not (os.path.exists(_LIB) and os.path.exists(_STAMP)):
+        return False
+    with open(_STAMP) as f:
+        return f.read().strip() == _src_sha()
+
+
 def build(force=False):
     """Compile ``oracle.c`` into ``liboracle.so`` (gcc, OpenMP, no fast-math)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    if not force and _built_from_current_source():
         return _LIB
+    sha = _src_sha()
     tmp = _LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-fno-fast-math", "-fPIC", "-shared", "-fopenmp", "-std=c11",
            _SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
+    with open(_STAMP + ".tmp%d" % os.getpid(), "w") as f:
+        f.write(sha + "\n")
+    os.replace(_STAMP + ".tmp%d" % os.getpid(), _STAMP)
     return _LIB
 
 

@@ -311,8 +311,9 @@ struct MlpStep {
 // the total within kCellTotal, rz reduced first), so partners within the cut
 // lie within rxy sub-cells in x and y and rz in z.  rxy = 1: with rxy = 2 a
 // home atom visits 1.44x fewer candidates, but each column block stages
-// 25/9 as many partners per home atom, and the pair pass of the 512-walker
-// workload took 24.6 ms instead of 14.9.
+// 25/9 as many partners per home atom over 25/9 as many sub-cells, and the
+// pair pass of the 512-walker workload took 21.2 ms (column blocks of 40
+// sub-cells) or 25.1 ms (20) instead of 13.0.
 constexpr int kCellMax = 16;   // cut-length cells per dimension
 constexpr int kCellTotal = 16384;
 constexpr int kXYReach = 1;    // largest rxy

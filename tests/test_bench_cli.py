@@ -1,7 +1,8 @@
 """The benchmark's command-line contract on the CPU: it measures one GPU,
 so a request for more exits with status 2 and says why, before anything
 touches a device; the traffic record is read only while the kernel sources
-hash to the value recorded with the counters."""
+hash to the value recorded with the counters; the graph length divides the
+timed steps."""
 import os
 import subprocess
 import sys
@@ -34,3 +35,12 @@ def test_traffic_record_keyed_to_sources(monkeypatch):
     assert bench.measured_traffic(8192) is None  # no counters at that tile
     monkeypatch.setattr(bench, "kernel_sources_sha", lambda: "0" * 16)
     assert bench.measured_traffic(4096) is None
+
+
+def test_graph_length_divides_the_timed_steps():
+    # the timed region is whole graphs of exactly --steps steps
+    for steps in (1, 7, 20, 50, 64, 97, 100, 2000):
+        g = bench.graph_len(steps, 50)
+        assert 1 <= g <= 50 and steps % g == 0
+        assert all(steps % h for h in range(g + 1, min(50, steps) + 1))  # the largest such
+    assert bench.graph_len(20, 50) == 20 and bench.graph_len(2000, 50) == 50 and bench.graph_len(97, 50) == 1
