@@ -189,7 +189,8 @@ def test_cn3_full_size_step_sampled_walkers(gpu):
     of the term scale (the survey's bound for cancelling sums) plus what the
     CV tolerance of 1e-6 moves the gradient through the oracle's Hessian
     (central differences); the forces add J's 1e-5.  Every walker's V finite
-    and positive."""
+    and positive, and every walker's V and dV/dxi within the same bounds of
+    the oracle's hill sum taken at the GPU's own xi."""
     import concurrent.futures as cf
 
     from gpu_util import hill_grad_bound, hill_v_rel_bound
@@ -244,6 +245,18 @@ def test_cn3_full_size_step_sampled_walkers(gpu):
     print("worst over the sampled walkers:", worst)
     assert worst["xi"] <= 1e-6 and worst["V/bound"] <= 1.0
     assert worst["dV/bound"] <= 1.0 and worst["F/bound"] <= 1.0
+    # every walker's V and dV/dxi against the oracle's hill sum over the 10^6
+    # hills at the GPU's own xi (the CV tolerance then does not enter): V
+    # within its float32-term bound, dV/dxi within 1e-5 of its term scale
+    Vg, dVg = oracle.hillsum_batch(xi, None, Cd, Hd, sig, per, nthreads=16)
+    zero3, nil = np.zeros((3, 3)), np.zeros(3)
+    with cf.ThreadPoolExecutor(16) as ex:
+        bnd = list(ex.map(lambda w: (hill_v_rel_bound(xi[w], Cd, Hd, sig, per),
+                                     hill_grad_bound(xi[w], Cd, Hd, sig, per, zero3, nil)), range(W)))
+    rV = max(abs(V[w] - Vg[w]) / Vg[w] / bnd[w][0] for w in range(W))
+    rdV = max(np.max(np.abs(dV[w] - dVg[w]) / bnd[w][1]) for w in range(W))
+    print("all %d walkers at the GPU's xi: V err / bound %.3f, dV err / bound %.3f" % (W, rV, rdV))
+    assert rV <= 1.0 and rdV <= 1.0
 
 
 def test_cell_surrogate_step(gpu):
