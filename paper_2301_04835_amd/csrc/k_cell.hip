@@ -301,10 +301,12 @@ __device__ __forceinline__ int stage_column(const CellArgs &c, int w, int gp, in
 // (one fma; scaling by a power of two keeps the rounding of r^2 - rc^2, so
 // the decision and its band are those of the unscaled difference), and
 // s = 1 / max(1 + x^6, t).  Inside the cut t < 0 and s is the switch; a
-// partner decided outside has t >= 2^100 * 1e-5 rc^2 > 1e25, so s < 1e-25
-// and x^4 s^2 underflows to zero: it adds nothing to the gradient and less
-// than 1e-25 to the switch sum, far below the sum's last bit.  Partners that
-// do not count (tail, exact decision outside) get t = +inf, s = 0.
+// partner decided outside (outside the band) has t > 2^100 * 1e-5 rc^2
+// (rc^2 in r0 units: 7e25 at rc = 2.4 r0, above 3e24 for any cut beyond
+// r0 / 2), so s < 3e-25 and x^4 s^2 underflows to zero or a denormal: it
+// adds nothing measurable to the gradient and less than 3e-25 to the switch
+// sum, far below the sum's last bit.  Partners that do not count (tail,
+// exact decision outside) get t = +inf, s = 0.
 constexpr float kTScale = 0x1p100f;
 
 template <bool S612, bool TAIL, bool SIDEA>
