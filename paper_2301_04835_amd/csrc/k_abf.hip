@@ -13,7 +13,10 @@
 // Fsum / max(N, N_thr) from the samples before this step (with FUNN: the
 // gradient of the network fitted to the mean forces, evaluated at xi, inside
 // the grid's range); then N += 1, Fsum += theta, and the bias force is
-// gathered onto the atoms.
+// gathered onto the atoms.  In the two-launch form the first launch also
+// sums the all-pairs coordination numbers' values from the CV kernel's block
+// records (unless FUNN needs xi earlier), which saves the value kernel's
+// launch.
 #include "sx_internal.h"
 #include "dev_gather.h"
 #include "dev_reduce.h"
@@ -252,12 +255,30 @@ __global__ void __launch_bounds__(kBlock) k_abf(AbfArgs a)
 // -- the first workgroup alone commits the sample, and every workgroup
 // gathers the forces of its atoms.  The grid is read in (1) and written in
 // (2) by one lane, so no workgroup reads it while it changes.
+// The coordination numbers' values of walker w from their block records:
+// lane-strided sums, a fixed butterfly, times the scale (the value kernel's
+// order, so the same bits); run by one whole wavefront, lane 0 writes.
+__device__ void fold_cn_values(const AbfArgs &a, int32_t w)
+{
+    const int lane = threadIdx.x & 63;
+    for (int k = 0; k < a.ncn_fold && k < kMaxBiasDim; ++k) {
+        const double *p = a.cn_vpart + (int64_t)w * a.vblk_per_walker + a.cn_vblk0[k];
+        double v = 0.0;
+        for (int b = lane; b < a.cn_nblk[k]; b += 64) v += p[b];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) a.xi_ws[(int64_t)w * a.D + a.cn_d[k]] = v * a.cn_scale[k];
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_abf_part(AbfArgs a)
 {
     __shared__ double lds[NA * (kBlock / 64)];
     const int32_t w = blockIdx.y;
     const int u = blockIdx.x * kBlock + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.pre[w] = abf_prefetch(a, w);
+    if (blockIdx.x == 0 && threadIdx.x < 64) {  // lane 0 reads the values it wrote
+        if (a.ncn_fold > 0) fold_cn_values(a, w);
+        if (threadIdx.x == 0) a.pre[w] = abf_prefetch(a, w);
+    }
     double acc[NA];
 #pragma unroll
     for (int j = 0; j < NA; ++j) acc[j] = 0.0;

@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(64) k_coord_value(CvSet cs, const double *vpar
 
 template <typename JT>
 hipError_t launch_cv_t(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, JT *J, double *cn_vpart,
-                       hipStream_t s)
+                       hipStream_t s, bool cn_values)
 {
     CvGrid g{};
     for (int c = 0; c < cs.ncv; ++c) {
@@ -326,7 +326,7 @@ hipError_t launch_cv_t(const CvSet &cs, const WalkerTabs &t, PosView pos, double
                            J, cn_vpart, g);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !g.ncn) return e;
+    if (e != hipSuccess || !g.ncn || !cn_values) return e;
     hipLaunchKernelGGL(k_coord_value, dim3((unsigned)t.W * g.ncn), dim3(64), 0, s, cs, cn_vpart, xi, g.ncn);
     return hipGetLastError();
 }
@@ -334,10 +334,10 @@ hipError_t launch_cv_t(const CvSet &cs, const WalkerTabs &t, PosView pos, double
 }  // namespace
 
 hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *J64,
-                     double *cn_vpart, hipStream_t s)
+                     double *cn_vpart, hipStream_t s, bool cn_values)
 {
-    if (J64) return launch_cv_t<double>(cs, t, pos, xi, J64, cn_vpart, s);
-    return launch_cv_t<float>(cs, t, pos, xi, J, cn_vpart, s);
+    if (J64) return launch_cv_t<double>(cs, t, pos, xi, J64, cn_vpart, s, cn_values);
+    return launch_cv_t<float>(cs, t, pos, xi, J, cn_vpart, s, cn_values);
 }
 
 }  // namespace sx

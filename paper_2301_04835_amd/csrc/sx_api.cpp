@@ -772,7 +772,7 @@ MlpArgs mlp_args(sx_ctx *c)
     return a;
 }
 
-sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J, double *J64 = nullptr);
+sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J, double *J64 = nullptr, bool cn_values = true);
 sx_status cell_forces(sx_ctx *c, const PosView &pv, const double *coef, double sign, float *out, int32_t layout);
 
 // the surrogate's step: network for every walker (outputs, certification
@@ -902,10 +902,10 @@ CellArgs cell_args(sx_ctx *c)
     return a;
 }
 
-sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J, double *J64)
+sx_status launch_cvs(sx_ctx *c, const PosView &pv, double *xi, float *J, double *J64, bool cn_values)
 {
     const Plan &p = c->plan;
-    hipError_t e = launch_cv(p.cs, tabs_of(c), pv, xi, J, J64, at<double>(c->ws, p.w_cnpart), c->stream);
+    hipError_t e = launch_cv(p.cs, tabs_of(c), pv, xi, J, J64, at<double>(c->ws, p.w_cnpart), c->stream, cn_values);
     if (e == hipSuccess && p.cell.ncn) e = launch_cell_cv(cell_args(c), p.cs, pv, xi, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "CV kernels");
     return SX_OK;
@@ -941,8 +941,14 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
     const bool fuse_harmonic = c->method == M_HARMONIC && p.all_dihedral;
     if (c->sg_on) return enqueue_surrogate_step(c, pv, step, xi, J, xi_out, V_out, dVdxi_out, forces, layout);
     double *J64 = c->method == M_ABF ? at<double>(c->ws, p.w_J64) : nullptr;
+    // ABF in two launches (without FUNN, which reads xi first) sums the
+    // all-pairs coordination values itself: one launch fewer
+    int ncn_all = 0;
+    for (int d = 0; d < p.cs.ncv; ++d) ncn_all += p.cs.cv[d].kind == CV_COORD;
+    const bool abf_fold = c->method == M_ABF && p.abf_nblk > 0 && !c->funn_on && ncn_all > 0 &&
+                          ncn_all <= kMaxBiasDim;
     if (!fuse && !fuse_grid && !fuse_harmonic) {
-        sx_status st = launch_cvs(c, pv, xi, J64 ? nullptr : J, J64);
+        sx_status st = launch_cvs(c, pv, xi, J64 ? nullptr : J, J64, !abf_fold);
         if (st != SX_OK) return st;
     }
     if (c->method == M_METAD && !c->sg_on && c->stride > 0) c->sg_certified = false;  // may deposit
@@ -1060,6 +1066,21 @@ sx_status enqueue_step(sx_ctx *c, const void *pos, int32_t dtype, int32_t layout
         a.nblk = p.abf_nblk;
         a.part = at<double>(c->ws, p.w_abfpart);
         a.pre = at<AbfPre>(c->ws, p.w_abfpre);
+        if (abf_fold) {
+            for (int d = 0; d < p.cs.ncv; ++d) {
+                const CvDesc &cv = p.cs.cv[d];
+                if (cv.kind != CV_COORD) continue;
+                const int per = kBlock / cv.lanes;
+                a.cn_d[a.ncn_fold] = cv.d;
+                a.cn_vblk0[a.ncn_fold] = cv.vblk0;
+                a.cn_nblk[a.ncn_fold] = (cv.na + per - 1) / per;
+                a.cn_scale[a.ncn_fold] = (double)cv.scale;
+                ++a.ncn_fold;
+            }
+            a.cn_vpart = at<double>(c->ws, p.w_cnpart);
+            a.vblk_per_walker = p.cs.vblk_per_walker;
+            a.xi_ws = xi;
+        }
         hipError_t e = launch_abf(a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "ABF kernel");
     }

@@ -186,6 +186,18 @@ struct AbfArgs {
     int32_t nblk;
     double *part;
     AbfPre *pre;
+    // two-launch form without FUNN: the all-pairs coordination numbers'
+    // values are summed here from their block records (cn_vpart, as the CV
+    // kernel left them) by the first wavefront of the first workgroup, in
+    // the order of the value kernel it replaces, and written to xi_ws before
+    // the bin is taken: cn_d the CV index, cn_vblk0 its first record,
+    // cn_nblk its records, cn_scale its scale
+    int32_t ncn_fold;
+    int32_t cn_d[kMaxBiasDim], cn_vblk0[kMaxBiasDim], cn_nblk[kMaxBiasDim];
+    double cn_scale[kMaxBiasDim];
+    const double *cn_vpart;
+    int64_t vblk_per_walker;
+    double *xi_ws;
 };
 constexpr int kAbfSplitU = 2 * kBlock;  // touched atoms above which ABF takes the two-launch form
 
@@ -363,8 +375,10 @@ struct MlpArgs {
 // Each returns the hipError_t of its launch.
 // Jacobian rows into J (float) or, when J64 is given, into J64 (double; the
 // ABF path); J may be null when only the values are wanted
+// cn_values false: the all-pairs coordination numbers stop at their block
+// records in cn_part (a later kernel sums them)
 hipError_t launch_cv(const CvSet &cs, const WalkerTabs &t, PosView pos, double *xi, float *J, double *J64,
-                     double *cn_part, hipStream_t s);
+                     double *cn_part, hipStream_t s, bool cn_values = true);
 // which: 1 = tiles (kernel A), 2 = finalize (kernel B), 3 = both
 hipError_t launch_hill_private(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t grid, hipStream_t s,
                                int which = 3);
