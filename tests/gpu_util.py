@@ -43,9 +43,10 @@ def hill_v_rel_bound(xi, C, H, sigma, period, base=1e-6):
 def hill_grad_bound(xi, C, H, sigma, period, hess, xi_tol, rel=1e-5):
     """Per-CV bound on |dV/dxi_gpu - dV/dxi_ref| for a hill sum whose
     gradient cancels: rel times the larger of max |dV/dxi| and the term scale
-    S_d = sum_k h_k g_k |D_kd| / sigma_d^2 (the survey's force bound for
-    cancelling sums), plus what the CV tolerance xi_tol (per CV) moves the
-    gradient through the bias's Hessian `hess` (D x D)."""
+    S_d = sum_k h_k g_k |D_kd| / sigma_d^2 (a sum whose terms cancel carries
+    a rounding error relative to the sum of their magnitudes, not to the
+    result), plus what the CV tolerance xi_tol (per CV) moves the gradient
+    through the bias's Hessian `hess` (D x D)."""
     xi = np.asarray(xi, dtype=np.float64)
     C = np.asarray(C, dtype=np.float64).reshape(-1, len(xi))
     H = np.asarray(H, dtype=np.float64)

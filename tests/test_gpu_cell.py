@@ -186,7 +186,7 @@ def test_cn3_full_size_step_sampled_walkers(gpu):
     float32-term bound; dV/dxi and the forces within their derived bounds:
     the walkers sit inside the hill cloud, where dV/dxi is a small remainder
     of large terms of both signs and the bias is steep, so the bound is 1e-5
-    of the term scale (the survey's bound for cancelling sums) plus what the
+    of the term scale (the sum of the terms' magnitudes) plus what the
     CV tolerance of 1e-6 moves the gradient through the oracle's Hessian
     (central differences); the forces add J's 1e-5.  Every walker's V finite
     and positive, and every walker's V and dV/dxi within the same bounds of
