@@ -455,7 +455,9 @@ sx_status make_plan(sx_ctx *c)
         if (cap > (int64_t)1 << 30) return fail(c, SX_EINVAL, "hill capacity above 2^30 per list");
         p.hill_cap[w] = (int32_t)cap;
         p.hill_base[w] = total;
-        total += (cap + 3) / 4 * 4;
+        // segments of 32 hills (128 bytes per array): every tile starts on
+        // a cache line, so no line is fetched by two tiles
+        total += (cap + 31) / 32 * 32;
     }
     p.total_cap = total;
     if (!c->shared)
