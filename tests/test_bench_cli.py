@@ -44,3 +44,22 @@ def test_graph_length_divides_the_timed_steps():
         assert 1 <= g <= 50 and steps % g == 0
         assert all(steps % h for h in range(g + 1, min(50, steps) + 1))  # the largest such
     assert bench.graph_len(20, 50) == 20 and bench.graph_len(2000, 50) == 50 and bench.graph_len(97, 50) == 1
+
+
+def test_tuning_cache_covers_the_benchmark_shape():
+    # the benchmark's 256-walker shape (capacity = hills + 64 per walker, each
+    # segment padded to 32 hills) has a recorded tiling, so the timed run
+    # never searches for one; a change of the state layout shows up here
+    import json
+
+    import numpy as np
+
+    from paper_2301_04835_amd import synth
+
+    p = synth.WALKERS256
+    d = synth.walkers_inputs(n_walkers=p["n_walkers"], seed=3)
+    cap = np.asarray(d["n_hills"], dtype=np.int64) + 64
+    total = int(np.sum((cap + 31) // 32 * 32))
+    cache = json.load(open(os.path.join(ROOT, "paper_2301_04835_amd", "tuning_mi355x.json")))
+    keys = [k for k in cache if "/D2/W%d/cap%d/fuse1" % (p["n_walkers"], total) in k]
+    assert keys and all(k.startswith("gfx950") for k in keys)
