@@ -99,6 +99,40 @@ def test_cell_values_dense_groups_several_staging_rounds(gpu):
         assert rel_inf(pb[off[w]:off[w + 1]], np.tensordot(xb[w], J, axes=1)) <= 1e-5
 
 
+def test_cell_values_orthorhombic_box(gpu):
+    """An orthorhombic box with a different cell count per dimension
+    (4.0 x 5.3 x 7.9 nm: 3, 4 and 6 cut-length cells, z cut further into
+    sub-cells), atoms outside the box and on cell faces: values and VJP
+    against the brute-force oracle with the same box."""
+    W, n = 2, 600
+    box = np.array([4.0, 5.3, 7.9])
+    g = np.random.default_rng(25)
+    pos = g.uniform(0.0, 1.0, size=(W * 3 * n, 3)) * box
+    pos[::7] += g.choice([-1.0, 1.0, 2.0], size=(pos[::7].shape[0], 1)) * box  # wrapped
+    pos[3::11, 1] = box[1] / 4.0  # on a cell face
+    pos[5::13, 2] = box[2]        # on the far face = 0
+    pos = pos.astype(np.float32)
+    off = np.arange(W + 1, dtype=np.int64) * 3 * n
+    cvs = synth.cn3_cvs(n, 0.5, 1.2)
+    s = Sampler(0)
+    s.add_cvs(cvs)
+    s.set_box(list(box))
+    s.set_walkers(off)
+    s.set_cell_lists(1)
+    s.bind()
+    assert s.cell_list_cvs() == 3
+    P = dev(pos)
+    xi = s.eval_cv(P)[0].cpu().numpy()
+    xb = np.random.default_rng(26).normal(size=(W, 3))
+    pb = torch.zeros_like(P)
+    s.cv_vjp(P, dev(xb), pb)
+    pb = pb.cpu().numpy()
+    for w in range(W):
+        xr, J = methods.cv_eval(pos[off[w]:off[w + 1]].astype(np.float64), cvs, box)
+        assert np.max(np.abs(xi[w] - xr) / np.abs(xr)) <= 1e-6
+        assert rel_inf(pb[off[w]:off[w + 1]], np.tensordot(xb[w], J, axes=1)) <= 1e-5
+
+
 def test_cell_mode_rules(gpu):
     W, n, L = 2, 300, 4.0
     pos, off, cvs = small_system(W, n, L, 5)
