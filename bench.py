@@ -71,11 +71,12 @@ def build_context(d, p):
     return s, pos, forces
 
 
-TRAFFIC_SOURCES = ("k_bias.hip", "dev_cv.h", "dev_gather.h", "dev_reduce.h")
+TRAFFIC_SOURCES = ("k_bias.hip", "dev_cv.h", "dev_gather.h", "dev_reduce.h", "sx_api.cpp")  # kernels + state layout
 
 
 def kernel_sources_sha():
-    """sha256 (first 16 hex digits) of the tile kernel's sources."""
+    """sha256 (first 16 hex digits) of the tile kernel's sources and of the
+    library source that lays out the state it reads."""
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
