@@ -9,21 +9,22 @@
 //                  exclusive scan, and an in-order placement (stable within
 //                  a cell), so every later sum runs in a fixed order; each
 //                  member is stored as (x, y, z) relative to its cell's
-//                  origin (float, ~6e-8 nm) and its atom index.
+//                  origin (float, ~6e-8 nm) and its atom index, and its
+//                  sorted position is kept in member order.
 //   k_cell_jac     one workgroup per (walker, group, column block of cells
 //                  in z): the partner group's members in the cells around
 //                  the block are staged in LDS relative to the block's
 //                  origin (a cell's offset is its cell step times the cell
 //                  edge, periodic wrap included), slice by slice, so each
-//                  home cell's neighbours form one contiguous range; four
+//                  home cell's neighbours form one contiguous range; eight
 //                  lanes own one home atom and walk that range: FP32 pair
 //                  terms, the switch sum (the CV value, on the A side) and
 //                  the gradient sum_j f(r_ij)(r_i - r_j) of each (CV, side)
 //                  use, stored per member (no atomics, fixed order).
 //   k_cn_cell_fin  per (walker, CV): the column-block partials in order.
 //   k_cell_gather  the vector-Jacobian product from the stored gradients,
-//                  one lane per member (groups identical or disjoint: one
-//                  writer per atom).
+//                  one lane per member in member order (groups identical
+//                  or disjoint: one writer per atom).
 
 // Cut-length cells (edge >= the cutoff, >= 3 per dimension) are cut into rxy
 // sub-cells in x and y and rz in z, so the (2 rxy + 1)^2 (2 rz + 1)
@@ -133,6 +134,7 @@ __global__ void __launch_bounds__(kBuildBlock) k_cell_build(CellArgs c, PosView 
             if (wave == t && valid) {
                 const int dst = s_off[cell] + rank;
                 srt[dst] = v;
+                cid[i] = dst;  // from here on: the member's sorted position
                 if (rank == cnt - 1) s_off[cell] += cnt;  // after every lane of the wave read it
             }
         }
@@ -483,13 +485,15 @@ __global__ void __launch_bounds__(kBlock) k_cn_cell_fin(CellArgs c, CvSet cs, do
     }
 }
 
-// VJP from the stored gradients: one lane per member of each group (sorted
-// order), out += sign sum over the group's uses of coef[cv] scale_cv J; the
-// groups are identical or disjoint, so every atom has one writer.  The force
-// writes of a walker go to its atoms in cell order, so all blocks of one
-// walker run on one XCD (blocks are dealt to the 8 XCDs in turn): block b
-// serves walker 8 (k / nch) + b % 8, chunk k % nch, k = b / 8, and each force
-// line passes through one L2.
+// VJP from the stored gradients: one lane per member of each group in
+// member order, out += sign sum over the group's uses of coef[cv] scale_cv J,
+// J read at the member's sorted position (left in cid by the build); the
+// groups are identical or disjoint, so every atom has one writer.  Members
+// listed in atom order make the force updates contiguous; the gradient
+// reads land anywhere in the walker's records, so all blocks of one walker
+// run on one XCD (blocks are dealt to the 8 XCDs in turn): block b serves
+// walker 8 (k / nch) + b % 8, chunk k % nch, k = b / 8, and those records
+// pass through one L2.
 __global__ void __launch_bounds__(kBlock) k_cell_gather(CellArgs c, CvSet cs, const double *coef, double sign,
                                                          ForceView F, int32_t nch)
 {
@@ -499,18 +503,18 @@ __global__ void __launch_bounds__(kBlock) k_cell_gather(CellArgs c, CvSet cs, co
     if (w >= c.W || e >= c.gtotal) return;
     int g = 0;
     while (g + 1 < c.G && e >= c.goff[g + 1]) ++g;
-    const int64_t i = e - c.goff[g];
-    const float4 me = c.sorted[(int64_t)w * c.gtotal + e];
+    const int32_t atom = c.gatoms[e];
+    const int32_t sp = c.cid[(int64_t)w * c.gtotal + e];
     double fx = 0.0, fy = 0.0, fz = 0.0;
     for (int u = 0; u < c.ninv[g]; ++u) {
         const CvDesc &cv = cs.cv[c.inv_cv[g][u]];
         const double cf = sign * coef[(int64_t)w * cs.D + cv.d] * (double)cv.scale;
-        const float4 j = c.jac[(int64_t)w * c.jtotal + c.joff[g][u] + i];
+        const float4 j = c.jac[(int64_t)w * c.jtotal + c.joff[g][u] + sp];
         fx += cf * (double)j.x;
         fy += cf * (double)j.y;
         fz += cf * (double)j.z;
     }
-    float *f = F.ptr + (c.atom_off[w] + __float_as_int(me.w)) * F.sa;
+    float *f = F.ptr + (c.atom_off[w] + atom) * F.sa;
     f[0] += (float)fx;
     f[F.sk] += (float)fy;
     f[2 * F.sk] += (float)fz;

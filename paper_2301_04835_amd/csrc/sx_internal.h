@@ -342,7 +342,7 @@ struct CellArgs {
     const int32_t *gatoms;             // walker-relative atoms of all groups, group after group
     int32_t goff[kMaxGroups + 1];      // group g: gatoms[goff[g] .. goff[g + 1])
     int64_t gtotal;                    // goff[G]
-    int32_t *cid;                      // W x gtotal: cell of each group member
+    int32_t *cid;                      // W x gtotal: cell of each group member, then its sorted position
     int32_t *cstart;                   // W x G x (ncell + 1): members of cell c
     float4 *sorted;                    // W x gtotal: (x, y, z) relative to the cell origin, atom
     double *part;                      // W x ncn x nblk: coordination partial sums per column block
