@@ -354,7 +354,10 @@ __global__ void __launch_bounds__(kBlock) k_hill_shared_qm(SharedArgs a)
     if (!a.fb[w]) return;  // uniform per workgroup
     const int32_t n = *a.count;
     const int64_t h0 = (int64_t)blockIdx.x * kQmChunk;
-    if (h0 >= n) return;  // uniform
+    if (h0 >= n) {  // uniform: a chunk past the count adds zero (the finalize sums every chunk)
+        if (threadIdx.x <= D) a.partial[((int64_t)blockIdx.x * a.nq + w) * 4 + threadIdx.x] = 0.0;
+        return;
+    }
     double sc[D], per[D], iper[D], xs[D];
     bool wrap[D];
 #pragma unroll

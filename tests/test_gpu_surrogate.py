@@ -282,6 +282,42 @@ def test_surrogate_step_against_exact(c4):
     s.surrogate_enable(False)
 
 
+def test_fallback_with_spare_capacity(gpu):
+    """A shared list filled to a fraction of its capacity (3,000 hills in
+    room for 15,000: the fallback sums' chunks past the count hold no
+    hills) and an untrained network that certifies nothing, so every walker
+    takes the exact fallback, right after a certification pass has left
+    other records in the same workspace: V and dV/dxi of every walker at the
+    exact path's bar against the oracle."""
+    W, K, cap = 8, 3000, 15000
+    C = synth.uniform_centers(K, 2, 41)
+    H = synth.uniform_heights(K, 42)
+    pos, off = synth.chain_walkers(W, 22, seed=43)
+    s = Sampler(0)
+    s.add_cvs(synth.backbone_cvs(4))
+    s.set_walkers(off, [cap], shared=True)
+    s.metad([0.3, 0.3], 1.0, 300.0, 6.0, 0, cap)
+    s.surrogate(64, max_samples=1024, max_batch=1024, cert_n=32, tol_force=0.1)
+    s.bind()
+    s.hills_set(0, C, H)
+    s.surrogate_params(rand_params(64, 2, 44))
+    s.surrogate_certify()
+    s.surrogate_enable(True)
+    P = dev(pos)
+    F = torch.zeros_like(P)
+    xi = torch.empty((W, 2), dtype=torch.float64, device=P.device)
+    V = torch.empty(W, dtype=torch.float64, device=P.device)
+    dV = torch.empty((W, 2), dtype=torch.float64, device=P.device)
+    s.step(P, forces=F, step=3, xi_out=xi, V_out=V, dV_out=dV)
+    s.check()
+    assert s.surrogate_fallback_count() == W
+    xi, V, dV = (t.cpu().numpy() for t in (xi, V, dV))
+    Vr, dVr = oracle.hillsum_batch(xi, None, C.astype(np.float64), H.astype(np.float64), [0.3, 0.3],
+                                   [TWO_PI] * 2, nthreads=8)
+    assert np.max(np.abs(V - Vr) / np.abs(Vr)) <= 1e-6
+    assert max(rel_inf(dV[w], dVr[w]) for w in range(W)) <= 1e-5
+
+
 def test_surrogate_errors(gpu):
     s = Sampler(0)
     s.add_cvs(synth.backbone_cvs(0))
