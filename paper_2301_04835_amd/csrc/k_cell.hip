@@ -65,16 +65,28 @@ __global__ void __launch_bounds__(kBuildBlock) k_cell_build(CellArgs c, PosView 
     float4 *srt = c.sorted + (int64_t)w * c.gtotal + c.goff[g];
     for (int i = tid; i < c.ncell; i += kBuildBlock) s_off[i] = 0;
     __syncthreads();
-    // pass 1: cells and counts
-    for (int32_t i = tid; i < n; i += kBuildBlock) {
-        const double3 r = ld_pos_t<T>(pos, aoff + ga[i]);
-        double rel;
-        const int cx = cell_of(r.x, c.L[0], c.inv_L[0], c.clen[0], c.nc[0], rel);
-        const int cy = cell_of(r.y, c.L[1], c.inv_L[1], c.clen[1], c.nc[1], rel);
-        const int cz = cell_of(r.z, c.L[2], c.inv_L[2], c.clen[2], c.nc[2], rel);
-        const int cell = (cx * c.nc[1] + cy) * c.nc[2] + cz;
-        cid[i] = cell;
-        atomicAdd(&s_off[cell], 1);  // counts only: the placement below is ordered
+    // pass 1: cells and counts, four members per thread at a time with their
+    // loads issued together (a member past the group's end reads member b
+    // instead and is dropped)
+    for (int32_t b = tid; b < n; b += 4 * kBuildBlock) {
+        double3 r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int32_t i = b + k * kBuildBlock;
+            r[k] = ld_pos_t<T>(pos, aoff + ga[i < n ? i : b]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int32_t i = b + k * kBuildBlock;
+            if (i >= n) break;
+            double rel;
+            const int cx = cell_of(r[k].x, c.L[0], c.inv_L[0], c.clen[0], c.nc[0], rel);
+            const int cy = cell_of(r[k].y, c.L[1], c.inv_L[1], c.clen[1], c.nc[1], rel);
+            const int cz = cell_of(r[k].z, c.L[2], c.inv_L[2], c.clen[2], c.nc[2], rel);
+            const int cell = (cx * c.nc[1] + cy) * c.nc[2] + cz;
+            cid[i] = cell;
+            atomicAdd(&s_off[cell], 1);  // counts only: the placement below is ordered
+        }
     }
     __syncthreads();
     // exclusive scan of the counts: kScanPer cells per thread, then across threads
@@ -113,6 +125,8 @@ __global__ void __launch_bounds__(kBuildBlock) k_cell_build(CellArgs c, PosView 
         const int32_t i = base + tid;
         const bool valid = i < n;
         const int cell = valid ? cid[i] : -1;
+        const int32_t atom = ga[valid ? i : base];  // in flight during the ranking
+        const double3 r = ld_pos_t<T>(pos, aoff + atom);
         int rank = 0, cnt = 0;
         for (int k = 0; k < 64; ++k) {
             const int ck = __shfl(cell, k, 64);
@@ -121,8 +135,6 @@ __global__ void __launch_bounds__(kBuildBlock) k_cell_build(CellArgs c, PosView 
         }
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (valid) {
-            const int32_t atom = ga[i];
-            const double3 r = ld_pos_t<T>(pos, aoff + atom);
             double rx, ry, rz;
             cell_of(r.x, c.L[0], c.inv_L[0], c.clen[0], c.nc[0], rx);
             cell_of(r.y, c.L[1], c.inv_L[1], c.clen[1], c.nc[1], ry);

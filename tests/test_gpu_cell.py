@@ -99,6 +99,26 @@ def test_cell_values_dense_groups_several_staging_rounds(gpu):
         assert rel_inf(pb[off[w]:off[w + 1]], np.tensordot(xb[w], J, axes=1)) <= 1e-5
 
 
+def test_cell_results_repeat_bitwise(gpu):
+    """The build places each member by its rank in member order among its
+    cell's members, whatever order the cell slots were taken in: repeated
+    evaluations of the dense system (~19 members per sub-cell) give bitwise the
+    same CN values and VJP."""
+    W, n, L = 2, 2000, 4.0
+    pos, off, cvs = small_system(W, n, L, 27)
+    s = ctx(cvs, L, off, 1)
+    P = dev(pos)
+    xb = dev(np.random.default_rng(5).normal(size=(W, 3)))
+    runs = []
+    for _ in range(3):
+        xi = s.eval_cv(P)[0].cpu().numpy()
+        pb = torch.zeros_like(P)
+        s.cv_vjp(P, xb, pb)
+        runs.append((xi, pb.cpu().numpy()))
+    for xi, pb in runs[1:]:
+        assert np.array_equal(xi, runs[0][0]) and np.array_equal(pb, runs[0][1])
+
+
 def test_cell_values_orthorhombic_box(gpu):
     """An orthorhombic box with a different cell count per dimension
     (4.0 x 5.3 x 7.9 nm: 3, 4 and 6 cut-length cells, z cut further into
