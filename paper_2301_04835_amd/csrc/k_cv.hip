@@ -142,6 +142,23 @@ __device__ __forceinline__ double3 ld_d3(const PosView &p, int64_t i)
 __device__ __forceinline__ float min_img(double d, double L, double iL) { return (float)fma(-L, rint(d * iL), d); }
 __device__ __forceinline__ double min_img_d(double d, double L, double iL) { return fma(-L, rint(d * iL), d); }
 
+// The hard cut decided from the positions as given, in FP64, one operation
+// at a time and without contraction: d = a - b, d -= L rint(d / L),
+// r = sqrt((dx^2 + dy^2) + dz^2), inside unless r >= rcut (the plain
+// definition, so that a pair at the cut's edge falls on the same side as
+// under it).  Called only for pairs whose working r^2 lies within a relative
+// band of rcut^2 wider than its rounding error.
+__device__ __attribute__((noinline)) bool cut_inside_exact(double ax, double ay, double az, double bx, double by,
+                                                          double bz, double L0, double L1, double L2, double rcut)
+{
+#pragma clang fp contract(off)
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    dx = dx - L0 * rint(dx / L0);
+    dy = dy - L1 * rint(dy / L1);
+    dz = dz - L2 * rint(dz / L2);
+    return !(sqrt(dx * dx + dy * dy + dz * dz) >= rcut);
+}
+
 // grid: x = block of kBlock / L members of one side, y = side (0: A gathers
 // over B, 1: B gathers over A), z = walker * ncoord + k (k-th coordination
 // CV); L = cv.lanes lanes per member.  The other side's members are staged
@@ -150,8 +167,9 @@ __device__ __forceinline__ double min_img_d(double d, double L, double iL) { ret
 // FP64 (exact for float inputs up to the final rounding), the switching
 // function in FP32, its sums in FP32 over each eight of a lane's partners and
 // in FP64 beyond (for a Jacobian kept in FP64, JT = double, every pair term
-// is FP64); the member's lanes combine in a fixed butterfly and the
-// first writes the Jacobian slot.  On the A side the members' switch sums are
+// is FP64); a pair whose r^2 lies within 1e-5 (FP64 terms: 1e-12) of the
+// hard cut's, relative, is re-decided by cut_inside_exact.  The member's
+// lanes combine in a fixed butterfly and the first writes the Jacobian slot.  On the A side the members' switch sums are
 // reduced per workgroup (fixed tree) into one value record per block, which
 // k_coord_value sums in order.
 template <typename T, typename JT>
@@ -186,50 +204,71 @@ __device__ __forceinline__ void coord_block(const CvSet &cs, const WalkerTabs &t
         }
         __syncthreads();
         if (!live) continue;
-        if (std::is_same<JT, double>::value) {  // FP64 pair terms: ABF's Gram matrix and J.F
-            for (int j = l; j < jn; j += L) {
-                const Partner o = oth[j];
-                const double dx = min_img_d(ri.x - o.x, Lb[0], iL[0]);
-                const double dy = min_img_d(ri.y - o.y, Lb[1], iL[1]);
-                const double dz = min_img_d(ri.z - o.z, Lb[2], iL[2]);
-                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                const bool use = (o.idx != me) && (cv.rcut <= 0.0 || r2 < cv.rcut * cv.rcut);
-                double sv, f;
-                switch_fn(r2, cv, sv, f);
-                S += use ? sv : 0.0;
-                f = use ? f : 0.0;
-                gx = fma(f, dx, gx);
-                gy = fma(f, dy, gy);
-                gz = fma(f, dz, gz);
+        // the loops below without any cut test when the CV has no hard cut
+        auto pairs = [&](auto has_cut) {
+            constexpr bool CUT = decltype(has_cut)::value;
+            if (std::is_same<JT, double>::value) {  // FP64 pair terms: ABF's Gram matrix and J.F
+                for (int j = l; j < jn; j += L) {
+                    const Partner o = oth[j];
+                    const double dx = min_img_d(ri.x - o.x, Lb[0], iL[0]);
+                    const double dy = min_img_d(ri.y - o.y, Lb[1], iL[1]);
+                    const double dz = min_img_d(ri.z - o.z, Lb[2], iL[2]);
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    bool use = o.idx != me;
+                    if (CUT) {
+                        const double rc2 = cv.rcut * cv.rcut;
+                        if (fabs(r2 - rc2) <= 1e-12 * rc2)  // rare: the edge of the cut
+                            use = use && cut_inside_exact(ri.x, ri.y, ri.z, o.x, o.y, o.z, Lb[0], Lb[1], Lb[2], cv.rcut);
+                        else
+                            use = use && r2 < rc2;
+                    }
+                    double sv, f;
+                    switch_fn(r2, cv, sv, f);
+                    S += use ? sv : 0.0;
+                    f = use ? f : 0.0;
+                    gx = fma(f, dx, gx);
+                    gy = fma(f, dy, gy);
+                    gz = fma(f, dz, gz);
+                }
+                return;
             }
-            continue;
-        }
-        for (int j = l; j < jn; j += 8 * L) {
-            float s8 = 0.f, x8 = 0.f, y8 = 0.f, z8 = 0.f;
+            for (int j = l; j < jn; j += 8 * L) {
+                float s8 = 0.f, x8 = 0.f, y8 = 0.f, z8 = 0.f;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int jj = j + q * L;
-                if (jj >= jn) break;
-                const Partner o = oth[jj];
-                const float dx = min_img(ri.x - o.x, Lb[0], iL[0]);
-                const float dy = min_img(ri.y - o.y, Lb[1], iL[1]);
-                const float dz = min_img(ri.z - o.z, Lb[2], iL[2]);
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const bool use = (o.idx != me) && (cv.rcut2 <= 0.f || r2 < cv.rcut2);
-                float sv, f;
-                switch_fn(r2, cv, sv, f);
-                sv = use ? sv : 0.f;
-                f = use ? f : 0.f;
-                s8 += sv;
-                x8 = fmaf(f, dx, x8);
-                y8 = fmaf(f, dy, y8);
-                z8 = fmaf(f, dz, z8);
+                for (int q = 0; q < 8; ++q) {
+                    const int jj = j + q * L;
+                    if (jj >= jn) break;
+                    const Partner o = oth[jj];
+                    const float dx = min_img(ri.x - o.x, Lb[0], iL[0]);
+                    const float dy = min_img(ri.y - o.y, Lb[1], iL[1]);
+                    const float dz = min_img(ri.z - o.z, Lb[2], iL[2]);
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    bool use = o.idx != me;
+                    if (CUT) {
+                        if (fabsf(r2 - cv.rcut2) <= 1e-5f * cv.rcut2)  // rare: the edge of the cut
+                            use = use && cut_inside_exact(ri.x, ri.y, ri.z, o.x, o.y, o.z, Lb[0], Lb[1], Lb[2], cv.rcut);
+                        else
+                            use = use && r2 < cv.rcut2;
+                    }
+                    float sv, f;
+                    switch_fn(r2, cv, sv, f);
+                    sv = use ? sv : 0.f;
+                    f = use ? f : 0.f;
+                    s8 += sv;
+                    x8 = fmaf(f, dx, x8);
+                    y8 = fmaf(f, dy, y8);
+                    z8 = fmaf(f, dz, z8);
+                }
+                S += s8;
+                gx += x8;
+                gy += y8;
+                gz += z8;
             }
-            S += s8;
-            gx += x8;
-            gy += y8;
-            gz += z8;
-        }
+        };
+        if (cv.rcut > 0.0)
+            pairs(std::true_type{});
+        else
+            pairs(std::false_type{});
     }
     for (int o = 1; o < L; o <<= 1) {  // within the member's lanes (aligned groups of a wavefront)
         S += __shfl_xor(S, o, 64);

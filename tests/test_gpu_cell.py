@@ -119,6 +119,50 @@ def test_cell_results_repeat_bitwise(gpu):
         assert np.array_equal(xi, runs[0][0]) and np.array_equal(pb, runs[0][1])
 
 
+@pytest.mark.parametrize("mode", [1, -1])
+def test_cut_edge_decisions_match_oracle(gpu, mode):
+    """Pairs placed at the hard cut, r = rcut (1 + delta) for delta from
+    -3e-5 to 3e-5 (the FP32 float positions move each by ~2e-7 relative),
+    some across the periodic boundary: every pair must fall on the side the
+    FP64 definition puts it (inside unless r >= rcut, from the positions as
+    given), through the cell lists (mode 1) and all pairs (mode -1).  One
+    pair decided the other way moves the unnormalised CN by s(rcut) = 5.2e-3;
+    the test allows a fifth of that."""
+    W, na, L, rc = 2, 64, 4.0, 1.2
+    deltas = np.array([-3e-5, -8e-6, -2e-6, -2e-7, -1e-8, 1e-8, 2e-7, 2e-6, 8e-6, 3e-5])
+    g = np.random.default_rng(28)
+    blocks = []
+    for w in range(W):
+        a = g.uniform(0.0, L, size=(na, 3))
+        u = g.normal(size=(na, deltas.size, 3))
+        u /= np.linalg.norm(u, axis=2, keepdims=True)
+        b = (a[:, None, :] + rc * (1.0 + deltas)[None, :, None] * u).reshape(-1, 3)
+        blocks.append(np.concatenate([a, np.mod(b, L)]))  # partners wrapped into the box
+    pos = np.concatenate(blocks).astype(np.float32)
+    n = na * (1 + deltas.size)
+    off = np.arange(W + 1, dtype=np.int64) * n
+    cvs = [{"kind": "coordination", "a": list(range(na)), "b": list(range(na, n)), "r0": 0.5, "n": 6, "m": 12,
+            "rcut": rc, "normalize": False}]
+    s = ctx(cvs, L, off, mode)
+    assert s.cell_list_cvs() == (1 if mode == 1 else 0)
+    P = dev(pos)
+    xi = s.eval_cv(P)[0].cpu().numpy()
+    xb = np.random.default_rng(29).normal(size=(W, 1))
+    pb = torch.zeros_like(P)
+    s.cv_vjp(P, dev(xb), pb)
+    pb = pb.cpu().numpy()
+    s_cut = 1.0 / (1.0 + (rc / 0.5) ** 6)
+    for w in range(W):
+        pw = pos[off[w]:off[w + 1]]
+        xr, J = oracle_walker(pw, cvs, L)
+        d = pw[na:].astype(np.float64).reshape(na, deltas.size, 3) - pw[:na, None, :].astype(np.float64)
+        d -= L * np.rint(d / L)
+        r = np.sqrt(np.sum(d * d, axis=2))
+        assert np.sum(r < rc) > 0 and np.sum(r >= rc) > 0  # both sides of the cut are present
+        assert abs(xi[w, 0] - xr[0]) <= 0.2 * s_cut
+        assert rel_inf(pb[off[w]:off[w + 1]], np.tensordot(xb[w], J, axes=1)) <= 1e-5
+
+
 def test_cell_values_orthorhombic_box(gpu):
     """An orthorhombic box with a different cell count per dimension
     (4.0 x 5.3 x 7.9 nm: 3, 4 and 6 cut-length cells, z cut further into
