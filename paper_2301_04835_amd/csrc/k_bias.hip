@@ -160,10 +160,11 @@ __device__ __forceinline__ void finish_dihedral(const HillArgs &a, const CvSet &
 // centre array and of the heights at float4 index q0 + u * kBlock, from
 // uniform (scalar) base pointers with 32-bit lane offsets; the scheduling
 // barrier keeps every load of the batch ahead of the arithmetic.
-// One tile: partial (V, sum e D_d) of hills [h0, h0 + 1024 U) of one walker.
+// One tile: partial (V, sum e D_d) of hills [h0, h0 + 1024 U) of one walker,
+// stored as the tile's record and left in thread 0's `sum`.
 template <int D, int U, bool FUSE, typename T>
 __device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, const PosView &pos, int t, double *lds,
-                                          double *s_xi)
+                                          double *s_xi, double (&sum)[1 + D])
 {
     constexpr int UB = U < kBatch ? U : kBatch;
         const TileRec tr = ld_uniform(a.tiles + t);
@@ -247,6 +248,8 @@ __device__ __forceinline__ void hill_tile(const HillArgs &a, const CvSet &cs, co
 #pragma unroll
             for (int j = 0; j <= D; ++j) p[j] = acc[j];
         }
+#pragma unroll
+        for (int j = 0; j <= D; ++j) sum[j] = acc[j];
 }
 
 // One workgroup per tile: the tile record is read before any store, so it
@@ -257,7 +260,8 @@ __global__ void __launch_bounds__(kBlock) k_hill_tiles(HillArgs a, CvSet cs, Pos
     __shared__ double lds[(1 + D) * (kBlock / 64)];
     __shared__ double s_xi[D];
     if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
-    hill_tile<D, U, FUSE, T>(a, cs, pos, blockIdx.x, lds, s_xi);
+    double sum[1 + D];
+    hill_tile<D, U, FUSE, T>(a, cs, pos, blockIdx.x, lds, s_xi, sum);
 }
 
 // Persistent grid: each workgroup strides over the tiles.
@@ -268,7 +272,8 @@ __global__ void __launch_bounds__(kBlock) k_hill_tiles_persist(HillArgs a, CvSet
     __shared__ double s_xi[D];
     if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
     for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        hill_tile<D, U, FUSE, T>(a, cs, pos, __builtin_amdgcn_readfirstlane(t), lds, s_xi);
+        double sum[1 + D];
+        hill_tile<D, U, FUSE, T>(a, cs, pos, __builtin_amdgcn_readfirstlane(t), lds, s_xi, sum);
         __syncthreads();  // lds / s_xi reuse by the next tile
     }
 }
@@ -282,39 +287,15 @@ __device__ __forceinline__ int32_t live_tiles(const HillArgs &a, const WalkerRec
     return min(wr.nt, max(1, (cnt + T - 1) / T));
 }
 
-template <int D, bool FUSE>
-__global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, PosView pos)
+// Kernel B's work once the walker's sum is in thread 0's acc: V, dV/dxi and
+// the outputs, the deposit (thread 0), then the forces (every thread; the
+// small table's rows were requested by lanes u < U before the sum).
+template <int D>
+__device__ __forceinline__ void finalize_tail(const HillArgs &a, int32_t w, const WalkerRec &wr, int32_t cnt0,
+                                              int64_t next_step, const double (&acc)[1 + D], const double *s_xi,
+                                              double *s_coef, bool small_lane, const SmallGather &sg, int nent,
+                                              const int32_t (&cvq)[kSmallPer], const float (&jr)[kSmallPer][3])
 {
-    __shared__ double lds[(1 + D) * (kBlock / 64)];
-    __shared__ double s_coef[kMaxCv];
-    __shared__ double s_xi[kMaxBiasDim];
-    const int32_t w = blockIdx.x;
-    const WalkerRec wr = ld_uniform(a.wrec + w);
-    // values thread 0 needs after the reduction, requested up front; the
-    // step counter was set by kernel A and is constant during this kernel
-    const int64_t next_step = a.deposit == 1 ? ld_uniform(a.dstep) : 0;
-    const int32_t cnt0 = ld_uniform(a.count + w);
-    const int32_t nlive = live_tiles(a, wr, cnt0);
-    // small gather table: lane u < U requests its atom's force and the
-    // Jacobian rows it will combine before the reduction, so that only the
-    // multiply-adds and the stores follow the barrier
-    const bool small_lane = a.do_forces && a.small.on && (int)threadIdx.x < a.small.U;
-    SmallGather sg{0.f, 0.f, 0.f, nullptr};
-    int nent = 0;
-    int32_t cvq[kSmallPer];
-    float jr[kSmallPer][3];
-    if (small_lane)
-        small_rows(a.small, a.J + (int64_t)w * a.nslots * 3, a.F, wr.aoff, threadIdx.x, sg, nent, cvq, jr);
-    if ((int)threadIdx.x < D) s_xi[threadIdx.x] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + threadIdx.x];
-    double acc[1 + D];
-#pragma unroll
-    for (int j = 0; j <= D; ++j) acc[j] = 0.0;
-    for (int i = threadIdx.x; i < nlive; i += kBlock) {
-        const double *p = a.partial + (int64_t)(wr.t0 + i) * 4;
-#pragma unroll
-        for (int j = 0; j <= D; ++j) acc[j] += p[j];
-    }
-    block_sum0<1 + D>(acc, lds);  // also orders the s_xi writes
     if (threadIdx.x == 0) {
         const double V = acc[0];
         bool finite = isfinite(V);
@@ -366,6 +347,42 @@ __global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, 
     } else {
         gather_forces(a.tabs, a.J + (int64_t)w * a.nslots * 3, w, s_coef, a.F);
     }
+}
+
+template <int D, bool FUSE>
+__global__ void __launch_bounds__(kBlock) k_hill_finalize(HillArgs a, CvSet cs, PosView pos)
+{
+    __shared__ double lds[(1 + D) * (kBlock / 64)];
+    __shared__ double s_coef[kMaxCv];
+    __shared__ double s_xi[kMaxBiasDim];
+    const int32_t w = blockIdx.x;
+    const WalkerRec wr = ld_uniform(a.wrec + w);
+    // values thread 0 needs after the reduction, requested up front; the
+    // step counter was set by kernel A and is constant during this kernel
+    const int64_t next_step = a.deposit == 1 ? ld_uniform(a.dstep) : 0;
+    const int32_t cnt0 = ld_uniform(a.count + w);
+    const int32_t nlive = live_tiles(a, wr, cnt0);
+    // small gather table: lane u < U requests its atom's force and the
+    // Jacobian rows it will combine before the reduction, so that only the
+    // multiply-adds and the stores follow the barrier
+    const bool small_lane = a.do_forces && a.small.on && (int)threadIdx.x < a.small.U;
+    SmallGather sg{0.f, 0.f, 0.f, nullptr};
+    int nent = 0;
+    int32_t cvq[kSmallPer];
+    float jr[kSmallPer][3];
+    if (small_lane)
+        small_rows(a.small, a.J + (int64_t)w * a.nslots * 3, a.F, wr.aoff, threadIdx.x, sg, nent, cvq, jr);
+    if ((int)threadIdx.x < D) s_xi[threadIdx.x] = (FUSE ? a.xi_save : a.xi)[(int64_t)w * D + threadIdx.x];
+    double acc[1 + D];
+#pragma unroll
+    for (int j = 0; j <= D; ++j) acc[j] = 0.0;
+    for (int i = threadIdx.x; i < nlive; i += kBlock) {
+        const double *p = a.partial + (int64_t)(wr.t0 + i) * 4;
+#pragma unroll
+        for (int j = 0; j <= D; ++j) acc[j] += p[j];
+    }
+    block_sum0<1 + D>(acc, lds);  // also orders the s_xi writes
+    finalize_tail<D>(a, w, wr, cnt0, next_step, acc, s_xi, s_coef, small_lane, sg, nent, cvq, jr);
 }
 
 // The same finalize in one wavefront, for steps that gather forces through a
@@ -469,6 +486,56 @@ __global__ void __launch_bounds__(64) k_hill_finalize_wave(HillArgs a, CvSet cs,
     }
 }
 
+// The whole step in one launch when all the hills are one tile (one walker
+// whose capacity fits a tile): the workgroup sums the tile, then does kernel
+// B's work on its own sum -- the same bits kernel B would form from the one
+// record -- with the Jacobian rows and CV values it wrote itself (visible to
+// it after the sum's barriers) and the step counter it set itself.
+template <int D, int U, bool FUSE, typename T>
+__global__ void __launch_bounds__(kBlock) k_hill_step_one_tile(HillArgs a, CvSet cs, PosView pos)
+{
+    __shared__ double lds[(1 + D) * (kBlock / 64)];
+    __shared__ double s_xi[kMaxBiasDim];
+    __shared__ double s_coef[kMaxCv];
+    int64_t next_step = 0;  // thread 0 alone decides the deposit
+    if (threadIdx.x == 0) {
+        if (a.count_step) {
+            next_step = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
+            *a.dstep = next_step;
+        } else if (a.deposit == 1) {
+            next_step = *a.dstep;
+        }
+    }
+    double acc[1 + D];
+    hill_tile<D, U, FUSE, T>(a, cs, pos, 0, lds, s_xi, acc);
+    const WalkerRec wr = ld_uniform(a.wrec);
+    const int32_t cnt0 = ld_uniform(a.count);  // what the tile saw: only the deposit below changes it
+    const bool small_lane = a.do_forces && a.small.on && (int)threadIdx.x < a.small.U;
+    SmallGather sg{0.f, 0.f, 0.f, nullptr};
+    int nent = 0;
+    int32_t cvq[kSmallPer];
+    float jr[kSmallPer][3];
+    if (small_lane) small_rows(a.small, a.J, a.F, wr.aoff, threadIdx.x, sg, nent, cvq, jr);
+    if (!FUSE) {
+        if ((int)threadIdx.x < D) s_xi[threadIdx.x] = a.xi[threadIdx.x];
+        __syncthreads();
+    }
+    finalize_tail<D>(a, 0, wr, cnt0, next_step, acc, s_xi, s_coef, small_lane, sg, nent, cvq, jr);
+}
+
+template <int D, bool FUSE, typename T>
+hipError_t launch_step_one_tile(const HillArgs &a, const CvSet &cs, const PosView &pos, hipStream_t s)
+{
+    switch (a.tile_units) {
+    case 1: hipLaunchKernelGGL((k_hill_step_one_tile<D, 1, FUSE, T>), dim3(1), dim3(kBlock), 0, s, a, cs, pos); break;
+    case 2: hipLaunchKernelGGL((k_hill_step_one_tile<D, 2, FUSE, T>), dim3(1), dim3(kBlock), 0, s, a, cs, pos); break;
+    case 4: hipLaunchKernelGGL((k_hill_step_one_tile<D, 4, FUSE, T>), dim3(1), dim3(kBlock), 0, s, a, cs, pos); break;
+    case 8: hipLaunchKernelGGL((k_hill_step_one_tile<D, 8, FUSE, T>), dim3(1), dim3(kBlock), 0, s, a, cs, pos); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int D, bool FUSE, typename T>
 hipError_t launch_tiles(const HillArgs &a, const CvSet &cs, const PosView &pos, int32_t g, hipStream_t s)
 {
@@ -496,6 +563,9 @@ hipError_t launch_hill_d(const HillArgs &a, const CvSet &cs, const PosView &pos,
                          int which)
 {
     const int g = (grid > 0 && grid < a.ntiles) ? grid : a.ntiles;
+    if (which == 3 && a.ntiles == 1)
+        return (FUSE && pos.f64) ? launch_step_one_tile<D, FUSE, double>(a, cs, pos, s)
+                                 : launch_step_one_tile<D, FUSE, float>(a, cs, pos, s);
     if (which & 1) {
         hipError_t e = (FUSE && pos.f64) ? launch_tiles<D, FUSE, double>(a, cs, pos, g, s)
                                          : launch_tiles<D, FUSE, float>(a, cs, pos, g, s);

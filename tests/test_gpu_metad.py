@@ -80,6 +80,46 @@ def test_wtmd22_1000_steps(gpu):
     assert rel_inf(h2[2000:], np.array(Hr[2000:])) <= 1e-6
 
 
+def test_one_tile_step_matches_the_two_kernel_step(gpu):
+    """A single walker whose capacity fits one tile takes the one-launch step
+    (the workgroup that sums the tile also finalizes); the same walker beside
+    a second one takes the tile kernel and the finalize kernel.  With a
+    deposit every step over 40 steps, walker 0's xi, V, dV/dxi, forces and
+    hills agree bit for bit between the two."""
+    p = synth.WTMD22
+    T = 40
+    d = synth.wtmd22_inputs(n_steps=T)
+    cvs, C = d["cvs"], d["centers"]
+    H = np.full(C.shape[0], p["w"], dtype=np.float32)
+    cap = C.shape[0] + 64
+    one = make_metad(cvs, p["sigma"], p["w"], p["T"], p["bias_factor"], 1, capacity=cap)
+    two = make_metad(cvs, p["sigma"], p["w"], p["T"], p["bias_factor"], 1, capacity=cap,
+                     atom_off=np.array([0, 22, 44]), hill_capacity=[cap, cap])
+    one.hills_set(0, C, H)
+    two.hills_set(0, C, H)
+    two.hills_set(1, C[::-1].copy(), H)
+    f1 = dev(d["frames"])
+    f2 = dev(np.concatenate([d["frames"], d["frames"][::-1]], axis=1))
+    z = lambda *sh, dt=torch.float64: torch.zeros(sh, dtype=dt, device=gpu)
+    o1 = (z(T, 22, 3, dt=torch.float32), z(T, 1, 2), z(T, 1), z(T, 1, 2))
+    o2 = (z(T, 44, 3, dt=torch.float32), z(T, 2, 2), z(T, 2), z(T, 2, 2))
+    for t in range(T):
+        one.step(f1[t], forces=o1[0][t], step=t, xi_out=o1[1][t], V_out=o1[2][t], dV_out=o1[3][t])
+        two.step(f2[t], forces=o2[0][t], step=t, xi_out=o2[1][t], V_out=o2[2][t], dV_out=o2[3][t])
+    one.check()
+    two.check()
+    F1, x1, V1, dV1 = (x.cpu().numpy() for x in o1)
+    F2, x2, V2, dV2 = (x.cpu().numpy() for x in o2)
+    assert np.array_equal(F1, F2[:, :22]) and np.any(F1 != 0)
+    assert np.array_equal(x1[:, 0], x2[:, 0])
+    assert np.array_equal(V1[:, 0], V2[:, 0])
+    assert np.array_equal(dV1[:, 0], dV2[:, 0])
+    c1, h1 = one.hills_get(0)
+    c2, h2 = two.hills_get(0)
+    assert c1.shape[0] == C.shape[0] + T
+    assert np.array_equal(c1, c2) and np.array_equal(h1, h2)
+
+
 def test_sequential_deposits_follow_wt_law(gpu):
     """Heights of hills deposited one after another obey h = w exp(-V/(k dT))."""
     K = 300
