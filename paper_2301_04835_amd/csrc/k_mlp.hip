@@ -109,33 +109,42 @@ __device__ __forceinline__ uint8_t fallback_flag(const MlpArgs &a, const double 
     return (inside && a.mask[cell]) ? 0 : 1;
 }
 
-// A surrogate step's CVs (every CV a dihedral) for sample si: all D x 4
-// positions requested before any angle is formed, then each angle and its
-// gradient in FP64, xi and the Jacobian slots stored.
+// A surrogate step's CVs (every CV a dihedral): dihedral d of sample si,
+// its four positions requested by dihedral_atoms at the start of the
+// kernel, the angle and its gradient formed in FP64 by step_dihedral, which
+// stores xi and the Jacobian slots.
 template <typename T, int D>
-__device__ __forceinline__ void step_dihedrals(const MlpStep &st, int64_t si, double (&x)[D])
+__device__ __forceinline__ void dihedral_atoms(const MlpStep &st, int64_t si, int d, double3 (&r)[4])
 {
     const int64_t aoff = st.tabs.atom_off[si];
-    double3 r[D][4];
+    int32_t at[4];
 #pragma unroll
-    for (int d = 0; d < D; ++d)
+    for (int q = 0; q < 4; ++q) at[q] = st.cs.cv[0].atom[q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) r[d][q] = ld_pos_t<T>(st.pos, aoff + st.cs.cv[d].atom[q]);
-    __builtin_amdgcn_sched_barrier(0);  // keep every load above the first angle's arithmetic
+    for (int dd = 1; dd < D; ++dd)
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const CvDesc &cv = st.cs.cv[d];
-        double3 g[4];
-        x[d] = dihedral_fp64<true>(r[d], g);
-        st.xi_ws[si * D + d] = x[d];
-        float *js = st.J + (si * st.nslots + cv.slot0) * 3;
+        for (int q = 0; q < 4; ++q) at[q] = d == dd ? st.cs.cv[dd].atom[q] : at[q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            js[3 * q] = (float)g[q].x;
-            js[3 * q + 1] = (float)g[q].y;
-            js[3 * q + 2] = (float)g[q].z;
-        }
+    for (int q = 0; q < 4; ++q) r[q] = ld_pos_t<T>(st.pos, aoff + at[q]);
+}
+
+template <int D>
+__device__ __forceinline__ double step_dihedral(const MlpStep &st, int64_t si, int d, const double3 (&r)[4])
+{
+    int32_t slot0 = st.cs.cv[0].slot0;
+#pragma unroll
+    for (int dd = 1; dd < D; ++dd) slot0 = d == dd ? st.cs.cv[dd].slot0 : slot0;
+    double3 g[4];
+    const double x = dihedral_fp64<true>(r, g);
+    st.xi_ws[si * D + d] = x;
+    float *js = st.J + (si * st.nslots + slot0) * 3;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        js[3 * q] = (float)g[q].x;
+        js[3 * q + 1] = (float)g[q].y;
+        js[3 * q + 2] = (float)g[q].z;
     }
+    return x;
 }
 
 template <int H, int D, bool CVF>
@@ -147,6 +156,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
     constexpr int KB = H / 32;  // 32-wide K blocks of the H x H product
     constexpr int NT = H / 16;  // 16-wide output tiles
     constexpr POff o = poff(H, F);
+    static_assert(D <= 4, "a surrogate step gives each dihedral one of the four row groups");
     __shared__ double s_coef[kSamplesPerWave][D];  // surrogate step: -dV/dxi per sample
     __shared__ uint8_t s_fb[kSamplesPerWave];
     const int lane = threadIdx.x & 63;
@@ -157,8 +167,17 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
     const int row = lane & 15, kg = lane >> 4;
     const int64_t si = s0 + row;  // this lane's sample in the A operand
     const bool live = si < n;
-    // a surrogate step: this lane's layer-1 weights and layer-2 fragments
-    // requested before the CVs, so that they arrive during the position loads
+    // a surrogate step: the lanes of row group kg < D evaluate dihedral kg
+    // of their walker; its positions are requested first, then this lane's
+    // layer-1 weights and layer-2 fragments, which arrive during the angles
+    const bool cv_lane = CVF && live && kg < D;
+    double3 rr[4];
+    if (cv_lane) {
+        if (st.pos.f64)
+            dihedral_atoms<double, D>(st, si, kg, rr);
+        else
+            dihedral_atoms<float, D>(st, si, kg, rr);
+    }
     float w1p[CVF ? KB : 1][8][F], b1p[CVF ? KB : 1][8];
     bf16x8 w2p[CVF ? NT : 1][CVF ? KB : 1];
     if (CVF) {
@@ -179,20 +198,12 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
     }
     double x[D];
     if (CVF) {
-        // the 16 lanes of row group 0 evaluate their walker's dihedrals
-        // (FP64) and store xi and the Jacobian slots; a shuffle hands xi to
-        // the lanes of the other row groups
-        if (kg == 0 && live) {
-            if (st.pos.f64)
-                step_dihedrals<double, D>(st, si, x);
-            else
-                step_dihedrals<float, D>(st, si, x);
-        } else {
+        // lane (kg, row) with kg < D forms dihedral kg of sample `row` (FP64)
+        // and stores it and its Jacobian slots; shuffles hand every lane its
+        // sample's D angles
+        const double xd = cv_lane ? step_dihedral<D>(st, si, kg, rr) : 0.0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) x[d] = 0.0;
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d) x[d] = __shfl(x[d], row, 64);
+        for (int d = 0; d < D; ++d) x[d] = __shfl(xd, d * 16 + row, 64);
     } else {
 #pragma unroll
         for (int d = 0; d < D; ++d) x[d] = live ? xi[si * D + d] : 0.0;
