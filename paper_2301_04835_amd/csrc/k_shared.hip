@@ -336,29 +336,65 @@ __global__ void __launch_bounds__(64) k_hill_shared_finalize_wave(SharedArgs a)
 }
 
 // Fallback sums of a surrogate step (the few walkers outside certified
-// cells): one workgroup per (flagged walker, chunk of kQmChunk hills), lanes
-// over hills with float4 loads all issued before use (the list is read from
-// L2 once per fallback walker), a fixed-order reduction, one partial record
-// per (chunk, walker); the finalize kernel then sums a walker's chunks in
-// order.  Workgroups of walkers the network serves leave at once.
+// cells): workgroup (c, y) sums chunk c of kQmChunk hills for its walkers,
+// lanes over hills with float4 loads all issued before use (the chunk is
+// read from L2 once per workgroup and kept in registers for all of its
+// walkers), a fixed-order reduction, one partial record per (chunk,
+// walker); the finalize kernel then sums a walker's chunks in order.
+// COMPACT (at most kQmCompactMax queries): gridDim.y = min(queries,
+// kQmSlots) rows, row y taking the flagged walkers of rank y, y + rows, ...
+// in walker order, so the grid does not grow with the walkers the network
+// serves; otherwise row y is walker y and leaves at once unless flagged.
+// A walker's records do not depend on which workgroup formed them.
 constexpr int kQmChunk = 4096;               // hills per workgroup
 constexpr int kQmGroups = kQmChunk / (4 * kBlock);  // float4 groups per lane
+constexpr int kQmSlots = 32;                 // workgroup rows of the compacted grid
+constexpr int kQmCompactMax = 1024;          // largest query count it serves
+constexpr int kQmPerRow = kQmCompactMax / kQmSlots;  // walkers one row takes at most
 
-template <int D, int PER>
+template <int D, int PER, bool COMPACT>
 __global__ void __launch_bounds__(kBlock) k_hill_shared_qm(SharedArgs a)
 {
     __shared__ double lds[(1 + D) * (kBlock / 64)];
-    const int64_t w = blockIdx.y;
-    if (a.count_step && blockIdx.x == 0 && w == 0 && threadIdx.x == 0)
+    __shared__ int32_t s_list[COMPACT ? kQmPerRow : 1];
+    __shared__ int32_t s_nw;
+    if (a.count_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
-    if (!a.fb[w]) return;  // uniform per workgroup
+    int nw = 1;
+    if (COMPACT) {
+        // wavefront 0 ranks the flagged walkers in order and lists this row's
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const unsigned long long below = (1ull << lane) - 1ull;
+            int base = 0, mine = 0;
+            for (int64_t b0 = 0; b0 < a.nq; b0 += 64) {
+                const int64_t ww = b0 + lane;
+                const bool f = ww < a.nq && a.fb[ww];
+                const unsigned long long m = __ballot(f);
+                const bool take = f && (base + __popcll(m & below)) % (int)gridDim.y == (int)blockIdx.y;
+                const unsigned long long mt = __ballot(take);
+                if (take) s_list[mine + __popcll(mt & below)] = (int32_t)ww;  // < kQmPerRow: at most nq / rows
+                mine += __popcll(mt);
+                base += __popcll(m);
+            }
+            if (lane == 0) s_nw = mine;
+        }
+        __syncthreads();
+        nw = s_nw;
+    } else if (!a.fb[blockIdx.y]) {
+        return;  // uniform per workgroup
+    }
+    if (nw == 0) return;  // uniform
     const int32_t n = *a.count;
     const int64_t h0 = (int64_t)blockIdx.x * kQmChunk;
     if (h0 >= n) {  // uniform: a chunk past the count adds zero (the finalize sums every chunk)
-        if (threadIdx.x <= D) a.partial[((int64_t)blockIdx.x * a.nq + w) * 4 + threadIdx.x] = 0.0;
+        for (int iw = 0; iw < nw; ++iw) {
+            const int64_t w = COMPACT ? (int64_t)s_list[iw] : (int64_t)blockIdx.y;
+            if (threadIdx.x <= D) a.partial[((int64_t)blockIdx.x * a.nq + w) * 4 + threadIdx.x] = 0.0;
+        }
         return;
     }
-    double sc[D], per[D], iper[D], xs[D];
+    double sc[D], per[D], iper[D];
     bool wrap[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -366,7 +402,6 @@ __global__ void __launch_bounds__(kBlock) k_hill_shared_qm(SharedArgs a)
         wrap[d] = PER == kPerAll || (PER == kPerMixed && a.period[d] > 0.0);
         per[d] = a.period[d] * sc[d];
         iper[d] = a.inv_period[d] / sc[d];
-        xs[d] = a.xi[w * D + d] * sc[d];
     }
     // groups of 4 hills; the list's storage is padded to a multiple of 4
     // floats and 16-byte aligned: a group past the count reads group 0 and
@@ -382,37 +417,43 @@ __global__ void __launch_bounds__(kBlock) k_hill_shared_qm(SharedArgs a)
         for (int d = 0; d < D; ++d) cv[it][d] = *reinterpret_cast<const float4 *>(a.c[d] + ks);
         hv[it] = *reinterpret_cast<const float4 *>(a.h + ks);
     }
-    double acc[1 + D];
+    for (int iw = 0; iw < nw; ++iw) {
+        const int64_t w = COMPACT ? (int64_t)s_list[iw] : (int64_t)blockIdx.y;
+        double xs[D];
 #pragma unroll
-    for (int j = 0; j <= D; ++j) acc[j] = 0.0;
+        for (int d = 0; d < D; ++d) xs[d] = a.xi[w * D + d] * sc[d];
+        double acc[1 + D];
 #pragma unroll
-    for (int it = 0; it < kQmGroups; ++it) {
-        const int64_t k = kk[it];
-        const float hh[4] = {k < n ? hv[it].x : 0.f, k + 1 < n ? hv[it].y : 0.f, k + 2 < n ? hv[it].z : 0.f,
-                             k + 3 < n ? hv[it].w : 0.f};
+        for (int j = 0; j <= D; ++j) acc[j] = 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double x[D], qd = 0.0;
+        for (int it = 0; it < kQmGroups; ++it) {
+            const int64_t k = kk[it];
+            const float hh[4] = {k < n ? hv[it].x : 0.f, k + 1 < n ? hv[it].y : 0.f, k + 2 < n ? hv[it].z : 0.f,
+                                 k + 3 < n ? hv[it].w : 0.f};
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const float4 &c4 = cv[it][d];
-                const float c = j == 0 ? c4.x : (j == 1 ? c4.y : (j == 2 ? c4.z : c4.w));
-                x[d] = xs[d] - (double)c * sc[d];
-                if (wrap[d]) x[d] = fma(-per[d], rint(x[d] * iper[d]), x[d]);
-                qd = fma(x[d], x[d], qd);
+            for (int j = 0; j < 4; ++j) {
+                double x[D], qd = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const float4 &c4 = cv[it][d];
+                    const float c = j == 0 ? c4.x : (j == 1 ? c4.y : (j == 2 ? c4.z : c4.w));
+                    x[d] = xs[d] - (double)c * sc[d];
+                    if (wrap[d]) x[d] = fma(-per[d], rint(x[d] * iper[d]), x[d]);
+                    qd = fma(x[d], x[d], qd);
+                }
+                const double e = (double)(hh[j] * __builtin_amdgcn_exp2f(-(float)qd));
+                acc[0] += e;
+#pragma unroll
+                for (int d = 0; d < D; ++d) acc[1 + d] = fma(e, x[d], acc[1 + d]);
             }
-            const double e = (double)(hh[j] * __builtin_amdgcn_exp2f(-(float)qd));
-            acc[0] += e;
-#pragma unroll
-            for (int d = 0; d < D; ++d) acc[1 + d] = fma(e, x[d], acc[1 + d]);
         }
-    }
-    block_sum0<1 + D>(acc, lds);
-    if (threadIdx.x == 0) {
-        double *p = a.partial + ((int64_t)blockIdx.x * a.nq + w) * 4;
-        p[0] = acc[0];
+        block_sum0<1 + D>(acc, lds);  // ends with a barrier: lds is free for the next walker
+        if (threadIdx.x == 0) {
+            double *p = a.partial + ((int64_t)blockIdx.x * a.nq + w) * 4;
+            p[0] = acc[0];
 #pragma unroll
-        for (int d = 0; d < D; ++d) p[1 + d] = acc[1 + d] / sc[d];  // back to CV units
+            for (int d = 0; d < D; ++d) p[1 + d] = acc[1 + d] / sc[d];  // back to CV units
+        }
     }
 }
 
@@ -445,10 +486,18 @@ hipError_t launch_shared_d(const SharedArgs &a, hipStream_t s)
             any = any || a.period[d] > 0.0;
             all = all && a.period[d] > 0.0;
         }
-        const dim3 g(b.nchunk, (unsigned)a.nq);
-        if (all) hipLaunchKernelGGL((k_hill_shared_qm<D, kPerAll>), g, dim3(kBlock), 0, s, b);
-        else if (!any) hipLaunchKernelGGL((k_hill_shared_qm<D, kPerNone>), g, dim3(kBlock), 0, s, b);
-        else hipLaunchKernelGGL((k_hill_shared_qm<D, kPerMixed>), g, dim3(kBlock), 0, s, b);
+        const int per = all ? kPerAll : (any ? kPerMixed : kPerNone);
+        if (a.nq <= kQmCompactMax) {
+            const dim3 g(b.nchunk, (unsigned)std::min<int64_t>(a.nq, kQmSlots));
+            if (per == kPerAll) hipLaunchKernelGGL((k_hill_shared_qm<D, kPerAll, true>), g, dim3(kBlock), 0, s, b);
+            else if (per == kPerNone) hipLaunchKernelGGL((k_hill_shared_qm<D, kPerNone, true>), g, dim3(kBlock), 0, s, b);
+            else hipLaunchKernelGGL((k_hill_shared_qm<D, kPerMixed, true>), g, dim3(kBlock), 0, s, b);
+        } else {
+            const dim3 g(b.nchunk, (unsigned)a.nq);
+            if (per == kPerAll) hipLaunchKernelGGL((k_hill_shared_qm<D, kPerAll, false>), g, dim3(kBlock), 0, s, b);
+            else if (per == kPerNone) hipLaunchKernelGGL((k_hill_shared_qm<D, kPerNone, false>), g, dim3(kBlock), 0, s, b);
+            else hipLaunchKernelGGL((k_hill_shared_qm<D, kPerMixed, false>), g, dim3(kBlock), 0, s, b);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (small_finalize(b))

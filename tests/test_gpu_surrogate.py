@@ -26,7 +26,7 @@ from oracle import _clib as oracle
 from oracle import methods, mlp
 from paper_2301_04835_amd import synth, synth_wt
 from paper_2301_04835_amd.api import Sampler, SxError
-from gpu_util import TWO_PI, dev, rel_inf
+from gpu_util import TWO_PI, dev, hill_grad_bound, hill_v_rel_bound, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -282,14 +282,18 @@ def test_surrogate_step_against_exact(c4):
     s.surrogate_enable(False)
 
 
-def test_fallback_with_spare_capacity(gpu):
+@pytest.mark.parametrize("W", [8, 40, 1100])
+def test_fallback_with_spare_capacity(gpu, W):
     """A shared list filled to a fraction of its capacity (3,000 hills in
     room for 15,000: the fallback sums' chunks past the count hold no
     hills) and an untrained network that certifies nothing, so every walker
     takes the exact fallback, right after a certification pass has left
-    other records in the same workspace: V and dV/dxi of every walker at the
-    exact path's bar against the oracle."""
-    W, K, cap = 8, 3000, 15000
+    other records in the same workspace: V and dV/dxi of every walker
+    against the oracle at the derived bounds of an FP32-term hill sum.  8
+    walkers: one per workgroup row of the fallback grid; 40: rows that sum
+    two walkers from the same loaded chunk; 1,100: more walkers than the
+    compacted grid serves, one row per walker."""
+    K, cap = 3000, 15000
     C = synth.uniform_centers(K, 2, 41)
     H = synth.uniform_heights(K, 42)
     pos, off = synth.chain_walkers(W, 22, seed=43)
@@ -297,7 +301,7 @@ def test_fallback_with_spare_capacity(gpu):
     s.add_cvs(synth.backbone_cvs(4))
     s.set_walkers(off, [cap], shared=True)
     s.metad([0.3, 0.3], 1.0, 300.0, 6.0, 0, cap)
-    s.surrogate(64, max_samples=1024, max_batch=1024, cert_n=32, tol_force=0.1)
+    s.surrogate(64, max_samples=1024, max_batch=2048, cert_n=32, tol_force=0.1)
     s.bind()
     s.hills_set(0, C, H)
     s.surrogate_params(rand_params(64, 2, 44))
@@ -312,10 +316,12 @@ def test_fallback_with_spare_capacity(gpu):
     s.check()
     assert s.surrogate_fallback_count() == W
     xi, V, dV = (t.cpu().numpy() for t in (xi, V, dV))
-    Vr, dVr = oracle.hillsum_batch(xi, None, C.astype(np.float64), H.astype(np.float64), [0.3, 0.3],
-                                   [TWO_PI] * 2, nthreads=8)
-    assert np.max(np.abs(V - Vr) / np.abs(Vr)) <= 1e-6
-    assert max(rel_inf(dV[w], dVr[w]) for w in range(W)) <= 1e-5
+    Cd, Hd = C.astype(np.float64), H.astype(np.float64)
+    Vr, dVr = oracle.hillsum_batch(xi, None, Cd, Hd, [0.3, 0.3], [TWO_PI] * 2, nthreads=8)
+    per, zero = [TWO_PI] * 2, np.zeros((2, 2))
+    for w in range(W):
+        assert abs(V[w] - Vr[w]) <= hill_v_rel_bound(xi[w], Cd, Hd, [0.3, 0.3], per) * abs(Vr[w])
+        assert np.all(np.abs(dV[w] - dVr[w]) <= hill_grad_bound(xi[w], Cd, Hd, [0.3, 0.3], per, zero, np.zeros(2)))
 
 
 def test_surrogate_errors(gpu):
