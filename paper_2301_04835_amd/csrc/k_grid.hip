@@ -127,10 +127,13 @@ __global__ void __launch_bounds__(kBlock) k_grid_step(GridArgs g)
         }
         if (!finite) atomicOr(g.flags, kFlagNonFinite);
         // the step number after this one: the step kernel reads the device
-        // counter, the add kernel that follows advances it
-        const int64_t next_step = g.step >= 0 ? g.step + 1 : *g.dstep + 1;
+        // counter (only where a deposit depends on it), the add kernel that
+        // follows advances it
         bool dep = g.deposit == 2;
-        if (g.deposit == 1 && g.stride > 0) dep = (next_step - 1) % g.stride == 0;
+        if (g.deposit == 1 && g.stride > 0) {
+            const int64_t next_step = g.step >= 0 ? g.step + 1 : *g.dstep + 1;
+            dep = (next_step - 1) % g.stride == 0;
+        }
         if (dep && (inside || g.shared)) {
             // outside the grid nothing is deposited, except that a walker
             // keeps its slot of a shared list (walker order) with a hill of
@@ -151,6 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_grid_step(GridArgs g)
         }
     }
     __syncthreads();
+    if (g.count_in_step && w == 0 && threadIdx.x == 0) *g.dstep = g.step >= 0 ? g.step + 1 : *g.dstep + 1;
     if (g.do_forces) gather_forces(g.tabs, g.J + (int64_t)w * g.nslots * 3, w, s_coef, g.F);
 }
 
@@ -171,6 +175,8 @@ __global__ void __launch_bounds__(64) k_grid_step_wave(GridArgs g)
     const bool dep_cnt = g.deposit == 1 && g.stride > 0;
     const int64_t dstep = dep_cnt && g.step < 0 ? *g.dstep : 0;
     const int32_t cnt = g.deposit ? g.count[l] : 0;
+    // no deposit in this configuration: the counter moves here (nothing reads it in this kernel)
+    if (g.count_in_step && w == 0 && lane == 0) *g.dstep = g.step >= 0 ? g.step + 1 : *g.dstep + 1;
     const WalkerRec wr = g.wrec[l];
     const int64_t aoff = g.tabs.atom_off[w];
     SmallGather sg{0.f, 0.f, 0.f, nullptr};
@@ -398,8 +404,14 @@ hipError_t launch_scale_f64(double *x, int64_t n, double a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_grid_step(const GridArgs &g, hipStream_t s)
+// A configuration that never deposits (deposit off, or on a stride of 0)
+// has nothing for the add kernel but the step counter: the step kernel then
+// advances it and the add kernel is not launched.
+hipError_t launch_grid_step(const GridArgs &g0, hipStream_t s)
 {
+    GridArgs g = g0;
+    const bool add = !(g.deposit == 0 || (g.deposit == 1 && g.stride <= 0));
+    g.count_in_step = add ? 0 : g.count_step;
     if (g.tabs.W < 1 || g.L < 1) return hipErrorInvalidValue;
     const bool wave = g.do_forces && g.small.on && g.small.U > 0;
     if (g.fuse_cv && !wave) return hipErrorInvalidValue;  // only the wavefront step evaluates CVs
@@ -408,7 +420,7 @@ hipError_t launch_grid_step(const GridArgs &g, hipStream_t s)
     else
         hipLaunchKernelGGL(k_grid_step, dim3(g.tabs.W), dim3(kBlock), 0, s, g);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !add) return e;
     hipLaunchKernelGGL(k_grid_add, dim3(g.L), dim3(kAddBlock), 0, s, g);
     return hipGetLastError();
 }

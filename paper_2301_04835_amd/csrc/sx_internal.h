@@ -223,6 +223,7 @@ struct GridArgs {
     const double *xi;                     // W x D
     double *V_ws, *dV_ws, *xi_out, *V_out, *dV_out;  // outputs may be null
     int32_t deposit, count_step, stride;
+    int32_t count_in_step;  // set by the launcher: the step kernel advances the counter (no add kernel follows)
     int64_t step;
     double height, inv_kdT;
     int64_t *dstep;
