@@ -12,15 +12,30 @@
 namespace sx {
 namespace {
 
-// one workgroup per walker; thread 0 owns the window's bookkeeping.  With
-// fuse_cv thread d < D first evaluates dihedral d (FP64) from the positions:
-// its value into LDS and the workspace, its gradient rows into the
-// workspace's Jacobian, which the gather below reads after the barrier.
+// one workgroup per walker; thread 0 owns the window's bookkeeping and
+// requests its centre and running sums before anything waits.  With fuse_cv
+// thread d < D first evaluates dihedral d (FP64) from the positions: its
+// value into LDS and the workspace, its gradient rows into the workspace's
+// Jacobian, which the gather below reads after the barrier.
 __global__ void __launch_bounds__(kBlock) k_harmonic(HarmonicArgs a)
 {
     __shared__ double s_coef[kMaxCv];
     __shared__ double s_xi[kMaxBiasDim];
     const int32_t w = blockIdx.x;
+    // thread 0's window data requested before anything waits
+    double x0[kMaxBiasDim], s1p[kMaxBiasDim], s2p[kMaxBiasDim][kMaxBiasDim];
+    int64_t np0 = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < kMaxBiasDim; ++d) {
+            x0[d] = d < a.D ? a.xi0[(int64_t)w * a.D + d] : 0.0;
+            s1p[d] = (a.accumulate && d < a.D) ? a.s1[(int64_t)w * a.D + d] : 0.0;
+#pragma unroll
+            for (int e = 0; e < kMaxBiasDim; ++e)
+                s2p[d][e] = (a.accumulate && d < a.D && e < a.D) ? a.s2[((int64_t)w * a.D + d) * a.D + e] : 0.0;
+        }
+        if (a.accumulate) np0 = a.n[w];
+    }
     if (a.fuse_cv) {
         if ((int)threadIdx.x < a.D) {
             const CvDesc &cv = a.cs.cv[threadIdx.x];
@@ -44,9 +59,11 @@ __global__ void __launch_bounds__(kBlock) k_harmonic(HarmonicArgs a)
     if (threadIdx.x == 0) {
         double Dv[kMaxBiasDim], V = 0.0;
         bool finite = true;
-        for (int d = 0; d < a.D; ++d) {
+#pragma unroll
+        for (int d = 0; d < kMaxBiasDim; ++d) {
+            if (d >= a.D) break;
             const double x = a.fuse_cv ? s_xi[d] : a.xi[(int64_t)w * a.D + d];
-            double t = x - a.xi0[(int64_t)w * a.D + d];
+            double t = x - x0[d];
             if (a.period[d] > 0.0) t -= a.period[d] * rint(t / a.period[d]);
             Dv[d] = t;
             const double g = a.k[d] * t;
@@ -61,10 +78,14 @@ __global__ void __launch_bounds__(kBlock) k_harmonic(HarmonicArgs a)
         if (a.V_out) a.V_out[w] = V;
         if (!finite || !isfinite(V)) atomicOr(a.flags, kFlagNonFinite);
         if (a.accumulate) {
-            a.n[w] += 1;
-            for (int d = 0; d < a.D; ++d) {
-                a.s1[(int64_t)w * a.D + d] += Dv[d];
-                for (int e = 0; e < a.D; ++e) a.s2[((int64_t)w * a.D + d) * a.D + e] += Dv[d] * Dv[e];
+            a.n[w] = np0 + 1;
+#pragma unroll
+            for (int d = 0; d < kMaxBiasDim; ++d) {
+                if (d >= a.D) break;
+                a.s1[(int64_t)w * a.D + d] = s1p[d] + Dv[d];
+#pragma unroll
+                for (int e = 0; e < kMaxBiasDim; ++e)
+                    if (e < a.D) a.s2[((int64_t)w * a.D + d) * a.D + e] = s2p[d][e] + Dv[d] * Dv[e];
             }
         }
         if (w == 0 && a.count_step) *a.dstep = a.step >= 0 ? a.step + 1 : *a.dstep + 1;
