@@ -168,8 +168,9 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
     const int64_t si = s0 + row;  // this lane's sample in the A operand
     const bool live = si < n;
     // a surrogate step: the lanes of row group kg < D evaluate dihedral kg
-    // of their walker; its positions are requested first, then this lane's
-    // layer-1 weights and layer-2 fragments, which arrive during the angles
+    // of their walker; its positions are requested first, then every weight
+    // this lane will use (layer 1, the layer-2 fragments, b2, w3 and b3),
+    // which arrive during the angles
     const bool cv_lane = CVF && live && kg < D;
     double3 rr[4];
     if (cv_lane) {
@@ -178,9 +179,15 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
         else
             dihedral_atoms<float, D>(st, si, kg, rr);
     }
-    float w1p[CVF ? KB : 1][8][F], b1p[CVF ? KB : 1][8];
+    float w1p[CVF ? KB : 1][8][F], b1p[CVF ? KB : 1][8], b2p[CVF ? NT : 1], w3p[CVF ? NT : 1], b3p = 0.f;
     bf16x8 w2p[CVF ? NT : 1][CVF ? KB : 1];
     if (CVF) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            b2p[nt] = bf(a.Pb, o.b2 + nt * 16 + row);
+            w3p[nt] = bf(a.Pb, o.w3 + nt * 16 + row);
+        }
+        b3p = bf(a.Pb, o.b3);
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
@@ -210,6 +217,10 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
     }
     float f[F], u[D][F];
     featurize<D>(a, x, f, u);
+    // the certification flag of this lane's sample, requested here so that
+    // the mask read overlaps the network
+    int fb_row = 0;
+    if (flag && live) fb_row = fallback_flag<D>(a, x);
     // layer 1 for this lane's 8 K entries of every K block (+ tangents),
     // each split into bf16 hi and lo parts
     bf16x8 av[KB], al[KB], tv[D][KB], tl[D][KB];
@@ -267,7 +278,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
                 tacc[d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tl[d][kb], bv, tacc[d], 0, 0, 0);
             }
         }
-        const float b2 = bf(a.Pb, o.b2 + j), w3 = bf(a.Pb, o.w3 + j);
+        const float b2 = CVF ? b2p[CVF ? nt : 0] : bf(a.Pb, o.b2 + j);
+        const float w3 = CVF ? w3p[CVF ? nt : 0] : bf(a.Pb, o.w3 + j);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float a2 = tanh_fast(acc[r] + b2);
@@ -298,8 +310,11 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int d = 0; d < D; ++d) xo[r][d] = __shfl(x[d], kg * 4 + r, 64);
+    int fbo[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fbo[r] = __shfl(fb_row, kg * 4 + r, 64);
     if (row == 0) {
-        const float b3 = bf(a.Pb, o.b3);
+        const float b3 = CVF ? b3p : bf(a.Pb, o.b3);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t sr = crow0 + r;
@@ -323,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd(MlpArgs a, const double *xi,
             if (!flag) continue;
 #pragma unroll
             for (int d = 0; d < D; ++d) xs[d] = xo[r][d];
-            const uint8_t fb = fallback_flag<D>(a, xs);
+            const uint8_t fb = (uint8_t)fbo[r];
             flag[sr] = fb;
             if (!step_on) continue;
             // a surrogate step: outputs (the fallback overwrites its walkers'
