@@ -408,8 +408,10 @@ sx_status sx_get_tuning(const sx_ctx *ctx, int32_t *tile_hills, int32_t *grid);
  * CV values of the last step are used.  Nothing is deposited and no force
  * is written.  cache_path (may be NULL): a JSON file of earlier choices
  * keyed by the problem shape; read first, updated after a search.  Each
- * candidate runs as a captured graph of 20 launches of the step's two
- * kernels, timed with hipEvents (best of three replays); synchronous. */
+ * candidate runs as a captured graph of 20 launches of the step's hill
+ * kernels (the tile kernel and the finalize, or the one kernel of a step
+ * whose hills are one tile), timed with hipEvents (best of three replays);
+ * synchronous. */
 sx_status sx_autotune(sx_ctx *ctx, const void *pos, int32_t dtype, int32_t layout, const char *cache_path);
 
 /* ------------------------------------------------- bias surrogate */
